@@ -195,31 +195,34 @@ double orc_trace_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *id
   return t;
 }
 
-/* e_i = sum over the sorted union of the two patterns of (y - x)^2, ascending j. */
+/* Row term e_i: the squared differences d*d (each rounded once), taken over the
+ * sorted union of the two stored patterns in ascending j, summed with the same
+ * pairwise tree as every other sum; eta^2 = pairwise tree of the e_i. */
 double orc_norm2_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *idxX, const double *valX,
                      int32_t M2, const int32_t *nnz2, const int32_t *idx2, const double *val2, double *e)
 {
   double *row = (double *)malloc((size_t)N * sizeof(double));
-  if (!row) return NAN;
+  double *q = (double *)malloc((size_t)(MX + M2 + 1) * sizeof(double));
+  if (!row || !q) { free(row); free(q); return NAN; }
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const double *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
-    int32_t p = 0, q = 0;
-    double acc = 0.0;
-    while (p < nnzX[i] || q < nnz2[i]) {
+    int32_t p = 0, r = 0, n = 0;
+    while (p < nnzX[i] || r < nnz2[i]) {
       int32_t jx = p < nnzX[i] ? cx[p] : N;
-      int32_t jy = q < nnz2[i] ? cy[q] : N;
+      int32_t jy = r < nnz2[i] ? cy[r] : N;
       double x = 0.0, y = 0.0;
       if (jx <= jy) x = vx[p++];
-      if (jy <= jx) y = vy[q++];
+      if (jy <= jx) y = vy[r++];
       double d = y - x;
-      acc = fma(d, d, acc);
+      q[n++] = d * d;
     }
-    row[i] = acc;
+    row[i] = orc_pairwise(n, q);
   }
   if (e) memcpy(e, row, (size_t)N * sizeof(double));
   double s = orc_pairwise(N, row);
   free(row);
+  free(q);
   return s;
 }
 
@@ -227,26 +230,27 @@ double orc_norm2_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *
                      int32_t M2, const int32_t *nnz2, const int32_t *idx2, const float *val2, double *e)
 {
   double *row = (double *)malloc((size_t)N * sizeof(double));
-  if (!row) return NAN;
+  double *q = (double *)malloc((size_t)(MX + M2 + 1) * sizeof(double));
+  if (!row || !q) { free(row); free(q); return NAN; }
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const float *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
-    int32_t p = 0, q = 0;
-    double acc = 0.0;
-    while (p < nnzX[i] || q < nnz2[i]) {
+    int32_t p = 0, r = 0, n = 0;
+    while (p < nnzX[i] || r < nnz2[i]) {
       int32_t jx = p < nnzX[i] ? cx[p] : N;
-      int32_t jy = q < nnz2[i] ? cy[q] : N;
+      int32_t jy = r < nnz2[i] ? cy[r] : N;
       double x = 0.0, y = 0.0;
       if (jx <= jy) x = (double)vx[p++];
-      if (jy <= jx) y = (double)vy[q++];
+      if (jy <= jx) y = (double)vy[r++];
       double d = y - x;
-      acc = fma(d, d, acc);
+      q[n++] = d * d;
     }
-    row[i] = acc;
+    row[i] = orc_pairwise(n, q);
   }
   if (e) memcpy(e, row, (size_t)N * sizeof(double));
   double s = orc_pairwise(N, row);
   free(row);
+  free(q);
   return s;
 }
 
@@ -706,22 +710,22 @@ void orc_dense_x2_bf16x3(int32_t N, const float *A, float *C)
   free(hi); free(lo);
 }
 
-/* dense traces/norm: diagonal pairwise; e_i ascending j with fma, rows pairwise */
+/* dense traces: diagonal by pairwise tree */
 static double dense_trace(int32_t N, const double *A, double *scratch)
 {
   for (int32_t i = 0; i < N; ++i) scratch[i] = A[(int64_t)i * N + i];
   return orc_pairwise(N, scratch);
 }
 
-static double dense_norm2(int32_t N, const double *X, const double *Y, double *scratch)
+/* dense norm: every entry of the row is in the pattern; same trees as the sparse norm */
+static double dense_norm2(int32_t N, const double *X, const double *Y, double *scratch, double *q)
 {
   for (int32_t i = 0; i < N; ++i) {
-    double acc = 0.0;
     for (int32_t j = 0; j < N; ++j) {
       double d = Y[(int64_t)i * N + j] - X[(int64_t)i * N + j];
-      acc = fma(d, d, acc);
+      q[j] = d * d;
     }
-    scratch[i] = acc;
+    scratch[i] = orc_pairwise(N, q);
   }
   return orc_pairwise(N, scratch);
 }
@@ -753,9 +757,10 @@ int orc_dense_sp2(int32_t N, const double *H, int32_t mode, const orc_sp2_params
   float *Xf = (float *)malloc((size_t)nn * sizeof(float));
   float *Yf = (float *)malloc((size_t)nn * sizeof(float));
   double *scr = (double *)malloc((size_t)N * sizeof(double));
+  double *qrow = (double *)malloc((size_t)N * sizeof(double));
   double *hist = (double *)malloc((size_t)p->max_iter * sizeof(double));
   int rc = ORC_OK;
-  if (!X || !Y || !Xf || !Yf || !scr || !hist) { rc = ORC_ENOMEM; goto done; }
+  if (!X || !Y || !Xf || !Yf || !scr || !qrow || !hist) { rc = ORC_ENOMEM; goto done; }
   for (int32_t i = 0; i < N; ++i)
     for (int32_t j = 0; j < N; ++j) {
       double h = H[(int64_t)i * N + j];
@@ -779,7 +784,7 @@ int orc_dense_sp2(int32_t N, const double *H, int32_t mode, const orc_sp2_params
     }
     trx = dense_trace(N, X, scr);
     double trx2 = dense_trace(N, Y, scr);
-    eta2 = dense_norm2(N, X, Y, scr);
+    eta2 = dense_norm2(N, X, Y, scr, qrow);
     hist[n] = eta2;
     if (r->hist_trx) r->hist_trx[n] = trx;
     if (r->hist_trx2) r->hist_trx2[n] = trx2;
@@ -824,6 +829,6 @@ int orc_dense_sp2(int32_t N, const double *H, int32_t mode, const orc_sp2_params
   rc = final_status;
 done:
   r->status = rc;
-  free(X); free(Y); free(Xf); free(Yf); free(scr); free(hist);
+  free(X); free(Y); free(Xf); free(Yf); free(scr); free(qrow); free(hist);
   return rc;
 }

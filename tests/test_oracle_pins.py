@@ -470,3 +470,18 @@ def test_dense_sp2_against_projector(mode):
     assert rep["eta"] < 1e-9
     if mode == oracle.DENSE_BF16X3:
         assert rep["fp32_iterations"] > 0 and rep["prec"][-1] == 0
+
+
+def test_norm_row_term_is_a_pairwise_tree():
+    # union entries d = [1, 0, 3*2^-28, 3*2^-28] -> squares [1, 0, 9*2^-56, 9*2^-56].
+    # A running sum gives 1 + 2^-51; the pairwise tree (1 + 0) + (9*2^-56 + 9*2^-56)
+    # = 1 + 1.125*2^-52 rounds to 1 + 2^-52.
+    s = 3 * 2.0 ** -28
+    Y = oracle.Ell(4, 4, [4, 0, 0, 0], [0, 1, 2, 3] + [-1] * 12, [1.0, 0.5, s, s] + [0.0] * 12)
+    X = oracle.Ell(4, 1, [1, 0, 0, 0], [1, -1, -1, -1], [0.5, 0, 0, 0])
+    eta2, e = oracle.norm2(X, Y)
+    assert e[0] == 1.0 + 2.0 ** -52
+    run = 0.0
+    for d in (1.0, 0.0, s, s):
+        run = run + d * d
+    assert run == 1.0 + 2.0 ** -51
