@@ -1,0 +1,806 @@
+// Host runtime and C ABI of libellsp2 (see include/ellsp2.h).
+//
+// Handles own (or borrow) row-major ELLPACK device buffers.  Every argument
+// check runs on the host before the first HIP call, so malformed arguments
+// are reported without a GPU.  sp2_solve keeps the whole purification loop on
+// the device: the per-iteration decision (trace branch, stop, stall, overflow,
+// precision switch) is taken by a one-thread kernel that writes a device
+// control block, every kernel of the loop returns at once when that block
+// says "stop", and the host reads the block only every poll_every iterations.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ellsp2.h"
+#include "ell_internal.h"
+
+using namespace ellsp2;
+
+struct ellpack {
+  int32_t N = 0, M = 0;
+  ell_prec_t prec = ELL_F64;
+  bool owned = false;
+  bool validated = false;
+  int32_t *nnz = nullptr;
+  int32_t *idx = nullptr;
+  void *val = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int device_error(hipError_t e, const char *what)
+{
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? ELL_ENOMEM : ELL_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                          \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return device_error(e_, #expr);      \
+  } while (0)
+
+size_t val_size(ell_prec_t p) { return p == ELL_F64 ? sizeof(double) : sizeof(float); }
+
+int32_t roundup32(int64_t x) { return (int32_t)((x + 31) / 32 * 32); }
+
+// Device allocation released on scope exit.
+struct DevMem {
+  void *p = nullptr;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  ~DevMem() { release(); }
+  void release()
+  {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+  hipError_t alloc(size_t bytes)
+  {
+    release();
+    return hipMalloc(&p, bytes ? bytes : 1);
+  }
+  template <typename T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+int have_device()
+{
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    g_last_error = "no HIP device available";
+    return ELL_ENODEV;
+  }
+  return ELL_OK;
+}
+
+template <typename T>
+EllView<T> view(const ellpack *A)
+{
+  return EllView<T>{A->nnz, A->idx, static_cast<T *>(A->val), A->M};
+}
+
+template <typename T>
+int validate_on_device(const ellpack *A_)
+{
+  ellpack *A = const_cast<ellpack *>(A_);
+  if (A->validated) return ELL_OK;
+  DevMem flags;
+  HIP_TRY(flags.alloc(sizeof(int32_t)));
+  HIP_TRY(hipMemsetAsync(flags.p, 0, sizeof(int32_t), A->stream));
+  HIP_TRY(launch_validate<T>(A->N, view<T>(A), flags.as<int32_t>(), A->stream));
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flags.p, sizeof(h), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  if (h & 1) return ELL_EINVAL;
+  if (h & 2) return ELL_ENONFINITE;
+  A->validated = true;
+  return ELL_OK;
+}
+
+int ensure_valid(const ellpack *A)
+{
+  return A->prec == ELL_F64 ? validate_on_device<double>(A) : validate_on_device<float>(A);
+}
+
+// Scratch of one fused step for N rows.
+struct StepMem {
+  DevMem d1, d2, e, wy, wu, part, partw, partn, out, outw, outn;
+  StepScratch s{};
+  hipError_t alloc(int N)
+  {
+    const int nb = (N + kRedBlock - 1) / kRedBlock;
+    hipError_t err;
+    if ((err = d1.alloc(sizeof(double) * N)) || (err = d2.alloc(sizeof(double) * N)) ||
+        (err = e.alloc(sizeof(double) * N)) || (err = wy.alloc(sizeof(int32_t) * N)) ||
+        (err = wu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nb)) ||
+        (err = partw.alloc(sizeof(int32_t) * 2 * nb)) || (err = partn.alloc(sizeof(int64_t) * 2 * nb)) ||
+        (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 2)) ||
+        (err = outn.alloc(sizeof(int64_t) * 2)))
+      return err;
+    s.d1 = d1.as<double>();
+    s.d2 = d2.as<double>();
+    s.e = e.as<double>();
+    s.wy = wy.as<int32_t>();
+    s.wu = wu.as<int32_t>();
+    s.part = part.as<double>();
+    s.partw = partw.as<int32_t>();
+    s.partn = partn.as<int64_t>();
+    s.out = out.as<double>();
+    s.outw = outw.as<int32_t>();
+    s.outn = outn.as<int64_t>();
+    s.nb = nb;
+    return hipSuccess;
+  }
+};
+
+bool bad_tau(double tau) { return !(tau >= 0.0); }  // rejects NaN and negatives
+
+template <typename T>
+int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
+{
+  const int N = X->N;
+  StepMem m;
+  HIP_TRY(m.alloc(N));
+  Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
+  HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, m.s, X->stream));
+  HIP_TRY(launch_reduce(N, nullptr, m.s, X->stream, X->nnz, Y->nnz, nullptr));
+  HIP_TRY(launch_final_only(m.s, X->stream));
+  double h[3];
+  int32_t w[2];
+  HIP_TRY(hipMemcpyAsync(h, m.s.out, sizeof(h), hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipMemcpyAsync(w, m.s.outw, sizeof(w), hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (out) {
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+  }
+  if (widths) {
+    widths[0] = w[0];
+    widths[1] = U ? w[1] : 0;
+  }
+  const bool over = w[0] > Y->M || (U && w[1] > U->M);
+  if (over) return ELL_EOVERFLOW;
+  Y->validated = true;
+  if (U) U->validated = true;
+  return ELL_OK;
+}
+
+int check_step_args(const ellpack *X, const ellpack *Y, const ellpack *U, double tau)
+{
+  if (!X || !Y) return ELL_EINVAL;
+  if (X == Y || (U && (U == X || U == Y))) return ELL_EINVAL;
+  if (X->N != Y->N || X->prec != Y->prec) return ELL_EINVAL;
+  if (U && (U->N != X->N || U->prec != X->prec)) return ELL_EINVAL;
+  if (X->val == Y->val || (U && (U->val == X->val || U->val == Y->val))) return ELL_EINVAL;
+  if (bad_tau(tau)) return ELL_EINVAL;
+  return ELL_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// handles
+// ===========================================================================
+extern "C" int ellpack_check_host(int32_t N, int32_t M, const int32_t *nnz, const int32_t *index,
+                                  const double *value)
+{
+  if (N <= 0 || N > kMaxN || M <= 0 || M > kMaxCap || !nnz || !index) return ELL_EINVAL;
+  for (int32_t i = 0; i < N; ++i) {
+    if (nnz[i] < 0 || nnz[i] > M) return ELL_EINVAL;
+    const int32_t *c = index + (int64_t)i * M;
+    for (int32_t q = 0; q < nnz[i]; ++q) {
+      if (c[q] < 0 || c[q] >= N) return ELL_EINVAL;
+      if (q > 0 && c[q] <= c[q - 1]) return ELL_EINVAL;
+    }
+  }
+  if (value)
+    for (int32_t i = 0; i < N; ++i)
+      for (int32_t q = 0; q < nnz[i]; ++q)
+        if (!std::isfinite(value[(int64_t)i * M + q])) return ELL_ENONFINITE;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_alloc(ellpack_t **A, int32_t N, int32_t M, ell_prec_t prec, void *hip_stream)
+{
+  if (!A || N <= 0 || N > kMaxN || M <= 0 || M > kMaxCap || (prec != ELL_F64 && prec != ELL_F32))
+    return ELL_EINVAL;
+  *A = nullptr;
+  int rc = have_device();
+  if (rc) return rc;
+  ellpack *h = new (std::nothrow) ellpack;
+  if (!h) return ELL_ENOMEM;
+  h->N = N;
+  h->M = M;
+  h->prec = prec;
+  h->owned = true;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t slots = (size_t)N * M;
+  hipError_t e = hipMalloc(&h->nnz, sizeof(int32_t) * N);
+  if (e == hipSuccess) e = hipMalloc(&h->idx, sizeof(int32_t) * slots);
+  if (e == hipSuccess) e = hipMalloc(&h->val, val_size(prec) * slots);
+  if (e == hipSuccess) e = hipMemsetAsync(h->nnz, 0, sizeof(int32_t) * N, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    int r = device_error(e, "ellpack_alloc");
+    ellpack_free(h);
+    return r;
+  }
+  h->validated = true;
+  *A = h;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_wrap(ellpack_t **A, int32_t N, int32_t M, ell_prec_t prec, int32_t *d_nnz,
+                            int32_t *d_index, void *d_value, void *hip_stream)
+{
+  if (!A || N <= 0 || N > kMaxN || M <= 0 || M > kMaxCap || !d_nnz || !d_index || !d_value) return ELL_EINVAL;
+  if (prec != ELL_F64 && prec != ELL_F32) return ELL_EINVAL;
+  *A = nullptr;
+  ellpack *h = new (std::nothrow) ellpack;
+  if (!h) return ELL_ENOMEM;
+  h->N = N;
+  h->M = M;
+  h->prec = prec;
+  h->owned = false;
+  h->validated = false;
+  h->nnz = d_nnz;
+  h->idx = d_index;
+  h->val = d_value;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  *A = h;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_free(ellpack_t *A)
+{
+  if (!A) return ELL_OK;
+  if (A->owned) {
+    if (A->nnz) (void)hipFree(A->nnz);
+    if (A->idx) (void)hipFree(A->idx);
+    if (A->val) (void)hipFree(A->val);
+  }
+  delete A;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_info(const ellpack_t *A, int32_t *N, int32_t *M, int32_t *prec)
+{
+  if (!A) return ELL_EINVAL;
+  if (N) *N = A->N;
+  if (M) *M = A->M;
+  if (prec) *prec = (int32_t)A->prec;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_upload(ellpack_t *A, const int32_t *nnz, const int32_t *index, const double *value)
+{
+  if (!A || !value) return ELL_EINVAL;
+  int rc = ellpack_check_host(A->N, A->M, nnz, index, value);
+  if (rc) return rc;
+  const size_t slots = (size_t)A->N * A->M;
+  HIP_TRY(hipMemcpyAsync(A->nnz, nnz, sizeof(int32_t) * A->N, hipMemcpyHostToDevice, A->stream));
+  HIP_TRY(hipMemcpyAsync(A->idx, index, sizeof(int32_t) * slots, hipMemcpyHostToDevice, A->stream));
+  if (A->prec == ELL_F64) {
+    HIP_TRY(hipMemcpyAsync(A->val, value, sizeof(double) * slots, hipMemcpyHostToDevice, A->stream));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+  } else {
+    std::vector<float> f(slots);
+    for (size_t q = 0; q < slots; ++q) f[q] = (float)value[q];
+    HIP_TRY(hipMemcpyAsync(A->val, f.data(), sizeof(float) * slots, hipMemcpyHostToDevice, A->stream));
+    HIP_TRY(hipStreamSynchronize(A->stream));
+  }
+  A->validated = true;
+  return ELL_OK;
+}
+
+extern "C" int ellpack_download(const ellpack_t *A, int32_t *nnz, int32_t *index, double *value)
+{
+  if (!A || !nnz || !index || !value) return ELL_EINVAL;
+  const size_t slots = (size_t)A->N * A->M;
+  HIP_TRY(hipMemcpyAsync(nnz, A->nnz, sizeof(int32_t) * A->N, hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipMemcpyAsync(index, A->idx, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, A->stream));
+  std::vector<float> f;
+  if (A->prec == ELL_F64) {
+    HIP_TRY(hipMemcpyAsync(value, A->val, sizeof(double) * slots, hipMemcpyDeviceToHost, A->stream));
+  } else {
+    f.resize(slots);
+    HIP_TRY(hipMemcpyAsync(f.data(), A->val, sizeof(float) * slots, hipMemcpyDeviceToHost, A->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  for (int32_t i = 0; i < A->N; ++i) {
+    const int32_t n = std::min(std::max(nnz[i], 0), A->M);
+    for (int32_t q = 0; q < A->M; ++q) {
+      const size_t at = (size_t)i * A->M + q;
+      if (q >= n) {
+        index[at] = -1;
+        value[at] = 0.0;
+      } else if (A->prec == ELL_F32) {
+        value[at] = (double)f[at];
+      }
+    }
+  }
+  return ELL_OK;
+}
+
+// ===========================================================================
+// single operations
+// ===========================================================================
+extern "C" int ellpack_x2_step(const ellpack_t *X, ellpack_t *X2, ellpack_t *U, double tau, double out[3],
+                               int32_t widths[2])
+{
+  int rc = check_step_args(X, X2, U, tau);
+  if (rc) return rc;
+  rc = ensure_valid(X);
+  if (rc) return rc;
+  return X->prec == ELL_F64 ? run_step<double>(X, X2, U, tau, out, widths)
+                            : run_step<float>(X, X2, U, tau, out, widths);
+}
+
+extern "C" int ellpack_x2_threshold(const ellpack_t *X, ellpack_t *X2, double tau, double trace_out[2],
+                                    int32_t *max_row_width_out)
+{
+  double out[3];
+  int32_t w[2] = {0, 0};
+  int rc = ellpack_x2_step(X, X2, nullptr, tau, out, w);
+  if (rc == ELL_OK || rc == ELL_EOVERFLOW) {
+    if (trace_out) {
+      trace_out[0] = out[0];
+      trace_out[1] = out[1];
+    }
+    if (max_row_width_out) *max_row_width_out = w[0];
+  }
+  return rc;
+}
+
+extern "C" int ellpack_trace(const ellpack_t *A, double *trace_out)
+{
+  if (!A || !trace_out) return ELL_EINVAL;
+  int rc = ensure_valid(A);
+  if (rc) return rc;
+  DevMem d, part, out;
+  HIP_TRY(d.alloc(sizeof(double) * A->N));
+  HIP_TRY(part.alloc(sizeof(double) * ((A->N + kRedBlock - 1) / kRedBlock)));
+  HIP_TRY(out.alloc(sizeof(double)));
+  if (A->prec == ELL_F64)
+    HIP_TRY(launch_trace_rows<double>(A->N, view<double>(A), d.as<double>(), A->stream));
+  else
+    HIP_TRY(launch_trace_rows<float>(A->N, view<float>(A), d.as<double>(), A->stream));
+  HIP_TRY(launch_tree_sum(A->N, d.as<double>(), part.as<double>(), out.as<double>(), A->stream));
+  HIP_TRY(hipMemcpyAsync(trace_out, out.p, sizeof(double), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return ELL_OK;
+}
+
+// ===========================================================================
+// SP2
+// ===========================================================================
+namespace {
+
+// Three working matrices of one precision with capacity cap.
+template <typename T>
+struct WorkSet {
+  DevMem nnz[3], idx[3], val[3];
+  int32_t cap = 0;
+  hipError_t alloc(int N, int32_t c)
+  {
+    cap = c;
+    for (int b = 0; b < 3; ++b) {
+      hipError_t e;
+      if ((e = nnz[b].alloc(sizeof(int32_t) * N)) || (e = idx[b].alloc(sizeof(int32_t) * (size_t)N * c)) ||
+          (e = val[b].alloc(sizeof(T) * (size_t)N * c)))
+        return e;
+    }
+    return hipSuccess;
+  }
+  void release()
+  {
+    for (int b = 0; b < 3; ++b) {
+      nnz[b].release();
+      idx[b].release();
+      val[b].release();
+    }
+    cap = 0;
+  }
+  EllView<T> v(int b) const { return EllView<T>{nnz[b].as<int32_t>(), idx[b].as<int32_t>(), val[b].as<T>(), cap}; }
+  Rot3<T> rot() const { return Rot3<T>{{v(0), v(1), v(2)}}; }
+};
+
+struct Solver {
+  int N = 0;
+  hipStream_t stream = nullptr;
+  StepMem step;
+  DevMem state, hist_trx, hist_trx2, hist_eta2, hist_up, hist_prec, hist_maxw, hist_nnzx, hist_nnzy;
+  DevMem glo, ghi, gout, flags, wmax;
+  SP2State *host_state = nullptr;
+  std::vector<hipEvent_t> events;
+  ~Solver()
+  {
+    if (host_state) (void)hipHostFree(host_state);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+  SP2Hist hist() const
+  {
+    return SP2Hist{hist_trx.as<double>(),  hist_trx2.as<double>(), hist_eta2.as<double>(),
+                   hist_up.as<int8_t>(),   hist_prec.as<int8_t>(), hist_maxw.as<int32_t>(),
+                   hist_nnzx.as<int64_t>(), hist_nnzy.as<int64_t>()};
+  }
+};
+
+template <typename T>
+hipError_t enqueue_step(Solver &S, const WorkSet<T> &W, T tau, const SP2Cfg &cfg)
+{
+  hipError_t e;
+  const Rot3<T> r = W.rot();
+  if ((e = launch_x2_step<T>(S.N, r, S.state.as<SP2State>(), true, tau, S.step.s, S.stream))) return e;
+  if ((e = launch_reduce(S.N, S.state.as<SP2State>(), S.step.s, S.stream, r.b[0].nnz, r.b[1].nnz, r.b[2].nnz)))
+    return e;
+  return launch_decide(S.state.as<SP2State>(), cfg, S.hist(), S.step.s, S.stream);
+}
+
+// Launch `count` iterations; with profiling, bracket every step kernel with events.
+template <typename T>
+int run_batch(Solver &S, const WorkSet<T> &W, T tau, const SP2Cfg &cfg, int count, bool profile,
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> &marks)
+{
+  for (int q = 0; q < count; ++q) {
+    if (profile) {
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a));
+      S.events.push_back(a);
+      HIP_TRY(hipEventCreate(&b));
+      S.events.push_back(b);
+      HIP_TRY(hipEventRecord(a, S.stream));
+      HIP_TRY(launch_x2_step<T>(S.N, W.rot(), S.state.as<SP2State>(), true, tau, S.step.s, S.stream));
+      HIP_TRY(hipEventRecord(b, S.stream));
+      const Rot3<T> r = W.rot();
+      HIP_TRY(launch_reduce(S.N, S.state.as<SP2State>(), S.step.s, S.stream, r.b[0].nnz, r.b[1].nnz,
+                            r.b[2].nnz));
+      HIP_TRY(launch_decide(S.state.as<SP2State>(), cfg, S.hist(), S.step.s, S.stream));
+      marks.emplace_back(a, b);
+    } else {
+      HIP_TRY(enqueue_step<T>(S, W, tau, cfg));
+    }
+  }
+  return ELL_OK;
+}
+
+template <typename T>
+int grow_set(Solver &S, WorkSet<T> &W, int32_t need)
+{
+  const int32_t newcap = roundup32(need);
+  if (newcap > kMaxCap) return ELL_EOVERFLOW;
+  WorkSet<T> G;
+  HIP_TRY(G.alloc(S.N, newcap));
+  const int cur = S.host_state->cur;
+  HIP_TRY((launch_copy<T, T>(S.N, W.v(cur), G.v(0), S.stream)));
+  HIP_TRY(hipStreamSynchronize(S.stream));
+  W.release();
+  for (int b = 0; b < 3; ++b) {
+    std::swap(W.nnz[b].p, G.nnz[b].p);
+    std::swap(W.idx[b].p, G.idx[b].p);
+    std::swap(W.val[b].p, G.val[b].p);
+  }
+  W.cap = newcap;
+  return ELL_OK;
+}
+
+int check_params(const sp2_params_t *p)
+{
+  if (!p) return ELL_EINVAL;
+  if (bad_tau(p->tau) || !(p->idem_target >= 0.0) || !std::isfinite(p->idem_target)) return ELL_EINVAL;
+  if (p->max_iter < 1 || p->fp64_tail_steps < 0 || p->poll_every < 0) return ELL_EINVAL;
+  if (p->precision != SP2_F64 && p->precision != SP2_MIXED) return ELL_EINVAL;
+  if (p->precision == SP2_MIXED && (bad_tau(p->tau_fp32) || !(p->switch_eta >= 0.0))) return ELL_EINVAL;
+  if (!std::isfinite(p->n_occ)) return ELL_EINVAL;
+  return ELL_OK;
+}
+
+// Copy the final X (buffer cur of W) into D, reallocating an owned D if needed.
+template <typename T>
+int deliver(Solver &S, const WorkSet<T> &W, int cur, ellpack *D, int32_t *final_width)
+{
+  DevMem wm;
+  HIP_TRY(wm.alloc(sizeof(int32_t)));
+  // widest stored row of X: the copy kernel clamps, so measure first
+  std::vector<int32_t> hn(S.N);
+  HIP_TRY(hipMemcpyAsync(hn.data(), W.nnz[cur].p, sizeof(int32_t) * S.N, hipMemcpyDeviceToHost, S.stream));
+  HIP_TRY(hipStreamSynchronize(S.stream));
+  int32_t width = 0;
+  for (int32_t v : hn) width = std::max(width, v);
+  *final_width = width;
+  if (width > D->M) {
+    if (!D->owned) return ELL_EOVERFLOW;
+    const int32_t M = std::max(roundup32(width), 32);
+    int32_t *idx = nullptr;
+    double *val = nullptr;
+    HIP_TRY(hipMalloc(&idx, sizeof(int32_t) * (size_t)D->N * M));
+    hipError_t e = hipMalloc(&val, sizeof(double) * (size_t)D->N * M);
+    if (e != hipSuccess) {
+      (void)hipFree(idx);
+      return device_error(e, "deliver");
+    }
+    (void)hipFree(D->idx);
+    (void)hipFree(D->val);
+    D->idx = idx;
+    D->val = val;
+    D->M = M;
+  }
+  HIP_TRY((launch_copy<T, double>(S.N, W.v(cur), view<double>(D), S.stream)));
+  HIP_TRY(hipStreamSynchronize(S.stream));
+  D->validated = true;
+  return ELL_OK;
+}
+
+}  // namespace
+
+extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p, sp2_report_t *r)
+{
+  if (!H || !D || H == D || H->prec != ELL_F64 || D->prec != ELL_F64 || H->N != D->N) return ELL_EINVAL;
+  if (H->val == D->val) return ELL_EINVAL;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (r) {
+    r->status = 0;
+    r->iterations = r->fp32_iterations = r->final_M = 0;
+    r->eta = r->trace_x = r->emin = r->emax = r->seconds = 0.0;
+    r->x2_seconds = 0.0;
+    r->x2_bytes = 0;
+    r->x2_launches = 0;
+  }
+  rc = ensure_valid(H);
+  if (rc) return rc;
+
+  const int N = H->N;
+  const bool mixed = p->precision == SP2_MIXED;
+  const int poll = p->poll_every > 0 ? p->poll_every : 4;
+  Solver S;
+  S.N = N;
+  S.stream = D->stream;
+  hipStream_t st = S.stream;
+  HIP_TRY(S.step.alloc(N));
+  HIP_TRY(S.state.alloc(sizeof(SP2State)));
+  const size_t mi = (size_t)p->max_iter;
+  HIP_TRY(S.hist_trx.alloc(sizeof(double) * mi));
+  HIP_TRY(S.hist_trx2.alloc(sizeof(double) * mi));
+  HIP_TRY(S.hist_eta2.alloc(sizeof(double) * mi));
+  HIP_TRY(S.hist_up.alloc(mi));
+  HIP_TRY(S.hist_prec.alloc(mi));
+  HIP_TRY(S.hist_maxw.alloc(sizeof(int32_t) * mi));
+  HIP_TRY(S.hist_nnzx.alloc(sizeof(int64_t) * mi));
+  HIP_TRY(S.hist_nnzy.alloc(sizeof(int64_t) * mi));
+  const int gb = (N + 255) / 256;
+  HIP_TRY(S.glo.alloc(sizeof(double) * gb));
+  HIP_TRY(S.ghi.alloc(sizeof(double) * gb));
+  HIP_TRY(S.gout.alloc(sizeof(double) * 2));
+  HIP_TRY(S.flags.alloc(sizeof(int32_t)));
+  HIP_TRY(S.wmax.alloc(sizeof(int32_t)));
+  HIP_TRY(hipHostMalloc((void **)&S.host_state, sizeof(SP2State), hipHostMallocDefault));
+
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  S.events.push_back(t0);
+  HIP_TRY(hipEventCreate(&t1));
+  S.events.push_back(t1);
+  HIP_TRY(hipEventRecord(t0, st));
+
+  // Init: Gershgorin bounds (one synchronisation: degenerate spectra are an error)
+  HIP_TRY(hipMemsetAsync(S.flags.p, 0, sizeof(int32_t), st));
+  HIP_TRY(launch_gershgorin(N, view<double>(H), S.glo.as<double>(), S.ghi.as<double>(), S.gout.as<double>(),
+                            S.flags.as<int32_t>(), st));
+  double ee[2];
+  int32_t fl = 0;
+  HIP_TRY(hipMemcpyAsync(ee, S.gout.p, sizeof(ee), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&fl, S.flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (fl & 2) return ELL_ENONFINITE;
+  const double emin = ee[0], emax = ee[1];
+  if (r) {
+    r->emin = emin;
+    r->emax = emax;
+  }
+  if (!(emax > emin)) return ELL_EDEGENERATE;
+  if (!(p->n_occ > 0.0 && p->n_occ < (double)N)) return ELL_EDEGENERATE;
+  const double inv = 1.0 / (emax - emin);
+
+  // Working capacity: the caller's D capacity as a hint, at least X0's width bound.
+  int32_t cap = roundup32(std::min<int64_t>((int64_t)H->M + 1, N));
+  cap = std::max(cap, std::min(roundup32(D->M), roundup32(N)));
+  cap = std::min(std::max(cap, 32), kMaxCap);
+
+  WorkSet<float> W32;
+  WorkSet<double> W64;
+  // X0 into buffer 0 (grows if a row is wider than the capacity)
+  for (;;) {
+    HIP_TRY(hipMemsetAsync(S.wmax.p, 0, sizeof(int32_t), st));
+    if (mixed) {
+      HIP_TRY(W32.alloc(N, cap));
+      HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), emax, inv, (float)p->tau_fp32, S.wmax.as<int32_t>(),
+                               st));
+    } else {
+      HIP_TRY(W64.alloc(N, cap));
+      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), emax, inv, p->tau, S.wmax.as<int32_t>(), st));
+    }
+    int32_t w0 = 0;
+    HIP_TRY(hipMemcpyAsync(&w0, S.wmax.p, sizeof(w0), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (w0 <= cap) break;
+    cap = roundup32(w0);
+    if (cap > kMaxCap) return ELL_EOVERFLOW;
+  }
+
+  SP2State &hs = *S.host_state;
+  std::memset(&hs, 0, sizeof(hs));
+  hs.cur = 0;
+  hs.status = ST_RUNNING;
+  hs.phase32 = mixed ? 1 : 0;
+  hs.cap = cap;
+  HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+
+  SP2Cfg cfg{};
+  cfg.n_occ = p->n_occ;
+  cfg.target2 = p->idem_target * p->idem_target;
+  cfg.switch2 = p->switch_eta * p->switch_eta;
+  cfg.max_iter = p->max_iter;
+  cfg.tail = p->fp64_tail_steps;
+  cfg.stall = p->stall_stop ? 1 : 0;
+  cfg.mixed = mixed ? 1 : 0;
+
+  const bool profile = p->profile != 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+  std::vector<int> useful;  // per batch: number of step kernels that did work
+  int status = ST_RUNNING;
+  // every batch advances the iteration count, grows the capacity or switches
+  // precision, so this bounds the loop even if the device control misbehaved
+  const int64_t max_batches = (int64_t)p->max_iter + 64;
+  for (int64_t batch = 0;; ++batch) {
+    if (batch > max_batches) {
+      g_last_error = "sp2_solve: device control block did not reach a stop";
+      return ELL_EDEVICE;
+    }
+    const int iter_before = hs.iter;
+    const size_t mark0 = marks.size();
+    if (hs.phase32)
+      rc = run_batch<float>(S, W32, (float)p->tau_fp32, cfg, poll, profile, marks);
+    else
+      rc = run_batch<double>(S, W64, p->tau, cfg, poll, profile, marks);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(&hs, S.state.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (profile) {
+      int worked = hs.iter - iter_before + (hs.stop && hs.status == ELL_EOVERFLOW ? 1 : 0);
+      for (size_t q = mark0; q < marks.size(); ++q)
+        if ((int)(q - mark0) >= worked) marks[q].first = nullptr;  // launched after the stop
+    }
+    if (!hs.stop) continue;
+    if (hs.status == ELL_EOVERFLOW) {
+      rc = hs.phase32 ? grow_set<float>(S, W32, hs.need_width) : grow_set<double>(S, W64, hs.need_width);
+      if (rc) return rc;
+      hs.cur = 0;
+      hs.stop = 0;
+      hs.status = ST_RUNNING;
+      hs.cap = hs.phase32 ? W32.cap : W64.cap;
+      HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+      continue;
+    }
+    if (hs.status == ST_SWITCH) {
+      HIP_TRY(W64.alloc(N, W32.cap));
+      HIP_TRY((launch_copy<float, double>(N, W32.v(hs.cur), W64.v(0), st)));
+      HIP_TRY(hipStreamSynchronize(st));
+      W32.release();
+      hs.cur = 0;
+      hs.phase32 = 0;
+      hs.stop = 0;
+      hs.status = ST_RUNNING;
+      hs.cap = W64.cap;
+      HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+      continue;
+    }
+    status = hs.status;
+    break;
+  }
+  HIP_TRY(hipEventRecord(t1, st));
+
+  int32_t width = 0;
+  rc = hs.phase32 ? deliver<float>(S, W32, hs.cur, D, &width) : deliver<double>(S, W64, hs.cur, D, &width);
+  const int final_status = rc ? rc : status;
+  if (!r) return final_status;
+
+  r->status = final_status;
+  r->iterations = hs.iter;
+  r->final_M = hs.phase32 ? W32.cap : W64.cap;
+  if (rc == ELL_EOVERFLOW) r->final_M = width;
+  r->eta = std::sqrt(hs.eta2);
+  r->trace_x = hs.trx;
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+  r->seconds = ms * 1e-3;
+  const int n = hs.iter;
+  std::vector<double> a(n), b(n), c(n);
+  std::vector<int8_t> up(n), pr(n);
+  std::vector<int32_t> mw(n);
+  std::vector<int64_t> nx(n), ny(n);
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(a.data(), S.hist_trx.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(b.data(), S.hist_trx2.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c.data(), S.hist_eta2.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(up.data(), S.hist_up.p, n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(pr.data(), S.hist_prec.p, n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(mw.data(), S.hist_maxw.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(nx.data(), S.hist_nnzx.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ny.data(), S.hist_nnzy.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  int f32 = 0;
+  for (int q = 0; q < n; ++q) f32 += pr[q] ? 1 : 0;
+  r->fp32_iterations = f32;
+  for (int q = 0; q < n; ++q) {
+    if (r->hist_trx) r->hist_trx[q] = a[q];
+    if (r->hist_trx2) r->hist_trx2[q] = b[q];
+    if (r->hist_eta2) r->hist_eta2[q] = c[q];
+    if (r->hist_up) r->hist_up[q] = up[q];
+    if (r->hist_prec) r->hist_prec[q] = pr[q];
+    if (r->hist_maxw) r->hist_maxw[q] = mw[q];
+  }
+  if (profile) {
+    double sec = 0.0;
+    int launches = 0;
+    for (auto &m : marks) {
+      if (!m.first) continue;
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, m.first, m.second));
+      sec += t * 1e-3;
+      ++launches;
+    }
+    int64_t bytes = 0;
+    for (int q = 0; q < n; ++q) {
+      const int64_t sv = pr[q] ? 4 : 8;
+      bytes += nx[q] * (sv + 4) + 4LL * N + ny[q] * (sv + 4) + 4LL * N;
+    }
+    r->x2_seconds = sec;
+    r->x2_bytes = bytes;
+    r->x2_launches = launches;
+  }
+  return final_status;
+}
+
+extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t *const *D, const sp2_params_t *p,
+                                 sp2_report_t *r)
+{
+  if (n < 0 || (n > 0 && (!H || !D))) return ELL_EINVAL;
+  int rc = check_params(p);
+  if (rc) return rc;
+  int worst = ELL_OK;
+  for (int32_t q = 0; q < n; ++q) {
+    rc = sp2_solve(H[q], D[q], p, r ? &r[q] : nullptr);
+    if (rc != ELL_OK && (worst == ELL_OK || rc < worst)) worst = rc;
+  }
+  return worst;
+}
+
+extern "C" const char *ellpack_strerror(int status)
+{
+  switch (status) {
+    case ELL_OK: return "ok";
+    case ELL_EINVAL: return "invalid argument";
+    case ELL_ENOMEM: return "out of memory";
+    case ELL_EOVERFLOW: return "row width exceeds capacity";
+    case ELL_ENOCONV: return "no convergence";
+    case ELL_EDEVICE: return "device error";
+    case ELL_ENODEV: return "no device";
+    case ELL_ENONFINITE: return "non-finite input";
+    case ELL_EDEGENERATE: return "degenerate input";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char *ellpack_last_device_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,262 @@
+"""GPU (HIP, gfx950) path against the CPU oracle, through the C ABI.
+
+FP64 and FP32 results are compared bit for bit: the GPU kernels add every
+output entry's products in ascending k with fused multiply-adds, and sum
+traces and norms with the same pairwise trees, so there is nothing to
+tolerate.  Patterns (column indices, row widths) must match exactly."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08505_amd import ellsp2 as E
+from paper_2102_08505_amd import synth
+from tests.gpu_helpers import assert_same_rows, dev_from_oracle, oracle_from_dev, same_float
+
+pytestmark = pytest.mark.gpu
+
+
+def random_ell(N, density, seed, symmetric=False, f32=False, full_rows=(), empty_rows=(), M=None):
+    rng = np.random.default_rng(seed)
+    D = rng.uniform(-1, 1, (N, N)) * (rng.random((N, N)) < density)
+    if symmetric:
+        D = np.triu(D) + np.triu(D, 1).T
+    for r in full_rows:
+        D[r, :] = rng.uniform(-1, 1, N)
+    for r in empty_rows:
+        D[r, :] = 0
+    if f32:
+        D = D.astype(np.float32).astype(np.float64)
+    nnz, idx, val, Mx = synth.dense_to_ell(D, M=M)
+    val = val.astype(np.float32) if f32 else val
+    return oracle.Ell(N, Mx, nnz, idx, val)
+
+
+CASES = [
+    # N, density, symmetric, full rows, empty rows
+    (1, 1.0, True, (), ()),
+    (7, 0.5, False, (3,), (0,)),
+    (64, 0.1, True, (), (5, 6)),
+    (257, 0.03, False, (100,), (0, 256)),
+    (1000, 0.004, True, (17,), (3,)),       # a full row: span 1000 > one 512-wide window
+    (1500, 0.002, False, (700, 701), ()),
+]
+
+
+def x2_pair(A, tau, f32, with_u, cap=None):
+    prec = E.ELL_F32 if f32 else E.ELL_F64
+    rc, Y, d1, d2, wy = oracle.x2(A, tau)
+    cap = cap or max(32, wy + 1)
+    X = dev_from_oracle(A, prec)
+    Yd = E.DeviceEll(A.N, cap, prec)
+    U = E.DeviceEll(A.N, cap + A.M, prec) if with_u else None
+    rc_g, out, widths = E.ellpack_x2_step(X.h, Yd.h, U.h if U else None, tau)
+    return rc_g, out, widths, X, Yd, U, (Y, d1, d2, wy)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_x2_step_bitwise(case, f32):
+    N, dens, sym, full, empty = CASES[case]
+    A = random_ell(N, dens, seed=100 + case, symmetric=sym, f32=f32, full_rows=full, empty_rows=empty)
+    tau = np.float32(0.02) if f32 else 0.02
+    rc, out, widths, X, Yd, U, (Y, d1, d2, wy) = x2_pair(A, tau, f32, with_u=True)
+    assert rc == E.ELL_OK, E.ellpack_strerror(rc)
+    assert_same_rows(oracle_from_dev(Yd, f32), Y, "X^2")
+    assert widths[0] == wy
+    assert same_float(out[0], oracle.pairwise(d1))
+    assert same_float(out[1], oracle.pairwise(d2))
+    eta2, _ = oracle.norm2(A, Y)
+    assert same_float(out[2], eta2)
+    rcu, Uo, wu = oracle.update(A, Y, tau)
+    assert_same_rows(oracle_from_dev(U, f32), Uo, "2X - X^2")
+    assert widths[1] == wu
+
+
+def test_x2_threshold_matches_step_and_is_deterministic():
+    A = random_ell(300, 0.05, seed=5, symmetric=True)
+    rc, Y, d1, d2, wy = oracle.x2(A, 1e-3)
+    X = dev_from_oracle(A)
+    outs = []
+    for _ in range(2):
+        Yd = E.DeviceEll(A.N, wy, E.ELL_F64)
+        rc, tr, w = E.ellpack_x2_threshold(X.h, Yd.h, 1e-3)
+        assert rc == E.ELL_OK and w == wy
+        assert same_float(tr[0], oracle.pairwise(d1)) and same_float(tr[1], oracle.pairwise(d2))
+        outs.append(Yd.download())
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0][2:], outs[1][2:]))
+
+
+def test_x2_threshold_edges_strict_on_gpu():
+    tau = 1e-5
+    vals = [tau, np.nextafter(tau, np.inf), np.nextafter(tau, 0), -tau, -np.nextafter(tau, np.inf), 0.5]
+    N = len(vals) + 2
+    D = np.zeros((N, N))
+    D[0, 1] = 1.0
+    D[1, 2:] = vals
+    nnz, idx, val, M = synth.dense_to_ell(D)
+    X = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    Y = E.DeviceEll(N, N, E.ELL_F64)
+    rc, tr, w = E.ellpack_x2_threshold(X.h, Y.h, tau)
+    assert rc == E.ELL_OK
+    R = oracle_from_dev(Y).rows()[0]
+    expect = [2 + q for q, x in enumerate(vals) if abs(x) > tau]
+    assert list(R[0]) == expect
+    assert list(R[1]) == [vals[q - 2] for q in expect]
+
+
+def test_x2_overflow_is_reported_not_truncated():
+    A = random_ell(200, 0.08, seed=9)
+    rc, Y, d1, d2, wy = oracle.x2(A, 0.0)
+    X = dev_from_oracle(A)
+    small = E.DeviceEll(A.N, wy - 1, E.ELL_F64)
+    rc, tr, w = E.ellpack_x2_threshold(X.h, small.h, 0.0)
+    assert rc == E.ELL_EOVERFLOW and w == wy
+    exact = E.DeviceEll(A.N, wy, E.ELL_F64)
+    rc, tr, w = E.ellpack_x2_threshold(X.h, exact.h, 0.0)
+    assert rc == E.ELL_OK
+    assert_same_rows(oracle_from_dev(exact), Y, "X^2 at exact capacity")
+
+
+def test_trace_bitwise():
+    for N in (1, 5, 1023, 1024, 1025, 5000):
+        A = random_ell(N, min(1.0, 3.0 / N), seed=N)
+        X = dev_from_oracle(A)
+        rc, t = E.ellpack_trace(X.h)
+        assert rc == E.ELL_OK and same_float(t, oracle.trace(A))
+
+
+@pytest.mark.parametrize("tau", [1e-5, 0.0])
+def test_x2_banded_full_size_bitwise(tau):
+    """Full-size banded workload (N = 32768, half-bandwidth 64): X0 and X0^2."""
+    N, b = 32768, 64
+    nnz, idx, val, M = synth.banded_hamiltonian(N, b)
+    H = oracle.Ell(N, M, nnz, idx, val)
+    rc, lo, hi = oracle.gershgorin(H)
+    rc, X0, w0 = oracle.x0(H, lo, hi, tau, Mo=M + 1)
+    rc, Y, d1, d2, wy = oracle.x2(X0, tau, M2=512)
+    X = dev_from_oracle(X0)
+    Yd = E.DeviceEll(N, 512, E.ELL_F64)
+    Ud = E.DeviceEll(N, 512, E.ELL_F64)
+    rc, out, widths = E.ellpack_x2_step(X.h, Yd.h, Ud.h, tau)
+    assert rc == E.ELL_OK
+    assert_same_rows(oracle_from_dev(Yd), Y, "X0^2")
+    assert same_float(out[1], oracle.pairwise(d2))
+    eta2, _ = oracle.norm2(X0, Y)
+    assert same_float(out[2], eta2)
+
+
+# ---------------------------------------------------------------------------------- SP2
+def sp2_both(N, b, tau, target, M=32, max_iter=100, mixed=False, seed=0, tau32=1e-7, switch_eta=1e-3):
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=seed)
+    H = oracle.Ell(N, Mh, nnz, idx, val)
+    po = oracle.make_params(N // 4, tau, target, max_iter=max_iter,
+                            precision=oracle.PREC_MIXED if mixed else oracle.PREC_F64,
+                            tau_fp32=tau32, switch_eta=switch_eta)
+    rc_o, Do, rep_o = oracle.sp2(H, po, Mo=N)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    Dd = E.DeviceEll(N, M, E.ELL_F64)
+    pg = E.sp2_params(N // 4, tau, target, max_iter=max_iter, precision=E.SP2_MIXED if mixed else E.SP2_F64,
+                      tau_fp32=tau32, switch_eta=switch_eta)
+    rc_g, rep_g = E.sp2_solve(Hd.h, Dd.h, pg)
+    return (rc_o, Do, rep_o), (rc_g, Dd, rep_g)
+
+
+def assert_same_trajectory(o, g):
+    rc_o, Do, ro = o
+    rc_g, Dd, rg = g
+    assert rc_g == rc_o, (rc_g, rc_o)
+    assert rg["iterations"] == ro["iterations"]
+    assert rg["fp32_iterations"] == ro["fp32_iterations"]
+    for k in ("trx", "trx2", "eta2"):
+        a, b = rg[k], ro[k]
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (k, np.nonzero(a != b)[0][:5])
+    for k in ("up", "maxw", "prec"):
+        assert np.array_equal(rg[k], ro[k]), k
+    assert_same_rows(oracle_from_dev(Dd), Do, "D")
+    assert same_float(rg["emin"], ro["emin"]) and same_float(rg["emax"], ro["emax"])
+
+
+@pytest.mark.parametrize("tau,target", [(1e-5, 1e-8), (1e-9, 1e-8)])
+def test_sp2_trajectory_bitwise_n512(tau, target):
+    """N = 512, half-bandwidth 16, N_occ = 128, capacity 32 to start (it must grow)."""
+    o, g = sp2_both(512, 16, tau, target, M=32)
+    assert_same_trajectory(o, g)
+    assert g[2]["final_M"] > 32
+
+
+def test_sp2_mixed_trajectory_bitwise():
+    o, g = sp2_both(512, 16, 1e-9, 1e-8, M=64, mixed=True, tau32=1e-7, switch_eta=1e-3)
+    assert_same_trajectory(o, g)
+    assert 0 < g[2]["fp32_iterations"] < g[2]["iterations"]
+
+
+def test_sp2_small_and_ragged_sizes():
+    for N, b in [(8, 2), (37, 3), (130, 5)]:
+        o, g = sp2_both(N, b, 0.0, 1e-9, M=32, max_iter=200)
+        assert_same_trajectory(o, g)
+
+
+def test_sp2_deterministic_and_poll_independent():
+    N, b = 400, 8
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=3)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    res = []
+    for poll in (1, 4, 7):
+        Dd = E.DeviceEll(N, 64, E.ELL_F64)
+        rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-8, 1e-7, poll_every=poll))
+        res.append((rc, rep["iterations"], Dd.download()))
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1]
+        assert all(np.array_equal(a, b) for a, b in zip(r[2][2:], res[0][2][2:]))
+
+
+def test_sp2_errors_on_device():
+    N = 16
+    # constant diagonal: emax == emin
+    D = np.eye(N) * 2.0
+    nnz, idx, val, M = synth.dense_to_ell(D)
+    Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    Dd = E.DeviceEll(N, 32, E.ELL_F64)
+    assert E.sp2_solve(Hd.h, Dd.h, E.sp2_params(4, 0.0, 1e-8))[0] == E.ELL_EDEGENERATE
+    nnz, idx, val, M = synth.banded_hamiltonian(N, 2)
+    Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    assert E.sp2_solve(Hd.h, Dd.h, E.sp2_params(0, 0.0, 1e-8))[0] == E.ELL_EDEGENERATE
+    assert E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N, 0.0, 1e-8))[0] == E.ELL_EDEGENERATE
+    rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(4, 0.0, 1e-30, max_iter=3, stall_stop=0))
+    assert rc == E.ELL_ENOCONV and rep["iterations"] == 3
+
+
+def test_wrapped_buffers_validated_on_device():
+    import torch
+    N, M = 16, 4
+    nnz = torch.full((N,), 1, dtype=torch.int32, device="cuda")
+    idx = torch.zeros((N, M), dtype=torch.int32, device="cuda")
+    idx[:, 0] = torch.arange(N, dtype=torch.int32, device="cuda")
+    val = torch.ones((N, M), dtype=torch.float64, device="cuda")
+    val[3, 0] = float("nan")
+    rc, H = E.ellpack_wrap(N, M, E.ELL_F64, nnz.data_ptr(), idx.data_ptr(), val.data_ptr())
+    assert rc == E.ELL_OK
+    Dd = E.DeviceEll(N, 32, E.ELL_F64)
+    assert E.sp2_solve(H, Dd.h, E.sp2_params(4, 0.0, 1e-8))[0] == E.ELL_ENONFINITE
+    E.ellpack_free(H)
+    idx[5, 0] = N  # column out of range
+    val[3, 0] = 1.0
+    rc, H = E.ellpack_wrap(N, M, E.ELL_F64, nnz.data_ptr(), idx.data_ptr(), val.data_ptr())
+    Y = E.DeviceEll(N, 8, E.ELL_F64)
+    assert E.ellpack_x2_threshold(H, Y.h, 0.0)[0] == E.ELL_EINVAL
+    E.ellpack_free(H)
+
+
+def test_wrapped_result_too_narrow_reports_width():
+    import torch
+    N, b = 128, 4
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    M = 8
+    dn = torch.zeros(N, dtype=torch.int32, device="cuda")
+    di = torch.zeros(N * M, dtype=torch.int32, device="cuda")
+    dv = torch.zeros(N * M, dtype=torch.float64, device="cuda")
+    rc, D = E.ellpack_wrap(N, M, E.ELL_F64, dn.data_ptr(), di.data_ptr(), dv.data_ptr())
+    rc, rep = E.sp2_solve(Hd.h, D, E.sp2_params(N // 4, 1e-10, 1e-8))
+    assert rc == E.ELL_EOVERFLOW and rep["final_M"] > M
+    E.ellpack_free(D)
