@@ -195,15 +195,42 @@ double orc_trace_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *id
   return t;
 }
 
-/* Row term e_i: the squared differences d*d (each rounded once), taken over the
- * sorted union of the two stored patterns in ascending j, summed with the same
- * pairwise tree as every other sum; eta^2 = pairwise tree of the e_i. */
+/* Row term e_i: the pairwise tree over the row's N column positions of
+ * q_j = d*d with d = X2_ij - X_ij (absent entries are 0, so q_j = +0 wherever
+ * neither matrix stores column j); eta^2 = pairwise tree of the e_i.  The tree
+ * over N leaves is the perfect tree over the next power of two with +0 leaves
+ * past N (an odd element passing a level unchanged is the same as adding +0).
+ * A subtree whose leaves are all +0 sums to +0 and adding +0 changes nothing,
+ * so only the stored columns need visiting: tree_sum() walks the aligned
+ * subtrees that contain one. */
+static double tree_sum(const int32_t *col, const double *q, int32_t n, int64_t lo, int64_t size)
+{
+  /* entries with lo <= col < lo + size, col ascending */
+  int32_t a = 0, b = n;
+  while (a < b && col[a] < lo) ++a;
+  int32_t e = a;
+  while (e < b && col[e] < lo + size) ++e;
+  if (a == e) return 0.0;
+  if (size == 1) return q[a];
+  const int64_t h = size / 2;
+  return tree_sum(col + a, q + a, e - a, lo, h) + tree_sum(col + a, q + a, e - a, lo + h, h);
+}
+
+static int64_t pow2_at_least(int64_t n)
+{
+  int64_t p = 1;
+  while (p < n) p *= 2;
+  return p;
+}
+
 double orc_norm2_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *idxX, const double *valX,
                      int32_t M2, const int32_t *nnz2, const int32_t *idx2, const double *val2, double *e)
 {
   double *row = (double *)malloc((size_t)N * sizeof(double));
   double *q = (double *)malloc((size_t)(MX + M2 + 1) * sizeof(double));
-  if (!row || !q) { free(row); free(q); return NAN; }
+  int32_t *c = (int32_t *)malloc((size_t)(MX + M2 + 1) * sizeof(int32_t));
+  if (!row || !q || !c) { free(row); free(q); free(c); return NAN; }
+  const int64_t P = pow2_at_least(N);
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const double *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
@@ -212,17 +239,19 @@ double orc_norm2_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *
       int32_t jx = p < nnzX[i] ? cx[p] : N;
       int32_t jy = r < nnz2[i] ? cy[r] : N;
       double x = 0.0, y = 0.0;
+      c[n] = jx < jy ? jx : jy;
       if (jx <= jy) x = vx[p++];
       if (jy <= jx) y = vy[r++];
       double d = y - x;
       q[n++] = d * d;
     }
-    row[i] = orc_pairwise(n, q);
+    row[i] = tree_sum(c, q, n, 0, P);
   }
   if (e) memcpy(e, row, (size_t)N * sizeof(double));
   double s = orc_pairwise(N, row);
   free(row);
   free(q);
+  free(c);
   return s;
 }
 
@@ -231,7 +260,9 @@ double orc_norm2_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *
 {
   double *row = (double *)malloc((size_t)N * sizeof(double));
   double *q = (double *)malloc((size_t)(MX + M2 + 1) * sizeof(double));
-  if (!row || !q) { free(row); free(q); return NAN; }
+  int32_t *c = (int32_t *)malloc((size_t)(MX + M2 + 1) * sizeof(int32_t));
+  if (!row || !q || !c) { free(row); free(q); free(c); return NAN; }
+  const int64_t P = pow2_at_least(N);
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const float *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
@@ -240,17 +271,19 @@ double orc_norm2_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *
       int32_t jx = p < nnzX[i] ? cx[p] : N;
       int32_t jy = r < nnz2[i] ? cy[r] : N;
       double x = 0.0, y = 0.0;
+      c[n] = jx < jy ? jx : jy;
       if (jx <= jy) x = (double)vx[p++];
       if (jy <= jx) y = (double)vy[r++];
       double d = y - x;
       q[n++] = d * d;
     }
-    row[i] = orc_pairwise(n, q);
+    row[i] = tree_sum(c, q, n, 0, P);
   }
   if (e) memcpy(e, row, (size_t)N * sizeof(double));
   double s = orc_pairwise(N, row);
   free(row);
   free(q);
+  free(c);
   return s;
 }
 

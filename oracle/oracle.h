@@ -21,9 +21,9 @@
  *   prune  an entry is kept iff |v| > tau (strict); exact zeros never stored.
  *   traces d1[i] = X_ii (0 if absent), d2[i] = (X.X)_ii before pruning;
  *          a trace is the pairwise tree sum of the vector (orc_pairwise).
- *   norm   eta^2 = ||X2 - X||_F^2 over the union of the stored patterns:
- *          e_i = pairwise tree of the rounded squares d*d in ascending j,
- *          eta^2 = pairwise tree of the e_i.
+ *   norm   eta^2 = ||X2 - X||_F^2: e_i = pairwise tree over the row's N
+ *          column positions of the rounded squares d*d (d = 0 where neither
+ *          matrix stores the column), eta^2 = pairwise tree of the e_i.
  *   X0     Gershgorin bounds; X0 = (emax I - H) / (emax - emin), pruned.
  *   branch up = |2 TrX - TrX2 - n_occ| < |TrX2 - n_occ|  (tie -> X^2);
  *          up: X <- prune(2X - X^2); else X <- X^2.

@@ -473,7 +473,7 @@ def test_dense_sp2_against_projector(mode):
 
 
 def test_norm_row_term_is_a_pairwise_tree():
-    # union entries d = [1, 0, 3*2^-28, 3*2^-28] -> squares [1, 0, 9*2^-56, 9*2^-56].
+    # d = [1, 0, 3*2^-28, 3*2^-28] at columns 0..3 -> squares [1, 0, 9*2^-56, 9*2^-56].
     # A running sum gives 1 + 2^-51; the pairwise tree (1 + 0) + (9*2^-56 + 9*2^-56)
     # = 1 + 1.125*2^-52 rounds to 1 + 2^-52.
     s = 3 * 2.0 ** -28
@@ -485,3 +485,29 @@ def test_norm_row_term_is_a_pairwise_tree():
     for d in (1.0, 0.0, s, s):
         run = run + d * d
     assert run == 1.0 + 2.0 ** -51
+
+
+def test_norm_tree_runs_over_column_positions():
+    # Stored columns 0, 2, 3 of a 4-column row (column 1 empty in both), squares
+    # q = [1, -, 9*2^-56, 9*2^-56].  Over column positions the tree is
+    # (1 + 0) + (q2 + q3) = 1 + 2^-52; a tree over the list of stored entries
+    # would pair (1 + q2) + q3 = 1 + 2^-51.
+    s = 3 * 2.0 ** -28
+    Y = oracle.Ell(4, 4, [3, 0, 0, 0], [0, 2, 3, -1] + [-1] * 12, [1.0, s, s, 0.0] + [0.0] * 12)
+    X = oracle.Ell(4, 1, [0, 0, 0, 0], [-1] * 4, [0.0] * 4)
+    eta2, e = oracle.norm2(X, Y)
+    assert e[0] == 1.0 + 2.0 ** -52
+    listed = (1.0 + s * s) + s * s
+    assert listed == 1.0 + 2.0 ** -51
+    # and the same value as the dense row summed by the pairwise definition
+    assert e[0] == exact.pairwise_recursive([1.0, 0.0, s * s, s * s])
+
+
+def test_norm_equals_pairwise_over_dense_rows():
+    rng = np.random.default_rng(21)
+    for N in (5, 37, 64, 100):
+        Dx, X = random_sparse(N, 0.2, rng)
+        Dy, Y = random_sparse(N, 0.2, rng)
+        eta2, e = oracle.norm2(X, Y)
+        for i in range(N):
+            assert e[i] == exact.pairwise_recursive((Dy[i] - Dx[i]) ** 2), (N, i)
