@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libellsp2.so")
-SOURCES = ["ell_api.hip", "ell_kernels.hip", "dense.hip"]
+SOURCES = ["ell_api.hip", "ell_kernels.hip", "ell_band.hip", "dense.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1,17 +1,650 @@
-// Dense variant of the SP2 step (placeholder until the MFMA kernels land).
-#include <string>
+// Dense-block variant of the SP2 step on the matrix cores (gfx950).
+//
+// With a dense X the square X^2 is a plain dense contraction, so it runs on MFMA:
+//  * BF16x3: X (float) is split once per step into hi = bf16(x) and
+//    lo = bf16(x - hi) (round to nearest even), and X^2 is approximated by
+//    hi.hi + hi.lo + lo.hi with float accumulation on v_mfma_f32_32x32x16_bf16
+//    (the three-product split of Henry, Tang and Heinecke, ARITH 2019);
+//  * FP64: v_mfma_f64_16x16x4_f64.
+// Both GEMMs read their B operand from a transposed copy, so the values a lane
+// feeds to one MFMA are contiguous along k.  After the product, one kernel per
+// row forms 2X - X^2, both diagonals and the row term of the idempotency norm
+// (pairwise tree over the N columns); the reductions and the device-side SP2
+// decision are those of the sparse path (Sec. 2, Alg. 1 of the paper).
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "../../include/ellsp2.h"
+#include "ell_internal.h"
+
+namespace ellsp2 {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kMaxDenseN = 32768;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// lane 0 receives the perfect pairwise tree over the 64 lanes
+__device__ __forceinline__ double wave_tree(double v)
+{
+  for (int s = 1; s < kWave; s <<= 1) v = v + __shfl_down(v, s, kWave);
+  return v;
+}
+
+// Operand selection: a fixed pair (x, y), or, during a solve, X = bufs[cur]
+// and X^2 into bufs[(cur + 1) % 3] with cur read from the device state.
+template <typename T>
+struct DSel {
+  const T *x;
+  T *y;
+  T *const *bufs;
+  const SP2State *st;
+};
+
+template <typename T>
+__device__ __forceinline__ bool resolve(const DSel<T> &s, const T *&x, T *&y)
+{
+  if (!s.st) {
+    x = s.x;
+    y = s.y;
+    return true;
+  }
+  if (s.st->stop) return false;
+  const int c = s.st->cur;
+  x = s.bufs[c];
+  y = s.bufs[c == 2 ? 0 : c + 1];
+  return true;
+}
+
+// round to nearest even; bf16 held as its 16-bit pattern
+__device__ __forceinline__ uint16_t bf16_bits(float x)
+{
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) {
+    if (u & 0x007fffffu) u |= 0x00400000u;
+    return (uint16_t)(u >> 16);
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// hi/lo split of an N x N float matrix, row-major and transposed (32 x 32 tiles through LDS)
+__global__ __launch_bounds__(256) void k_split(int N, DSel<float> sel, uint16_t *hi, uint16_t *lo, uint16_t *hiT,
+                                               uint16_t *loT)
+{
+  __shared__ uint16_t th[32][33], tl[32][33];
+  const float *X;
+  float *unused;
+  if (!resolve(sel, X, unused)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    uint16_t h = 0, l = 0;
+    if (r < N && c < N) {
+      const float x = X[(size_t)r * N + c];
+      h = bf16_bits(x);
+      l = bf16_bits(x - bf16_val(h));
+      hi[(size_t)r * N + c] = h;
+      lo[(size_t)r * N + c] = l;
+    }
+    th[ty + 8 * q][tx] = h;
+    tl[ty + 8 * q][tx] = l;
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int r = c0 + ty + 8 * q, c = r0 + tx;  // position in the transpose
+    if (r < N && c < N) {
+      hiT[(size_t)r * N + c] = th[tx][ty + 8 * q];
+      loT[(size_t)r * N + c] = tl[tx][ty + 8 * q];
+    }
+  }
+}
+
+// transpose of an N x N double matrix
+__global__ __launch_bounds__(256) void k_transpose64(int N, DSel<double> sel, double *AT)
+{
+  __shared__ double t[32][33];
+  const double *A;
+  double *unused;
+  if (!resolve(sel, A, unused)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    t[ty + 8 * q][tx] = (r < N && c < N) ? A[(size_t)r * N + c] : 0.0;
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int r = c0 + ty + 8 * q, c = r0 + tx;
+    if (r < N && c < N) AT[(size_t)r * N + c] = t[tx][ty + 8 * q];
+  }
+}
+
+// ---- BF16x3 GEMM: C = hi.hi + hi.lo + lo.hi, 128 x 128 tile per block ----------------
+// LDS holds 32 k-values per row (A tiles) and per column (B tiles, read from the
+// transposed copies).  Wave (wm, wn) computes rows 64 wm .. +63 and columns
+// 64 wn .. +63 as 2 x 2 MFMA 32 x 32 blocks.  v_mfma_f32_32x32x16_bf16 operand
+// layout: lane l feeds A[l % 32][8 (l / 32) .. +7] and B[8 (l / 32) .. +7][l % 32]
+// and holds C[8 g + 4 (l / 32) + t][l % 32] in accumulator 4 g + t.
+constexpr int kBM = 128, kBK = 32;
+constexpr int kLdsK = kBK + 8;  // padded LDS row: 40 bf16 (80 bytes)
+
+template <bool VEC>
+__device__ __forceinline__ void stage_tile(int N, const uint16_t *__restrict__ src, int row0, int k0,
+                                           uint16_t (*dst)[kLdsK])
+{
+  // 128 rows x 32 k = 512 pieces of 8 values, two per thread
+  for (int p = threadIdx.x; p < kBM * kBK / 8; p += 256) {
+    const int r = p >> 2, kc = (p & 3) * 8;
+    const int gr = row0 + r, gk = k0 + kc;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (VEC && gr < N && gk + 8 <= N) {
+      v = *(const uint4 *)(src + (size_t)gr * N + gk);  // 16-byte aligned: N % 8 == 0, gk % 8 == 0
+    } else if (gr < N) {
+      uint16_t tmp[8];
+      for (int e = 0; e < 8; ++e) tmp[e] = gk + e < N ? src[(size_t)gr * N + gk + e] : 0;
+      memcpy(&v, tmp, 16);
+    }
+    memcpy(&dst[r][kc], &v, 16);
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__restrict__ hi,
+                                                     const uint16_t *__restrict__ lo,
+                                                     const uint16_t *__restrict__ hiT,
+                                                     const uint16_t *__restrict__ loT, DSel<float> sel)
+{
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[kBM][kLdsK], Al[kBM][kLdsK], Bh[kBM][kLdsK], Bl[kBM][kLdsK];
+  const float *unused;
+  float *C;
+  if (!resolve(sel, unused, C)) return;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int row0 = blockIdx.y * kBM, col0 = blockIdx.x * kBM;
+  f32x16 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+  for (int k0 = 0; k0 < N; k0 += kBK) {
+    stage_tile<VEC>(N, hi, row0, k0, Ah);
+    stage_tile<VEC>(N, lo, row0, k0, Al);
+    stage_tile<VEC>(N, hiT, col0, k0, Bh);
+    stage_tile<VEC>(N, loT, col0, k0, Bl);
+    __syncthreads();
+    for (int ks = 0; ks < kBK; ks += 16) {
+      const int kk = ks + 8 * (lane >> 5);
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+      for (int a = 0; a < 2; ++a) {
+        const int r = wm * 64 + a * 32 + (lane & 31);
+        memcpy(&ah[a], &Ah[r][kk], 16);
+        memcpy(&al[a], &Al[r][kk], 16);
+      }
+      for (int b = 0; b < 2; ++b) {
+        const int c = wn * 64 + b * 32 + (lane & 31);
+        memcpy(&bh[b], &Bh[c][kk], 16);
+        memcpy(&bl[b], &Bl[c][kk], 16);
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 16; ++e) {
+        const int r = row0 + wm * 64 + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int c = col0 + wn * 64 + b * 32 + (lane & 31);
+        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
+      }
+}
+
+// ---- FP64 GEMM: C = A.A, 64 x 64 tile per block -------------------------------------
+// v_mfma_f64_16x16x4_f64: lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds C[l / 16 + 4 t][l % 16] in accumulator t.  Each output is updated by
+// a chain of four fused multiply-adds in ascending k (checked on gfx950 against
+// exactly rounded fma on random operands), so with k0 ascending the whole
+// product is the same fma chain as the textbook loop, bit for bit.  Wave
+// (wm, wn) owns rows 32 wm .. +31 and columns 32 wn .. +31 (2 x 2 MFMA blocks).
+constexpr int kDM = 64, kDK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restrict__ AT, DSel<double> sel)
+{
+  __shared__ double As[kDM][kDK + 1], Bs[kDM][kDK + 1];
+  const double *A;
+  double *C;
+  if (!resolve(sel, A, C)) return;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int row0 = blockIdx.y * kDM, col0 = blockIdx.x * kDM;
+  f64x4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0.0;
+  for (int k0 = 0; k0 < N; k0 += kDK) {
+    for (int p = threadIdx.x; p < kDM * kDK; p += 256) {
+      const int r = p / kDK, k = p % kDK;
+      const int gk = k0 + k;
+      As[r][k] = (row0 + r < N && gk < N) ? A[(size_t)(row0 + r) * N + gk] : 0.0;
+      Bs[r][k] = (col0 + r < N && gk < N) ? AT[(size_t)(col0 + r) * N + gk] : 0.0;
+    }
+    __syncthreads();
+    for (int ks = 0; ks < kDK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      double av[2], bv[2];
+      for (int a = 0; a < 2; ++a) av[a] = As[wm * 32 + a * 16 + (lane & 15)][kk];
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[wn * 32 + b * 16 + (lane & 15)][kk];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 4; ++e) {
+        const int r = row0 + wm * 32 + a * 16 + (lane >> 4) + 4 * e;
+        const int c = col0 + wn * 32 + b * 16 + (lane & 15);
+        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
+      }
+}
+
+// ---- per-row step outputs: U = 2X - Y, diagonals, norm row term ---------------------
+// One wave per row.  The norm's row term is the pairwise tree over the N column
+// positions, evaluated as the perfect tree over 64-column blocks (lane tree),
+// then over groups of 64 blocks, then over the (at most 64) groups; positions
+// past N contribute +0, the exact identity for these non-negative terms.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_rows(int N, T *const *bufs, const SP2State *st, StepScratch s)
+{
+  __shared__ double gs[4][kWave];
+  if (st->stop) return;
+  const int cur = st->cur;
+  const T *X = bufs[cur];
+  const T *Y = bufs[cur == 2 ? 0 : cur + 1];
+  T *U = bufs[cur == 0 ? 2 : cur - 1];
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * 4 + w;
+  if (i >= N) return;  // whole wave: i is wave-uniform
+  const int nblk = (N + kWave - 1) / kWave;
+  const int ngrp = (nblk + kWave - 1) / kWave;
+  for (int g = 0; g < ngrp; ++g) {
+    double mine = 0.0;
+    for (int b = g * kWave; b < min(nblk, (g + 1) * kWave); ++b) {
+      const int j = b * kWave + lane;
+      double q = 0.0;
+      if (j < N) {
+        const T x = X[(size_t)i * N + j], y = Y[(size_t)i * N + j];
+        U[(size_t)i * N + j] = T(2) * x - y;
+        const double d = (double)y - (double)x;
+        q = d * d;
+        if (j == i) {
+          s.d1[i] = (double)x;
+          s.d2[i] = (double)y;
+        }
+      }
+      const double t = __shfl(wave_tree(q), 0, kWave);
+      if (lane == b - g * kWave) mine = t;
+    }
+    const double gsum = wave_tree(mine);
+    if (lane == 0) gs[w][g] = gsum;
+  }
+  const double v = lane < ngrp ? gs[w][lane] : 0.0;
+  const double total = wave_tree(v);
+  if (lane == 0) {
+    s.e[i] = total;
+    s.wy[i] = 0;
+    s.wu[i] = 0;
+  }
+}
+
+// Gershgorin bounds per row: H_ii -/+ the sum over j != i of |H_ij|, ascending j
+__global__ __launch_bounds__(256) void k_dense_gersh(int N, const double *__restrict__ H, double *lo_out,
+                                                     double *hi_out)
+{
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double r = 0.0;
+  for (int j = 0; j < N; ++j)
+    if (j != i) r = r + fabs(H[(size_t)i * N + j]);
+  const double h = H[(size_t)i * N + i];
+  lo_out[i] = h - r;
+  hi_out[i] = h + r;
+}
+
+// X0 = (emax I - H) / (emax - emin), with inv = 1 / (emax - emin)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_x0(int N, const double *__restrict__ H, T *X, double emax, double inv)
+{
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)N * N) return;
+  const int i = (int)(q / N), j = (int)(q % N);
+  const double h = H[q];
+  const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
+  X[q] = (T)x;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_dense_copy(size_t n, const TS *__restrict__ a, TD *b)
+{
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) b[q] = (TD)a[q];
+}
+
+struct DMem {
+  void *p = nullptr;
+  ~DMem() { if (p) (void)hipFree(p); }
+  hipError_t alloc(size_t n) { return hipMalloc(&p, n ? n : 1); }
+};
+
+#define DTRY(expr)                                          \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return device_error(e_, #expr);   \
+  } while (0)
+
+hipError_t product_f32(int N, DSel<float> sel, uint16_t *hi, uint16_t *lo, uint16_t *hiT, uint16_t *loT,
+                       hipStream_t s)
+{
+  const dim3 tb((N + 31) / 32, (N + 31) / 32);
+  hipLaunchKernelGGL(k_split, tb, dim3(256), 0, s, N, sel, hi, lo, hiT, loT);
+  const dim3 gb((N + kBM - 1) / kBM, (N + kBM - 1) / kBM);
+  if (N % 8 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16x3<true>, gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16x3<false>, gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+  return hipGetLastError();
+}
+
+hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s)
+{
+  const dim3 tb((N + 31) / 32, (N + 31) / 32);
+  hipLaunchKernelGGL(k_transpose64, tb, dim3(256), 0, s, N, sel, XT);
+  const dim3 gb((N + kDM - 1) / kDM, (N + kDM - 1) / kDM);
+  hipLaunchKernelGGL(k_gemm_f64, gb, dim3(256), 0, s, N, XT, sel);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace ellsp2
+
+using namespace ellsp2;
 
 extern "C" int dense_x2(const void *d_A, void *d_C, int32_t N, int32_t mode, void *hip_stream)
 {
-  (void)d_A; (void)d_C; (void)N; (void)mode; (void)hip_stream;
-  return ELL_EINVAL;
+  if (!d_A || !d_C || N <= 0 || N > kMaxDenseN || d_A == d_C) return ELL_EINVAL;
+  if (mode != DENSE_F64 && mode != DENSE_BF16X3) return ELL_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t nn = (size_t)N * N;
+  if (mode == DENSE_BF16X3) {
+    DMem hi, lo, hiT, loT;
+    DTRY(hi.alloc(nn * 2));
+    DTRY(lo.alloc(nn * 2));
+    DTRY(hiT.alloc(nn * 2));
+    DTRY(loT.alloc(nn * 2));
+    DSel<float> sel{(const float *)d_A, (float *)d_C, nullptr, nullptr};
+    DTRY(product_f32(N, sel, (uint16_t *)hi.p, (uint16_t *)lo.p, (uint16_t *)hiT.p, (uint16_t *)loT.p, s));
+    DTRY(hipStreamSynchronize(s));
+  } else {
+    DMem at;
+    DTRY(at.alloc(nn * 8));
+    DSel<double> sel{(const double *)d_A, (double *)d_C, nullptr, nullptr};
+    DTRY(product_f64(N, sel, (double *)at.p, s));
+    DTRY(hipStreamSynchronize(s));
+  }
+  return ELL_OK;
 }
 
 extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_t mode, const sp2_params_t *p,
                                sp2_report_t *r, void *hip_stream)
 {
-  (void)d_H; (void)N; (void)d_D; (void)mode; (void)p; (void)r; (void)hip_stream;
-  return ELL_EINVAL;
+  if (!d_H || !d_D || N <= 0 || N > kMaxDenseN || !p || (const void *)d_H == (const void *)d_D) return ELL_EINVAL;
+  if (mode != DENSE_F64 && mode != DENSE_BF16X3) return ELL_EINVAL;
+  if (!(p->idem_target >= 0.0) || p->max_iter < 1 || p->fp64_tail_steps < 0 || !std::isfinite(p->n_occ))
+    return ELL_EINVAL;
+  if (r) {
+    r->status = 0;
+    r->iterations = r->fp32_iterations = r->final_M = 0;
+    r->eta = r->trace_x = r->emin = r->emax = r->seconds = r->x2_seconds = 0.0;
+    r->x2_bytes = 0;
+    r->x2_launches = 0;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const size_t nn = (size_t)N * N;
+  const bool lowp = mode == DENSE_BF16X3;
+
+  // Gershgorin bounds: per-row bounds on the device, min / max (exact) on the host
+  DMem glo, ghi;
+  DTRY(glo.alloc(sizeof(double) * N));
+  DTRY(ghi.alloc(sizeof(double) * N));
+  hipLaunchKernelGGL(k_dense_gersh, dim3((N + 255) / 256), dim3(256), 0, s, N, d_H, (double *)glo.p,
+                     (double *)ghi.p);
+  DTRY(hipGetLastError());
+  std::vector<double> hlo(N), hhi(N);
+  DTRY(hipMemcpyAsync(hlo.data(), glo.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  DTRY(hipMemcpyAsync(hhi.data(), ghi.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  DTRY(hipStreamSynchronize(s));
+  double emin = INFINITY, emax = -INFINITY;
+  for (int i = 0; i < N; ++i) {
+    if (!std::isfinite(hlo[i]) || !std::isfinite(hhi[i])) return ELL_ENONFINITE;
+    emin = std::min(emin, hlo[i]);
+    emax = std::max(emax, hhi[i]);
+  }
+  if (r) {
+    r->emin = emin;
+    r->emax = emax;
+  }
+  if (!(emax > emin)) return ELL_EDEGENERATE;
+  if (!(p->n_occ > 0.0 && p->n_occ < (double)N)) return ELL_EDEGENERATE;
+  const double inv = 1.0 / (emax - emin);
+
+  // working matrices: three of each precision in use, rotated by the device state
+  DMem b32[3], b64[3], hi, lo, hiT, loT, xt, ptrs32, ptrs64;
+  if (lowp) {
+    for (auto &b : b32) DTRY(b.alloc(nn * 4));
+    DTRY(hi.alloc(nn * 2));
+    DTRY(lo.alloc(nn * 2));
+    DTRY(hiT.alloc(nn * 2));
+    DTRY(loT.alloc(nn * 2));
+  }
+  for (auto &b : b64) DTRY(b.alloc(nn * 8));
+  DTRY(xt.alloc(nn * 8));
+  float *p32[3] = {(float *)b32[0].p, (float *)b32[1].p, (float *)b32[2].p};
+  double *p64[3] = {(double *)b64[0].p, (double *)b64[1].p, (double *)b64[2].p};
+  DTRY(ptrs32.alloc(sizeof(p32)));
+  DTRY(ptrs64.alloc(sizeof(p64)));
+  DTRY(hipMemcpyAsync(ptrs32.p, p32, sizeof(p32), hipMemcpyHostToDevice, s));
+  DTRY(hipMemcpyAsync(ptrs64.p, p64, sizeof(p64), hipMemcpyHostToDevice, s));
+
+  // step scratch and device state
+  const int nb = (N + kRedBlock - 1) / kRedBlock;
+  const size_t mi = (size_t)p->max_iter;
+  DMem d1, d2, e, wy, wu, part, partw, partn, out, outw, outn, state, h_trx, h_trx2, h_eta2, h_up, h_prec, h_maxw,
+      h_nx, h_ny;
+  DTRY(d1.alloc(8 * (size_t)N));
+  DTRY(d2.alloc(8 * (size_t)N));
+  DTRY(e.alloc(8 * (size_t)N));
+  DTRY(wy.alloc(4 * (size_t)N));
+  DTRY(wu.alloc(4 * (size_t)N));
+  DTRY(part.alloc(8 * 3 * (size_t)nb));
+  DTRY(partw.alloc(4 * 4 * (size_t)nb));
+  DTRY(partn.alloc(8 * 2 * (size_t)nb));
+  DTRY(out.alloc(8 * 3));
+  DTRY(outw.alloc(4 * 4));
+  DTRY(outn.alloc(8 * 2));
+  DTRY(state.alloc(sizeof(SP2State)));
+  DTRY(h_trx.alloc(8 * mi));
+  DTRY(h_trx2.alloc(8 * mi));
+  DTRY(h_eta2.alloc(8 * mi));
+  DTRY(h_up.alloc(mi));
+  DTRY(h_prec.alloc(mi));
+  DTRY(h_maxw.alloc(4 * mi));
+  DTRY(h_nx.alloc(8 * mi));
+  DTRY(h_ny.alloc(8 * mi));
+  StepScratch sc{};
+  sc.d1 = (double *)d1.p;
+  sc.d2 = (double *)d2.p;
+  sc.e = (double *)e.p;
+  sc.wy = (int32_t *)wy.p;
+  sc.wu = (int32_t *)wu.p;
+  sc.part = (double *)part.p;
+  sc.partw = (int32_t *)partw.p;
+  sc.partn = (int64_t *)partn.p;
+  sc.out = (double *)out.p;
+  sc.outw = (int32_t *)outw.p;
+  sc.outn = (int64_t *)outn.p;
+  sc.nb = nb;
+  SP2Hist hist{(double *)h_trx.p, (double *)h_trx2.p, (double *)h_eta2.p, (int8_t *)h_up.p,
+               (int8_t *)h_prec.p, (int32_t *)h_maxw.p, (int64_t *)h_nx.p, (int64_t *)h_ny.p};
+  SP2Cfg cfg{};
+  cfg.n_occ = p->n_occ;
+  cfg.target2 = p->idem_target * p->idem_target;
+  cfg.switch2 = p->switch_eta * p->switch_eta;
+  cfg.max_iter = p->max_iter;
+  cfg.tail = p->fp64_tail_steps;
+  cfg.stall = p->stall_stop ? 1 : 0;
+  cfg.mixed = lowp ? 1 : 0;
+  cfg.span = 0;
+
+  std::vector<hipEvent_t> ev(2 + (p->profile ? 2 * (size_t)std::max(1, p->poll_every) : 0), nullptr);
+  struct EvList {
+    std::vector<hipEvent_t> &v;
+    ~EvList()
+    {
+      for (auto x : v)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } evl{ev};
+  for (auto &x : ev) DTRY(hipEventCreate(&x));
+  hipEvent_t t0 = ev[0], t1 = ev[1];
+  DTRY(hipEventRecord(t0, s));
+  const unsigned eb = (unsigned)((nn + 255) / 256);
+  if (lowp)
+    hipLaunchKernelGGL((k_dense_x0<float>), dim3(eb), dim3(256), 0, s, N, d_H, p32[0], emax, inv);
+  else
+    hipLaunchKernelGGL((k_dense_x0<double>), dim3(eb), dim3(256), 0, s, N, d_H, p64[0], emax, inv);
+  DTRY(hipGetLastError());
+  SP2State hs{};
+  hs.status = ST_RUNNING;
+  hs.phase32 = lowp ? 1 : 0;
+  hs.cap = INT_MAX;
+  hs.sw = INT_MAX;
+  hs.nnz_cur = (int64_t)nn;
+  SP2State *dst = (SP2State *)state.p;
+  DTRY(hipMemcpyAsync(dst, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+  const int poll = p->poll_every > 0 ? p->poll_every : 1;
+  const dim3 rowgrid((N + 3) / 4);
+  DSel<float> sel32{nullptr, nullptr, (float *const *)ptrs32.p, dst};
+  DSel<double> sel64{nullptr, nullptr, (double *const *)ptrs64.p, dst};
+  double x2_sec = 0.0;
+  int32_t x2_n = 0;
+  int64_t x2_bytes = 0;
+  int status = ST_RUNNING;
+  for (int64_t batch = 0;; ++batch) {
+    if (batch > (int64_t)p->max_iter + 8) {
+      set_device_error("dense_sp2_solve: the device state did not reach a stop");
+      return ELL_EDEVICE;
+    }
+    const int iter0 = hs.iter;
+    for (int q = 0; q < poll; ++q) {
+      if (p->profile) DTRY(hipEventRecord(ev[2 + 2 * q], s));
+      if (hs.phase32)
+        DTRY(product_f32(N, sel32, (uint16_t *)hi.p, (uint16_t *)lo.p, (uint16_t *)hiT.p, (uint16_t *)loT.p, s));
+      else
+        DTRY(product_f64(N, sel64, (double *)xt.p, s));
+      if (p->profile) DTRY(hipEventRecord(ev[3 + 2 * q], s));
+      if (hs.phase32)
+        hipLaunchKernelGGL((k_dense_rows<float>), rowgrid, dim3(256), 0, s, N, (float *const *)ptrs32.p, dst, sc);
+      else
+        hipLaunchKernelGGL((k_dense_rows<double>), rowgrid, dim3(256), 0, s, N, (double *const *)ptrs64.p, dst,
+                           sc);
+      DTRY(hipGetLastError());
+      DTRY(launch_reduce(N, dst, sc, s));
+      DTRY(launch_decide(dst, cfg, hist, sc, s));
+    }
+    const int phase32 = hs.phase32;
+    DTRY(hipMemcpyAsync(&hs, dst, sizeof(hs), hipMemcpyDeviceToHost, s));
+    DTRY(hipStreamSynchronize(s));
+    if (p->profile) {  // products that ran: one per decision taken in this batch
+      const int ran = std::min(poll, hs.iter - iter0);
+      for (int q = 0; q < ran; ++q) {
+        float ms = 0.f;
+        DTRY(hipEventElapsedTime(&ms, ev[2 + 2 * q], ev[3 + 2 * q]));
+        x2_sec += ms * 1e-3;
+        ++x2_n;
+        // algorithmic traffic of one product: X read once, X^2 written once
+        x2_bytes += (int64_t)nn * (phase32 ? 8 : 16);
+      }
+    }
+    if (!hs.stop) continue;
+    if (hs.status == ST_SWITCH) {
+      // widen the current FP32 X into FP64 buffer 0 and go on in FP64
+      hipLaunchKernelGGL((k_dense_copy<float, double>), dim3(eb), dim3(256), 0, s, nn, p32[hs.cur], p64[0]);
+      DTRY(hipGetLastError());
+      hs.cur = 0;
+      hs.phase32 = 0;
+      hs.stop = 0;
+      hs.status = ST_RUNNING;
+      DTRY(hipMemcpyAsync(dst, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+      continue;
+    }
+    status = hs.status;
+    break;
+  }
+  DTRY(hipEventRecord(t1, s));
+  // the returned X, in double
+  if (hs.phase32)
+    hipLaunchKernelGGL((k_dense_copy<float, double>), dim3(eb), dim3(256), 0, s, nn, p32[hs.cur], d_D);
+  else
+    hipLaunchKernelGGL((k_dense_copy<double, double>), dim3(eb), dim3(256), 0, s, nn, p64[hs.cur], d_D);
+  DTRY(hipGetLastError());
+  DTRY(hipStreamSynchronize(s));
+  if (r) {
+    const int n = hs.iter;
+    r->status = status;
+    r->iterations = n;
+    r->final_M = N;
+    r->eta = std::sqrt(hs.eta2);
+    r->trace_x = hs.trx;
+    float ms = 0.f;
+    DTRY(hipEventElapsedTime(&ms, t0, t1));
+    r->seconds = ms * 1e-3;
+    std::vector<double> va(n), vb(n), vc(n);
+    std::vector<int8_t> vu(n), vp(n);
+    if (n > 0) {
+      DTRY(hipMemcpy(va.data(), h_trx.p, 8 * (size_t)n, hipMemcpyDeviceToHost));
+      DTRY(hipMemcpy(vb.data(), h_trx2.p, 8 * (size_t)n, hipMemcpyDeviceToHost));
+      DTRY(hipMemcpy(vc.data(), h_eta2.p, 8 * (size_t)n, hipMemcpyDeviceToHost));
+      DTRY(hipMemcpy(vu.data(), h_up.p, (size_t)n, hipMemcpyDeviceToHost));
+      DTRY(hipMemcpy(vp.data(), h_prec.p, (size_t)n, hipMemcpyDeviceToHost));
+    }
+    int f32 = 0;
+    for (int q = 0; q < n; ++q) {
+      f32 += vp[q] ? 1 : 0;
+      if (r->hist_trx) r->hist_trx[q] = va[q];
+      if (r->hist_trx2) r->hist_trx2[q] = vb[q];
+      if (r->hist_eta2) r->hist_eta2[q] = vc[q];
+      if (r->hist_up) r->hist_up[q] = vu[q];
+      if (r->hist_prec) r->hist_prec[q] = vp[q];
+      if (r->hist_maxw) r->hist_maxw[q] = N;
+    }
+    r->fp32_iterations = f32;
+    r->x2_seconds = x2_sec;
+    r->x2_launches = x2_n;
+    r->x2_bytes = x2_bytes;
+  }
+  return status;
 }

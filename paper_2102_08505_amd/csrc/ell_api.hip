@@ -31,14 +31,18 @@ struct ellpack {
 };
 
 namespace {
-
 thread_local std::string g_last_error = "no error";
+}  // namespace
 
-int device_error(hipError_t e, const char *what)
+int ellsp2::device_error(hipError_t e, const char *what)
 {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? ELL_ENOMEM : ELL_EDEVICE;
 }
+
+void ellsp2::set_device_error(const char *what) { g_last_error = what; }
+
+namespace {
 
 #define HIP_TRY(expr)                                          \
   do {                                                         \
@@ -113,7 +117,7 @@ int ensure_valid(const ellpack *A)
 
 // Scratch of one fused step for N rows.
 struct StepMem {
-  DevMem d1, d2, e, wy, wu, part, partw, partn, out, outw, outn;
+  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags;
   StepScratch s{};
   hipError_t alloc(int N)
   {
@@ -121,16 +125,21 @@ struct StepMem {
     hipError_t err;
     if ((err = d1.alloc(sizeof(double) * N)) || (err = d2.alloc(sizeof(double) * N)) ||
         (err = e.alloc(sizeof(double) * N)) || (err = wy.alloc(sizeof(int32_t) * N)) ||
-        (err = wu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nb)) ||
-        (err = partw.alloc(sizeof(int32_t) * 2 * nb)) || (err = partn.alloc(sizeof(int64_t) * 2 * nb)) ||
-        (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 2)) ||
-        (err = outn.alloc(sizeof(int64_t) * 2)))
+        (err = wu.alloc(sizeof(int32_t) * N)) || (err = ly.alloc(sizeof(int32_t) * N)) ||
+        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nb)) ||
+        (err = partw.alloc(sizeof(int32_t) * 4 * nb)) || (err = partn.alloc(sizeof(int64_t) * 2 * nb)) ||
+        (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
+        (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))))
       return err;
+    if ((err = hipMemset(flags.p, 0, sizeof(int32_t)))) return err;
     s.d1 = d1.as<double>();
     s.d2 = d2.as<double>();
     s.e = e.as<double>();
     s.wy = wy.as<int32_t>();
     s.wu = wu.as<int32_t>();
+    s.ly = ly.as<int32_t>();
+    s.lu = lu.as<int32_t>();
+    s.flags = flags.as<int32_t>();
     s.part = part.as<double>();
     s.partw = partw.as<int32_t>();
     s.partn = partn.as<int64_t>();
@@ -144,18 +153,75 @@ struct StepMem {
 
 bool bad_tau(double tau) { return !(tau >= 0.0); }  // rejects NaN and negatives
 
-template <typename T>
-int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
+// The ELLPACK pipeline neither writes interval lengths nor raises the fallback flag.
+StepScratch ell_scratch(const StepScratch &s)
 {
-  const int N = X->N;
-  StepMem m;
-  HIP_TRY(m.alloc(N));
-  Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
-  HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, m.s, X->stream));
-  HIP_TRY(launch_reduce(N, nullptr, m.s, X->stream, X->nnz, Y->nnz, nullptr));
-  HIP_TRY(launch_final_only(m.s, X->stream));
+  StepScratch t = s;
+  t.ly = t.lu = nullptr;
+  t.flags = nullptr;
+  return t;
+}
+
+int32_t roundup64(int64_t x) { return (int32_t)((x + 63) / 64 * 64); }
+
+// Span-form storage of one matrix (see SpanView).
+template <typename T>
+struct SpanMem {
+  DevMem val, base, len;
+  int32_t SW = 0;
+  hipError_t alloc(int N, int32_t sw)
+  {
+    SW = sw;
+    hipError_t e;
+    if ((e = val.alloc(sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard))) ||
+        (e = base.alloc(sizeof(int32_t) * ((size_t)N + kSpanPadRows))) ||
+        (e = len.alloc(sizeof(int32_t) * ((size_t)N + kSpanPadRows))))
+      return e;
+    // rows past N read as empty by the band kernel's batched interval loads
+    if ((e = hipMemset(base.p, 0, sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    if ((e = hipMemset(len.p, 0, sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    // the guard bands are read (and masked) by the band kernel: keep them finite
+    return hipMemset(val.p, 0, sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard));
+  }
+  void release()
+  {
+    val.release();
+    base.release();
+    len.release();
+    SW = 0;
+  }
+  SpanView<T> v() const
+  {
+    return SpanView<T>{val.as<T>() + kSpanGuard, base.as<int32_t>(), len.as<int32_t>(), SW};
+  }
+};
+
+// Longest row interval of an ELLPACK matrix and whether it stores exact zeros.
+template <typename T>
+int ell_extent(const ellpack *A, DevMem &lens, int32_t *maxlen, bool *zeros)
+{
+  DevMem fl;
+  HIP_TRY(lens.alloc(sizeof(int32_t) * A->N));
+  HIP_TRY(fl.alloc(sizeof(int32_t)));
+  HIP_TRY(hipMemsetAsync(fl.p, 0, sizeof(int32_t), A->stream));
+  HIP_TRY(launch_ell_extent<T>(A->N, view<T>(A), lens.as<int32_t>(), fl.as<int32_t>(), A->stream));
+  std::vector<int32_t> h(A->N);
+  int32_t f = 0;
+  HIP_TRY(hipMemcpyAsync(h.data(), lens.p, sizeof(int32_t) * A->N, hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipMemcpyAsync(&f, fl.p, sizeof(f), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  int32_t m = 0;
+  for (int32_t v : h) m = std::max(m, v);
+  *maxlen = m;
+  *zeros = (f & 4) != 0;
+  return ELL_OK;
+}
+
+template <typename T>
+int finish_step(const ellpack *X, ellpack *Y, ellpack *U, const StepMem &m, double out[3], int32_t widths[2])
+{
   double h[3];
-  int32_t w[2];
+  int32_t w[4];
   HIP_TRY(hipMemcpyAsync(h, m.s.out, sizeof(h), hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipMemcpyAsync(w, m.s.outw, sizeof(w), hipMemcpyDeviceToHost, X->stream));
   HIP_TRY(hipStreamSynchronize(X->stream));
@@ -173,6 +239,44 @@ int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3]
   Y->validated = true;
   if (U) U->validated = true;
   return ELL_OK;
+}
+
+// One fused step on ELLPACK handles.  Matrices whose rows are short intervals
+// go through the register-tiled band kernel (after an exact conversion to span
+// form); anything else, or a row group whose window is too wide, through the
+// LDS-window kernel.
+template <typename T>
+int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
+{
+  const int N = X->N;
+  StepMem m;
+  HIP_TRY(m.alloc(N));
+  Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
+  DevMem lens;
+  int32_t maxlen = 0;
+  bool zeros = false;
+  int rc = ell_extent<T>(X, lens, &maxlen, &zeros);
+  if (rc) return rc;
+  if (!zeros && maxlen <= kMaxCap) {
+    SpanMem<T> sx;
+    HIP_TRY(sx.alloc(N, std::max(64, roundup64(maxlen))));
+    HIP_TRY(launch_ell_to_span<T>(N, view<T>(X), sx.v(), X->stream));
+    SpanRot3<T> spans{{sx.v(), sx.v(), sx.v()}};  // outputs go to ELLPACK; the span slots are unused
+    HIP_TRY(launch_x2_band<T>(N, spans, bufs, nullptr, U != nullptr, true, (T)tau, m.s, m.s.flags, X->stream));
+    int32_t fb = 0;
+    HIP_TRY(hipMemcpyAsync(&fb, m.s.flags, sizeof(fb), hipMemcpyDeviceToHost, X->stream));
+    HIP_TRY(hipStreamSynchronize(X->stream));
+    if (!(fb & 1)) {
+      HIP_TRY(launch_reduce(N, nullptr, m.s, X->stream));
+      HIP_TRY(launch_final_only(m.s, X->stream));
+      return finish_step<T>(X, Y, U, m, out, widths);
+    }
+  }
+  const StepScratch se = ell_scratch(m.s);
+  HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, se, X->stream));
+  HIP_TRY(launch_reduce(N, nullptr, se, X->stream));
+  HIP_TRY(launch_final_only(se, X->stream));
+  return finish_step<T>(X, Y, U, m, out, widths);
 }
 
 int check_step_args(const ellpack *X, const ellpack *Y, const ellpack *U, double tau)
@@ -386,7 +490,7 @@ extern "C" int ellpack_trace(const ellpack_t *A, double *trace_out)
 // ===========================================================================
 namespace {
 
-// Three working matrices of one precision with capacity cap.
+// Three working matrices of one precision in ELLPACK form, capacity cap.
 template <typename T>
 struct WorkSet {
   DevMem nnz[3], idx[3], val[3];
@@ -415,14 +519,39 @@ struct WorkSet {
   Rot3<T> rot() const { return Rot3<T>{{v(0), v(1), v(2)}}; }
 };
 
+// Three working matrices of one precision in span form, stride SW.
+template <typename T>
+struct SpanSet {
+  SpanMem<T> m[3];
+  int32_t SW = 0;
+  hipError_t alloc(int N, int32_t sw)
+  {
+    SW = sw;
+    for (int b = 0; b < 3; ++b) {
+      hipError_t e = m[b].alloc(N, sw);
+      if (e) return e;
+    }
+    return hipSuccess;
+  }
+  void release()
+  {
+    for (int b = 0; b < 3; ++b) m[b].release();
+    SW = 0;
+  }
+  SpanView<T> v(int b) const { return m[b].v(); }
+  SpanRot3<T> rot() const { return SpanRot3<T>{{v(0), v(1), v(2)}}; }
+};
+
 struct Solver {
   int N = 0;
   hipStream_t stream = nullptr;
   StepMem step;
   DevMem state, hist_trx, hist_trx2, hist_eta2, hist_up, hist_prec, hist_maxw, hist_nnzx, hist_nnzy;
-  DevMem glo, ghi, gout, flags, wmax;
+  DevMem glo, ghi, gout, flags, wmax, total;
   SP2State *host_state = nullptr;
   std::vector<hipEvent_t> events;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // step-kernel launches when profiling
+  bool profile = false;
   ~Solver()
   {
     if (host_state) (void)hipHostFree(host_state);
@@ -434,63 +563,39 @@ struct Solver {
                    hist_up.as<int8_t>(),   hist_prec.as<int8_t>(), hist_maxw.as<int32_t>(),
                    hist_nnzx.as<int64_t>(), hist_nnzy.as<int64_t>()};
   }
+  hipError_t mark(hipEvent_t *e)
+  {
+    hipError_t r = hipEventCreate(e);
+    if (r == hipSuccess) events.push_back(*e);
+    if (r == hipSuccess) r = hipEventRecord(*e, stream);
+    return r;
+  }
 };
 
-template <typename T>
-hipError_t enqueue_step(Solver &S, const WorkSet<T> &W, T tau, const SP2Cfg &cfg)
-{
-  hipError_t e;
-  const Rot3<T> r = W.rot();
-  if ((e = launch_x2_step<T>(S.N, r, S.state.as<SP2State>(), true, tau, S.step.s, S.stream))) return e;
-  if ((e = launch_reduce(S.N, S.state.as<SP2State>(), S.step.s, S.stream, r.b[0].nnz, r.b[1].nnz, r.b[2].nnz)))
-    return e;
-  return launch_decide(S.state.as<SP2State>(), cfg, S.hist(), S.step.s, S.stream);
-}
-
-// Launch `count` iterations; with profiling, bracket every step kernel with events.
-template <typename T>
-int run_batch(Solver &S, const WorkSet<T> &W, T tau, const SP2Cfg &cfg, int count, bool profile,
-              std::vector<std::pair<hipEvent_t, hipEvent_t>> &marks)
-{
-  for (int q = 0; q < count; ++q) {
-    if (profile) {
-      hipEvent_t a, b;
-      HIP_TRY(hipEventCreate(&a));
-      S.events.push_back(a);
-      HIP_TRY(hipEventCreate(&b));
-      S.events.push_back(b);
-      HIP_TRY(hipEventRecord(a, S.stream));
-      HIP_TRY(launch_x2_step<T>(S.N, W.rot(), S.state.as<SP2State>(), true, tau, S.step.s, S.stream));
-      HIP_TRY(hipEventRecord(b, S.stream));
-      const Rot3<T> r = W.rot();
-      HIP_TRY(launch_reduce(S.N, S.state.as<SP2State>(), S.step.s, S.stream, r.b[0].nnz, r.b[1].nnz,
-                            r.b[2].nnz));
-      HIP_TRY(launch_decide(S.state.as<SP2State>(), cfg, S.hist(), S.step.s, S.stream));
-      marks.emplace_back(a, b);
-    } else {
-      HIP_TRY(enqueue_step<T>(S, W, tau, cfg));
-    }
-  }
-  return ELL_OK;
-}
+// Pipelines: the step kernel, then the reductions and the decision.
+enum Pipe { PIPE_SPAN = 0, PIPE_ELL = 1 };
 
 template <typename T>
-int grow_set(Solver &S, WorkSet<T> &W, int32_t need)
+int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T> &W, T tau, SP2Cfg cfg)
 {
-  const int32_t newcap = roundup32(need);
-  if (newcap > kMaxCap) return ELL_EOVERFLOW;
-  WorkSet<T> G;
-  HIP_TRY(G.alloc(S.N, newcap));
-  const int cur = S.host_state->cur;
-  HIP_TRY((launch_copy<T, T>(S.N, W.v(cur), G.v(0), S.stream)));
-  HIP_TRY(hipStreamSynchronize(S.stream));
-  W.release();
-  for (int b = 0; b < 3; ++b) {
-    std::swap(W.nnz[b].p, G.nnz[b].p);
-    std::swap(W.idx[b].p, G.idx[b].p);
-    std::swap(W.val[b].p, G.val[b].p);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (S.profile) HIP_TRY(S.mark(&a));
+  SP2State *st = S.state.as<SP2State>();
+  StepScratch sc = S.step.s;
+  if (pipe == PIPE_SPAN) {
+    cfg.span = 1;
+    HIP_TRY(launch_x2_band<T>(S.N, Sp.rot(), W.rot(), st, true, false, tau, sc, sc.flags, S.stream));
+  } else {
+    cfg.span = 0;
+    sc = ell_scratch(sc);
+    HIP_TRY(launch_x2_step<T>(S.N, W.rot(), st, true, tau, sc, S.stream));
   }
-  W.cap = newcap;
+  if (S.profile) {
+    HIP_TRY(S.mark(&b));
+    S.marks.emplace_back(a, b);
+  }
+  HIP_TRY(launch_reduce(S.N, st, sc, S.stream));
+  HIP_TRY(launch_decide(st, cfg, S.hist(), sc, S.stream));
   return ELL_OK;
 }
 
@@ -505,40 +610,56 @@ int check_params(const sp2_params_t *p)
   return ELL_OK;
 }
 
-// Copy the final X (buffer cur of W) into D, reallocating an owned D if needed.
-template <typename T>
-int deliver(Solver &S, const WorkSet<T> &W, int cur, ellpack *D, int32_t *final_width)
+// Reallocate an owned D to capacity M (contents discarded).
+int regrow_owned(ellpack *D, int32_t M)
 {
-  DevMem wm;
-  HIP_TRY(wm.alloc(sizeof(int32_t)));
-  // widest stored row of X: the copy kernel clamps, so measure first
-  std::vector<int32_t> hn(S.N);
-  HIP_TRY(hipMemcpyAsync(hn.data(), W.nnz[cur].p, sizeof(int32_t) * S.N, hipMemcpyDeviceToHost, S.stream));
-  HIP_TRY(hipStreamSynchronize(S.stream));
-  int32_t width = 0;
-  for (int32_t v : hn) width = std::max(width, v);
-  *final_width = width;
-  if (width > D->M) {
-    if (!D->owned) return ELL_EOVERFLOW;
-    const int32_t M = std::max(roundup32(width), 32);
-    int32_t *idx = nullptr;
-    double *val = nullptr;
-    HIP_TRY(hipMalloc(&idx, sizeof(int32_t) * (size_t)D->N * M));
-    hipError_t e = hipMalloc(&val, sizeof(double) * (size_t)D->N * M);
-    if (e != hipSuccess) {
-      (void)hipFree(idx);
-      return device_error(e, "deliver");
-    }
-    (void)hipFree(D->idx);
-    (void)hipFree(D->val);
-    D->idx = idx;
-    D->val = val;
-    D->M = M;
+  int32_t *idx = nullptr;
+  double *val = nullptr;
+  HIP_TRY(hipMalloc(&idx, sizeof(int32_t) * (size_t)D->N * M));
+  hipError_t e = hipMalloc(&val, sizeof(double) * (size_t)D->N * M);
+  if (e != hipSuccess) {
+    (void)hipFree(idx);
+    return device_error(e, "sp2_solve: result allocation");
   }
-  HIP_TRY((launch_copy<T, double>(S.N, W.v(cur), view<double>(D), S.stream)));
-  HIP_TRY(hipStreamSynchronize(S.stream));
-  D->validated = true;
+  (void)hipFree(D->idx);
+  (void)hipFree(D->val);
+  D->idx = idx;
+  D->val = val;
+  D->M = M;
   return ELL_OK;
+}
+
+// The final X into D (ELLPACK, FP64), reallocating an owned D when too narrow.
+template <typename T>
+int deliver(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T> &W, int cur, ellpack *D,
+            int32_t *final_width)
+{
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    HIP_TRY(hipMemsetAsync(S.wmax.p, 0, sizeof(int32_t), S.stream));
+    if (pipe == PIPE_SPAN) {
+      HIP_TRY((launch_span_to_ell<T, double>(S.N, Sp.v(cur), view<double>(D), S.wmax.as<int32_t>(), S.stream)));
+    } else {
+      std::vector<int32_t> hn(S.N);
+      HIP_TRY(hipMemcpyAsync(hn.data(), W.nnz[cur].p, sizeof(int32_t) * S.N, hipMemcpyDeviceToHost, S.stream));
+      HIP_TRY(hipStreamSynchronize(S.stream));
+      int32_t w = 0;
+      for (int32_t v : hn) w = std::max(w, v);
+      HIP_TRY(hipMemcpyAsync(S.wmax.p, &w, sizeof(w), hipMemcpyHostToDevice, S.stream));
+      if (w <= D->M) HIP_TRY((launch_copy<T, double>(S.N, W.v(cur), view<double>(D), S.stream)));
+    }
+    int32_t width = 0;
+    HIP_TRY(hipMemcpyAsync(&width, S.wmax.p, sizeof(width), hipMemcpyDeviceToHost, S.stream));
+    HIP_TRY(hipStreamSynchronize(S.stream));
+    *final_width = width;
+    if (width <= D->M) {
+      D->validated = true;
+      return ELL_OK;
+    }
+    if (!D->owned) return ELL_EOVERFLOW;
+    int rc = regrow_owned(D, std::max(roundup32(width), 32));
+    if (rc) return rc;
+  }
+  return ELL_EOVERFLOW;
 }
 
 }  // namespace
@@ -566,6 +687,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   Solver S;
   S.N = N;
   S.stream = D->stream;
+  S.profile = p->profile != 0;
   hipStream_t st = S.stream;
   HIP_TRY(S.step.alloc(N));
   HIP_TRY(S.state.alloc(sizeof(SP2State)));
@@ -584,14 +706,11 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   HIP_TRY(S.gout.alloc(sizeof(double) * 2));
   HIP_TRY(S.flags.alloc(sizeof(int32_t)));
   HIP_TRY(S.wmax.alloc(sizeof(int32_t)));
+  HIP_TRY(S.total.alloc(sizeof(unsigned long long)));
   HIP_TRY(hipHostMalloc((void **)&S.host_state, sizeof(SP2State), hipHostMallocDefault));
 
   hipEvent_t t0, t1;
-  HIP_TRY(hipEventCreate(&t0));
-  S.events.push_back(t0);
-  HIP_TRY(hipEventCreate(&t1));
-  S.events.push_back(t1);
-  HIP_TRY(hipEventRecord(t0, st));
+  HIP_TRY(S.mark(&t0));
 
   // Init: Gershgorin bounds (one synchronisation: degenerate spectra are an error)
   HIP_TRY(hipMemsetAsync(S.flags.p, 0, sizeof(int32_t), st));
@@ -612,30 +731,72 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   if (!(p->n_occ > 0.0 && p->n_occ < (double)N)) return ELL_EDEGENERATE;
   const double inv = 1.0 / (emax - emin);
 
-  // Working capacity: the caller's D capacity as a hint, at least X0's width bound.
+  // X0 in ELLPACK form (capacity grows if a row is wider)
   int32_t cap = roundup32(std::min<int64_t>((int64_t)H->M + 1, N));
   cap = std::max(cap, std::min(roundup32(D->M), roundup32(N)));
   cap = std::min(std::max(cap, 32), kMaxCap);
-
   WorkSet<float> W32;
   WorkSet<double> W64;
-  // X0 into buffer 0 (grows if a row is wider than the capacity)
+  SpanSet<float> S32;
+  SpanSet<double> S64;
+  unsigned long long nnz0 = 0;
   for (;;) {
     HIP_TRY(hipMemsetAsync(S.wmax.p, 0, sizeof(int32_t), st));
+    HIP_TRY(hipMemsetAsync(S.total.p, 0, sizeof(unsigned long long), st));
     if (mixed) {
       HIP_TRY(W32.alloc(N, cap));
       HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), emax, inv, (float)p->tau_fp32, S.wmax.as<int32_t>(),
-                               st));
+                               S.total.as<unsigned long long>(), st));
     } else {
       HIP_TRY(W64.alloc(N, cap));
-      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), emax, inv, p->tau, S.wmax.as<int32_t>(), st));
+      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), emax, inv, p->tau, S.wmax.as<int32_t>(),
+                                S.total.as<unsigned long long>(), st));
     }
     int32_t w0 = 0;
     HIP_TRY(hipMemcpyAsync(&w0, S.wmax.p, sizeof(w0), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&nnz0, S.total.p, sizeof(nnz0), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (w0 <= cap) break;
     cap = roundup32(w0);
     if (cap > kMaxCap) return ELL_EOVERFLOW;
+  }
+
+  // Span pipeline when X0's rows are intervals short enough for it.
+  Pipe pipe = PIPE_ELL;
+  {
+    DevMem lens;
+    int32_t maxlen = 0;
+    bool zeros = false;
+    ellpack tmp;
+    tmp.N = N;
+    tmp.stream = st;
+    if (mixed) {
+      tmp.M = W32.cap;
+      tmp.nnz = W32.nnz[0].as<int32_t>();
+      tmp.idx = W32.idx[0].as<int32_t>();
+      tmp.val = W32.val[0].p;
+      rc = ell_extent<float>(&tmp, lens, &maxlen, &zeros);
+    } else {
+      tmp.M = W64.cap;
+      tmp.nnz = W64.nnz[0].as<int32_t>();
+      tmp.idx = W64.idx[0].as<int32_t>();
+      tmp.val = W64.val[0].p;
+      rc = ell_extent<double>(&tmp, lens, &maxlen, &zeros);
+    }
+    tmp.nnz = nullptr;  // borrowed: not freed by ~ellpack (plain struct)
+    if (rc) return rc;
+    const int32_t sw = std::min(std::max(256, roundup64(maxlen)), std::max(64, roundup64(N)));
+    if (!zeros && maxlen <= kMaxCap) {
+      if (mixed) {
+        HIP_TRY(S32.alloc(N, sw));
+        HIP_TRY(launch_ell_to_span<float>(N, W32.v(0), S32.v(0), st));
+      } else {
+        HIP_TRY(S64.alloc(N, sw));
+        HIP_TRY(launch_ell_to_span<double>(N, W64.v(0), S64.v(0), st));
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      pipe = PIPE_SPAN;
+    }
   }
 
   SP2State &hs = *S.host_state;
@@ -644,6 +805,8 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   hs.status = ST_RUNNING;
   hs.phase32 = mixed ? 1 : 0;
   hs.cap = cap;
+  hs.sw = mixed ? S32.SW : S64.SW;
+  hs.nnz_cur = (int64_t)nnz0;
   HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
 
   SP2Cfg cfg{};
@@ -655,12 +818,17 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   cfg.stall = p->stall_stop ? 1 : 0;
   cfg.mixed = mixed ? 1 : 0;
 
-  const bool profile = p->profile != 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
-  std::vector<int> useful;  // per batch: number of step kernels that did work
+  auto restart = [&]() -> int {
+    hs.stop = 0;
+    hs.status = ST_RUNNING;
+    HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+    return ELL_OK;
+  };
+
   int status = ST_RUNNING;
-  // every batch advances the iteration count, grows the capacity or switches
-  // precision, so this bounds the loop even if the device control misbehaved
+  // every batch advances the iteration count or changes capacity, precision or
+  // pipeline (each a bounded number of times), so this bounds the loop even if
+  // the device control misbehaved
   const int64_t max_batches = (int64_t)p->max_iter + 64;
   for (int64_t batch = 0;; ++batch) {
     if (batch > max_batches) {
@@ -668,56 +836,157 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       return ELL_EDEVICE;
     }
     const int iter_before = hs.iter;
-    const size_t mark0 = marks.size();
-    if (hs.phase32)
-      rc = run_batch<float>(S, W32, (float)p->tau_fp32, cfg, poll, profile, marks);
-    else
-      rc = run_batch<double>(S, W64, p->tau, cfg, poll, profile, marks);
-    if (rc) return rc;
+    const size_t mark0 = S.marks.size();
+    for (int q = 0; q < poll; ++q) {
+      rc = hs.phase32 ? launch_iteration<float>(S, pipe, S32, W32, (float)p->tau_fp32, cfg)
+                      : launch_iteration<double>(S, pipe, S64, W64, p->tau, cfg);
+      if (rc) return rc;
+    }
     HIP_TRY(hipMemcpyAsync(&hs, S.state.p, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (profile) {
-      int worked = hs.iter - iter_before + (hs.stop && hs.status == ELL_EOVERFLOW ? 1 : 0);
-      for (size_t q = mark0; q < marks.size(); ++q)
-        if ((int)(q - mark0) >= worked) marks[q].first = nullptr;  // launched after the stop
+    if (S.profile) {
+      // step kernels launched after the stop returned at once: drop them
+      const bool redo = hs.stop && (hs.status == ELL_EOVERFLOW || hs.status == ST_FALLBACK);
+      const int worked = hs.iter - iter_before + (redo ? 1 : 0);
+      for (size_t q = mark0; q < S.marks.size(); ++q)
+        if ((int)(q - mark0) >= worked) S.marks[q].first = nullptr;
     }
     if (!hs.stop) continue;
     if (hs.status == ELL_EOVERFLOW) {
-      rc = hs.phase32 ? grow_set<float>(S, W32, hs.need_width) : grow_set<double>(S, W64, hs.need_width);
-      if (rc) return rc;
+      const int32_t need = hs.need_width;
+      if (pipe == PIPE_SPAN) {
+        const int32_t sw = roundup64(need);
+        if (sw > kMaxCap) {
+          hs.status = ST_FALLBACK;  // continue on ELLPACK rather than grow the interval stride further
+        } else {
+          if (hs.phase32) {
+            SpanSet<float> G;
+            HIP_TRY(G.alloc(N, sw));
+            HIP_TRY((launch_span_copy<float, float>(N, S32.v(hs.cur), G.v(0), st)));
+            HIP_TRY(hipStreamSynchronize(st));
+            S32.release();
+            for (int b = 0; b < 3; ++b) {
+              std::swap(S32.m[b].val.p, G.m[b].val.p);
+              std::swap(S32.m[b].base.p, G.m[b].base.p);
+              std::swap(S32.m[b].len.p, G.m[b].len.p);
+              S32.m[b].SW = sw;
+            }
+            S32.SW = sw;
+          } else {
+            SpanSet<double> G;
+            HIP_TRY(G.alloc(N, sw));
+            HIP_TRY((launch_span_copy<double, double>(N, S64.v(hs.cur), G.v(0), st)));
+            HIP_TRY(hipStreamSynchronize(st));
+            S64.release();
+            for (int b = 0; b < 3; ++b) {
+              std::swap(S64.m[b].val.p, G.m[b].val.p);
+              std::swap(S64.m[b].base.p, G.m[b].base.p);
+              std::swap(S64.m[b].len.p, G.m[b].len.p);
+              S64.m[b].SW = sw;
+            }
+            S64.SW = sw;
+          }
+          hs.cur = 0;
+          hs.sw = sw;
+          if ((rc = restart())) return rc;
+          continue;
+        }
+      } else {
+        const int32_t newcap = roundup32(need);
+        if (newcap > kMaxCap) {
+          status = ELL_EOVERFLOW;
+          break;
+        }
+        if (hs.phase32) {
+          WorkSet<float> G;
+          HIP_TRY(G.alloc(N, newcap));
+          HIP_TRY((launch_copy<float, float>(N, W32.v(hs.cur), G.v(0), st)));
+          HIP_TRY(hipStreamSynchronize(st));
+          W32.release();
+          for (int b = 0; b < 3; ++b) {
+            std::swap(W32.nnz[b].p, G.nnz[b].p);
+            std::swap(W32.idx[b].p, G.idx[b].p);
+            std::swap(W32.val[b].p, G.val[b].p);
+          }
+          W32.cap = newcap;
+        } else {
+          WorkSet<double> G;
+          HIP_TRY(G.alloc(N, newcap));
+          HIP_TRY((launch_copy<double, double>(N, W64.v(hs.cur), G.v(0), st)));
+          HIP_TRY(hipStreamSynchronize(st));
+          W64.release();
+          for (int b = 0; b < 3; ++b) {
+            std::swap(W64.nnz[b].p, G.nnz[b].p);
+            std::swap(W64.idx[b].p, G.idx[b].p);
+            std::swap(W64.val[b].p, G.val[b].p);
+          }
+          W64.cap = newcap;
+        }
+        hs.cur = 0;
+        hs.cap = newcap;
+        if ((rc = restart())) return rc;
+        continue;
+      }
+    }
+    if (hs.status == ST_FALLBACK) {
+      // the current X (span form) into ELLPACK working matrices of capacity SW
+      const int32_t c = std::min(std::max(32, roundup32(hs.phase32 ? S32.SW : S64.SW)), kMaxCap);
+      HIP_TRY(hipMemsetAsync(S.wmax.p, 0, sizeof(int32_t), st));
+      if (hs.phase32) {
+        HIP_TRY(W32.alloc(N, c));
+        HIP_TRY((launch_span_to_ell<float, float>(N, S32.v(hs.cur), W32.v(0), S.wmax.as<int32_t>(), st)));
+      } else {
+        HIP_TRY(W64.alloc(N, c));
+        HIP_TRY((launch_span_to_ell<double, double>(N, S64.v(hs.cur), W64.v(0), S.wmax.as<int32_t>(), st)));
+      }
+      int32_t w = 0;
+      HIP_TRY(hipMemcpyAsync(&w, S.wmax.p, sizeof(w), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (w > c) {
+        status = ELL_EOVERFLOW;
+        break;
+      }
+      S32.release();
+      S64.release();
+      pipe = PIPE_ELL;
       hs.cur = 0;
-      hs.stop = 0;
-      hs.status = ST_RUNNING;
-      hs.cap = hs.phase32 ? W32.cap : W64.cap;
-      HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+      hs.cap = c;
+      if ((rc = restart())) return rc;
       continue;
     }
     if (hs.status == ST_SWITCH) {
-      HIP_TRY(W64.alloc(N, W32.cap));
-      HIP_TRY((launch_copy<float, double>(N, W32.v(hs.cur), W64.v(0), st)));
-      HIP_TRY(hipStreamSynchronize(st));
-      W32.release();
+      if (pipe == PIPE_SPAN) {
+        HIP_TRY(S64.alloc(N, S32.SW));
+        HIP_TRY((launch_span_copy<float, double>(N, S32.v(hs.cur), S64.v(0), st)));
+        HIP_TRY(hipStreamSynchronize(st));
+        S32.release();
+        hs.sw = S64.SW;
+      } else {
+        HIP_TRY(W64.alloc(N, W32.cap));
+        HIP_TRY((launch_copy<float, double>(N, W32.v(hs.cur), W64.v(0), st)));
+        HIP_TRY(hipStreamSynchronize(st));
+        W32.release();
+        hs.cap = W64.cap;
+      }
       hs.cur = 0;
       hs.phase32 = 0;
-      hs.stop = 0;
-      hs.status = ST_RUNNING;
-      hs.cap = W64.cap;
-      HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
+      if ((rc = restart())) return rc;
       continue;
     }
     status = hs.status;
     break;
   }
-  HIP_TRY(hipEventRecord(t1, st));
+  HIP_TRY(S.mark(&t1));
 
   int32_t width = 0;
-  rc = hs.phase32 ? deliver<float>(S, W32, hs.cur, D, &width) : deliver<double>(S, W64, hs.cur, D, &width);
+  rc = hs.phase32 ? deliver<float>(S, pipe, S32, W32, hs.cur, D, &width)
+                  : deliver<double>(S, pipe, S64, W64, hs.cur, D, &width);
   const int final_status = rc ? rc : status;
   if (!r) return final_status;
 
   r->status = final_status;
   r->iterations = hs.iter;
-  r->final_M = hs.phase32 ? W32.cap : W64.cap;
+  r->final_M = pipe == PIPE_SPAN ? (hs.phase32 ? S32.SW : S64.SW) : (hs.phase32 ? W32.cap : W64.cap);
   if (rc == ELL_EOVERFLOW) r->final_M = width;
   r->eta = std::sqrt(hs.eta2);
   r->trace_x = hs.trx;
@@ -751,10 +1020,10 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     if (r->hist_prec) r->hist_prec[q] = pr[q];
     if (r->hist_maxw) r->hist_maxw[q] = mw[q];
   }
-  if (profile) {
+  if (S.profile) {
     double sec = 0.0;
     int launches = 0;
-    for (auto &m : marks) {
+    for (auto &m : S.marks) {
       if (!m.first) continue;
       float t = 0.f;
       HIP_TRY(hipEventElapsedTime(&t, m.first, m.second));

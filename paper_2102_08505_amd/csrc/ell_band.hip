@@ -1,0 +1,563 @@
+// Register-tiled X^2 for matrices whose rows are short column intervals
+// (banded Hamiltonians and the density matrices SP2 makes from them).
+//
+// Inside the SP2 loop a matrix is held in span form: row i is stored densely
+// over the columns [base[i], base[i] + len[i]) at val[i*SW ...], with zeros at
+// the pruned positions inside the interval.  Stored ELLPACK entries are never
+// exactly zero (they are kept only if |v| > tau >= 0), so the span form and the
+// ELLPACK form describe the same matrix and convert into each other exactly.
+//
+// One wavefront computes G = 8 consecutive output rows.  Lane l of chunk r owns
+// output column wlo + 64 r + l of all 8 rows, in registers acc[g][r].  For
+// every chunk r the wave walks k in ascending order over the rows k whose
+// interval meets the chunk, loads B = X[k][column] for its 64 columns with one
+// coalesced load, and applies acc[g][r] = fma(X[i_g][k], B, acc[g][r]) for the
+// 8 rows, the row value X[i_g][k] being the same for every lane (scalar
+// loads).  Absent entries enter as zeros and a zero product leaves the
+// accumulator unchanged, so every output entry is exactly the ascending-k
+// chain of fused multiply-adds over the entries that exist: the same bits as
+// the row-by-row sparse product.  A B load feeds 8 FMAs and no accumulator
+// touches memory until the row is complete.
+#include <climits>
+#include <cmath>
+
+#include "ell_internal.h"
+#include "../../include/ellsp2.h"
+
+namespace ellsp2 {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kG = 8;           // output rows per wave
+constexpr int kWavesPerBlock = 4;
+constexpr int kSB = 8;          // rows k per batch of B loads
+constexpr int kKQ = 4;          // rows k held in registers per group: 64 kKQ
+constexpr int kNormBlocks = 128;  // aligned 64-column blocks per row in the norm table
+constexpr int kMaxChunks = 64;    // widest output window: 64 chunks of 64 columns
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ void wave_sync()
+{
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ int wmin(int v)
+{
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ int wmax(int v)
+{
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_tree(double v)
+{
+  for (int s = 1; s < kWave; s <<= 1) v = v + __shfl_down(v, s, kWave);
+  return v;
+}
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double absv(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float absv(float a) { return __builtin_fabsf(a); }
+
+__device__ __forceinline__ int xcd_block(int b, int nblocks)
+{
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd;
+  const int full = per * kXcd;
+  if (b >= full) return b;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+// B operand of one batch: X[k][col] for k = kb .. kb + kSB - 1 (zero past khi
+// or outside row k's interval).  The intervals come from scalar loads of the
+// base/len arrays, which are padded past N (see SpanMem).
+template <typename T>
+__device__ __forceinline__ void load_b(const SpanView<T> &X, const T *__restrict__ xv, const int SW, const int kb,
+                                       const int khi, const int col, T (&out)[kSB])
+{
+  int kbase[kSB], klen[kSB];
+#pragma unroll
+  for (int u = 0; u < kSB; ++u) {
+    kbase[u] = X.base[kb + u];
+    klen[u] = kb + u <= khi ? X.len[kb + u] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kSB; ++u) {
+    const int off = col - kbase[u];
+    out[u] = ((unsigned)off < (unsigned)klen[u]) ? xv[(size_t)(kb + u) * SW + off] : T(0);
+  }
+}
+
+// Per-row running state of the sweep, one lane per row (lane g holds row g).
+__device__ __forceinline__ int row_get(int v, int g) { return __builtin_amdgcn_readlane(v, g); }
+__device__ __forceinline__ int row_set(int v, int g, int x) { return lane_id() == g ? x : v; }
+
+// One wave: output rows i0 .. i0 + nrows - 1, streamed 64 columns at a time.
+// For every aligned 64-column chunk of the output window: accumulate the chunk
+// of all 8 rows in registers (k ascending), then sweep it for each row --
+// threshold, compaction of X^2 and 2X - X^2 (ELLPACK and/or span form), and
+// the lane tree of the norm's squared differences for that aligned block.
+template <typename T, bool WITH_U, bool OUT_ELL, bool OUT_SPAN>
+__device__ void band_rows(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
+                          const SpanView<T> SU, const EllView<T> Y, const EllView<T> U, const T tau,
+                          const StepScratch &s, double *bsum, int32_t *fallback)
+{
+  const int lane = lane_id();
+  const T *__restrict__ xv = X.val;
+  const int SW = X.SW;
+
+  // the 8 rows' intervals (uniform)
+  int bs[kG], ln[kG];
+#pragma unroll
+  for (int g = 0; g < kG; ++g) {
+    const bool ok = g < nrows;
+    bs[g] = ok ? uni(X.base[i0 + g]) : 0;
+    ln[g] = ok ? uni(X.len[i0 + g]) : 0;
+  }
+  int kmin = INT_MAX, kmax = -1;
+#pragma unroll
+  for (int g = 0; g < kG; ++g)
+    if (ln[g] > 0) {
+      kmin = min(kmin, bs[g]);
+      kmax = max(kmax, bs[g] + ln[g] - 1);
+    }
+  if (kmax < 0) {
+    // every row of the group is empty: so are its rows of X^2 and 2X - X^2.
+    // (Handled first: no index arithmetic may start from kmin = INT_MAX.)
+    if (lane == 0) {
+      for (int g = 0; g < nrows; ++g) {
+        const int i = i0 + g;
+        if (OUT_ELL) Y.nnz[i] = 0;
+        if (OUT_ELL && WITH_U) U.nnz[i] = 0;
+        if (OUT_SPAN) {
+          SY.base[i] = 0;
+          SY.len[i] = 0;
+          if (WITH_U) {
+            SU.base[i] = 0;
+            SU.len[i] = 0;
+          }
+        }
+        s.wy[i] = 0;
+        s.wu[i] = 0;
+        if (s.ly) s.ly[i] = 0;
+        if (s.lu) s.lu[i] = 0;
+        s.d1[i] = 0.0;
+        s.d2[i] = 0.0;
+        s.e[i] = 0.0;
+      }
+    }
+    return;
+  }
+  // intervals of the rows k in [kmin, kmax], lane-distributed: k = kmin + 64 q + lane
+  int kbq[kKQ], klq[kKQ];
+#pragma unroll
+  for (int q = 0; q < kKQ; ++q) {
+    const int k = kmin + q * kWave + lane;
+    const bool ok = k <= kmax;
+    klq[q] = ok ? X.len[k] : 0;
+    kbq[q] = ok ? X.base[k] : 0;
+  }
+  const bool kfit = kmax - kmin < kKQ * kWave;  // every row k is in registers
+  // output window: every row k's interval and the rows' own intervals,
+  // widened to whole aligned 64-column blocks
+  int wlo = kmin, whi = kmax;
+  if (kfit) {
+#pragma unroll
+    for (int q = 0; q < kKQ; ++q)
+      if (klq[q] > 0) {
+        wlo = min(wlo, kbq[q]);
+        whi = max(whi, kbq[q] + klq[q] - 1);
+      }
+  } else {
+    for (int k0 = kmin; k0 <= kmax; k0 += kWave) {
+      const int k = k0 + lane;
+      if (k <= kmax) {
+        const int l = X.len[k];
+        if (l > 0) {
+          const int b = X.base[k];
+          wlo = min(wlo, b);
+          whi = max(whi, b + l - 1);
+        }
+      }
+    }
+  }
+  wlo = wmin(wlo) & ~63;
+  whi = wmax(whi);
+  const int nchunk = (whi - wlo + kWave) / kWave;
+  if (nchunk > kMaxChunks) {
+    if (lane == 0) atomicOr(fallback, 1);
+    return;
+  }
+  const int b0 = (wlo >> 6) & ~63;  // first block of the norm's 128-block table
+
+  // running state, lane g = row g
+  int st_cy = 0, st_cu = 0, st_yf = INT_MAX, st_yl = -1, st_uf = INT_MAX, st_ul = -1;
+  for (int r = lane; r < kG * kNormBlocks; r += kWave) bsum[r] = 0.0;
+
+  for (int r = 0; r < nchunk; ++r) {
+    const int c0 = wlo + r * kWave;  // first column of the chunk
+    const int col = c0 + lane;
+    // rows k whose interval meets the chunk: a conservative k range
+    int klo = INT_MAX, khi = -1;
+    if (kfit) {
+#pragma unroll
+      for (int q = 0; q < kKQ; ++q) {
+        const bool meet = klq[q] > 0 && kbq[q] <= c0 + kWave - 1 && kbq[q] + klq[q] - 1 >= c0;
+        const uint64_t m = __ballot(meet);
+        if (m) {
+          klo = min(klo, kmin + q * kWave + (int)__builtin_ctzll(m));
+          khi = max(khi, kmin + q * kWave + 63 - (int)__builtin_clzll(m));
+        }
+      }
+    } else {
+      for (int k0 = kmin; k0 <= kmax; k0 += kWave) {
+        const int k = k0 + lane;
+        bool meet = false;
+        if (k <= kmax) {
+          const int l = X.len[k];
+          const int b = X.base[k];
+          meet = l > 0 && b <= c0 + kWave - 1 && b + l - 1 >= c0;
+        }
+        const uint64_t m = __ballot(meet);
+        if (m) {
+          klo = min(klo, k0 + (int)__builtin_ctzll(m));
+          khi = max(khi, k0 + 63 - (int)__builtin_clzll(m));
+        }
+      }
+    }
+    T acc[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) acc[g] = T(0);
+    if (khi >= klo) {
+      // B = X[k][column], kSB rows k at a time, the next batch loaded before the
+      // current one is used; rows k past khi read as zero
+      T bcur[kSB];
+      load_b<T>(X, xv, SW, klo, khi, col, bcur);
+      for (int kb = klo; kb <= khi; kb += kSB) {
+        T bnext[kSB];
+        const bool more = kb + kSB <= khi;
+        if (more) load_b<T>(X, xv, SW, kb + kSB, khi, col, bnext);
+        // A = X[i_g][kb + u], the same for every lane: one scalar load of kSB
+        // consecutive values per row whose interval meets the batch (addresses
+        // stay inside the guard band around the span buffer), masked where the
+        // batch sticks out of the interval
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+          const int o = kb - bs[g];
+          if (o + kSB <= 0 || o >= ln[g]) continue;
+          const T *pa = xv + (ptrdiff_t)(i0 + g) * SW + o;
+          T av[kSB];
+#pragma unroll
+          for (int u = 0; u < kSB; ++u) av[u] = pa[u];
+          if (o < 0 || o + kSB > ln[g]) {
+#pragma unroll
+            for (int u = 0; u < kSB; ++u) av[u] = ((unsigned)(o + u) < (unsigned)ln[g]) ? av[u] : T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < kSB; ++u) acc[g] = fmadd(av[u], bcur[u], acc[g]);
+        }
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < kSB; ++u) bcur[u] = bnext[u];
+        }
+      }
+    }
+    // sweep the chunk for every row
+    const int rel = (c0 >> 6) - b0;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      if (g >= nrows) break;
+      const int i = i0 + g;
+      const T y = acc[g];
+      const int ox = col - bs[g];
+      const T x = (unsigned)ox < (unsigned)ln[g] ? xv[(size_t)i * SW + ox] : T(0);
+      if (col == i) {  // X_ii and the unpruned (X.X)_ii
+        s.d1[i] = (double)x;
+        s.d2[i] = (double)y;
+      }
+      const bool ky = absv(y) > tau;
+      const T yk = ky ? y : T(0);
+      const uint64_t my = __ballot(ky);
+      int cy = row_get(st_cy, g);
+      if (OUT_ELL && ky) {
+        const int pos = cy + lanes_below(my);
+        if (pos < Y.M) {
+          Y.idx[(size_t)i * Y.M + pos] = col;
+          Y.val[(size_t)i * Y.M + pos] = y;
+        }
+      }
+      st_cy = row_set(st_cy, g, cy + __popcll(my));
+      int yf = row_get(st_yf, g);
+      if (my) {
+        yf = min(yf, c0 + (int)__builtin_ctzll(my));
+        st_yf = row_set(st_yf, g, yf);
+        st_yl = row_set(st_yl, g, c0 + 63 - (int)__builtin_clzll(my));
+      }
+      if (OUT_SPAN && yf != INT_MAX) {
+        const int o = col - yf;
+        if ((unsigned)o < (unsigned)SY.SW) SY.val[(size_t)i * SY.SW + o] = yk;
+      }
+      if (WITH_U) {
+        const T v = T(2) * x - yk;
+        const bool ku = absv(v) > tau;
+        const uint64_t mu = __ballot(ku);
+        const int cu = row_get(st_cu, g);
+        if (OUT_ELL && ku) {
+          const int pos = cu + lanes_below(mu);
+          if (pos < U.M) {
+            U.idx[(size_t)i * U.M + pos] = col;
+            U.val[(size_t)i * U.M + pos] = v;
+          }
+        }
+        st_cu = row_set(st_cu, g, cu + __popcll(mu));
+        int uf = row_get(st_uf, g);
+        if (mu) {
+          uf = min(uf, c0 + (int)__builtin_ctzll(mu));
+          st_uf = row_set(st_uf, g, uf);
+          st_ul = row_set(st_ul, g, c0 + 63 - (int)__builtin_clzll(mu));
+        }
+        if (OUT_SPAN && uf != INT_MAX) {
+          const int o = col - uf;
+          if ((unsigned)o < (unsigned)SU.SW) SU.val[(size_t)i * SU.SW + o] = ku ? v : T(0);
+        }
+      }
+      const double dd = (double)yk - (double)x;
+      const double t = wave_tree(dd * dd);
+      if (lane == 0 && rel < kNormBlocks) bsum[g * kNormBlocks + rel] = t;
+    }
+  }
+
+  // finish every row
+  wave_sync();
+#pragma unroll 1
+  for (int g = 0; g < nrows; ++g) {
+    const int i = i0 + g;
+    // norm row term: blocks b0 .. b0 + 127 form two perfect 64-block subtrees
+    const double g0 = wave_tree(bsum[g * kNormBlocks + lane]);
+    const double g1 = wave_tree(bsum[g * kNormBlocks + kWave + lane]);
+    const int cy = row_get(st_cy, g), cu = row_get(st_cu, g);
+    const int yf = row_get(st_yf, g), yl = row_get(st_yl, g);
+    const int uf = row_get(st_uf, g), ul = row_get(st_ul, g);
+    const int ylen = yl >= 0 ? yl - yf + 1 : 0;
+    const int ulen = ul >= 0 ? ul - uf + 1 : 0;
+    if (lane == 0) {
+      if (OUT_ELL) Y.nnz[i] = min(cy, Y.M);
+      if (OUT_ELL && WITH_U) U.nnz[i] = min(cu, U.M);
+      if (OUT_SPAN) {
+        SY.base[i] = ylen ? yf : 0;
+        SY.len[i] = ylen;
+        if (WITH_U) {
+          SU.base[i] = ulen ? uf : 0;
+          SU.len[i] = ulen;
+        }
+      }
+      s.wy[i] = cy;
+      s.wu[i] = WITH_U ? cu : 0;
+      if (s.ly) s.ly[i] = ylen;
+      if (s.lu) s.lu[i] = WITH_U ? ulen : 0;
+      s.e[i] = g0 + g1;
+      if (i < wlo || i >= wlo + nchunk * kWave) {  // column i never swept
+        s.d1[i] = 0.0;
+        s.d2[i] = 0.0;
+      }
+    }
+  }
+}
+
+template <typename T, bool WITH_U, bool OUT_ELL, bool OUT_SPAN>
+__global__ __launch_bounds__(256) void k_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State *st,
+                                                 T tau, StepScratch s, int32_t *fallback)
+{
+  __shared__ double bsum_s[kWavesPerBlock][kG * kNormBlocks];
+  int cur = 0;
+  if (st) {
+    if (st->stop) return;
+    cur = st->cur;
+  }
+  const int w = uni(threadIdx.x >> 6);
+  const int grp = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  const int i0 = grp * kG;
+  if (i0 >= N) return;
+  const int nrows = min(kG, N - i0);
+  const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
+  band_rows<T, WITH_U, OUT_ELL, OUT_SPAN>(N, i0, nrows, spans.b[cur], spans.b[cy], spans.b[cu], ells.b[cy],
+                                          ells.b[cu], tau, s, bsum_s[w], fallback);
+}
+
+// ---- conversions between ELLPACK and span form -----------------------------------------
+
+// Interval length of every row of an ELLPACK matrix, and a flag if any stored
+// value is exactly zero (the span form cannot represent it).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags)
+{
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int n = A.nnz[i];
+  int l = 0;
+  if (n > 0) l = A.idx[(size_t)i * A.M + n - 1] - A.idx[(size_t)i * A.M] + 1;
+  len[i] = l;
+  bool zero = false;
+  for (int q = 0; q < n; ++q) zero |= A.val[(size_t)i * A.M + q] == T(0);
+  if (zero) atomicOr(flags, 4);
+}
+
+// ELLPACK -> span form, one wave per row: positions not stored are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanView<T> S)
+{
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kWavesPerBlock + w;
+  if (i >= N) return;
+  const int lane = lane_id();
+  const int n = A.nnz[i];
+  const int32_t *ci = A.idx + (size_t)i * A.M;
+  const T *vi = A.val + (size_t)i * A.M;
+  const int b = n > 0 ? ci[0] : 0;
+  const int l = n > 0 ? ci[n - 1] - b + 1 : 0;
+  // each lane fills its positions by a binary search in the sorted row
+  for (int p = lane; p < l; p += kWave) {
+    const int j = b + p;
+    int lo = 0, hi = n - 1;
+    T v = T(0);
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int c = ci[mid];
+      if (c == j) {
+        v = vi[mid];
+        break;
+      }
+      if (c < j) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    S.val[(size_t)i * S.SW + p] = v;
+  }
+  if (lane == 0) {
+    S.base[i] = b;
+    S.len[i] = l;
+  }
+}
+
+// span form -> ELLPACK (nonzero positions, ascending), one wave per row.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax)
+{
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kWavesPerBlock + w;
+  if (i >= N) return;
+  const int lane = lane_id();
+  const int b = S.base[i], l = S.len[i];
+  int c = 0;
+  for (int p0 = 0; p0 < l; p0 += kWave) {
+    const int p = p0 + lane;
+    const TS v = p < l ? S.val[(size_t)i * S.SW + p] : TS(0);
+    const bool keep = v != TS(0);
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int pos = c + lanes_below(m);
+      if (pos < A.M) {
+        A.idx[(size_t)i * A.M + pos] = b + p;
+        A.val[(size_t)i * A.M + pos] = (TD)v;
+      }
+    }
+    c += __popcll(m);
+  }
+  if (lane == 0) {
+    A.nnz[i] = min(c, A.M);
+    if (wmax) atomicMax(wmax, c);
+  }
+}
+
+// span copy between strides and precisions (float -> double is exact)
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_span_copy(int N, SpanView<TS> S, SpanView<TD> D)
+{
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * kWavesPerBlock + w;
+  if (i >= N) return;
+  const int l = S.len[i];
+  for (int p = lane_id(); p < l; p += kWave) D.val[(size_t)i * D.SW + p] = (TD)S.val[(size_t)i * S.SW + p];
+  if (lane_id() == 0) {
+    D.base[i] = S.base[i];
+    D.len[i] = l;
+  }
+}
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State *st, bool with_u, bool out_ell,
+                          T tau, const StepScratch &s, int32_t *fallback, hipStream_t stream)
+{
+  const int groups = (N + kG - 1) / kG;
+  const dim3 grid((groups + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
+  if (out_ell) {
+    if (with_u)
+      hipLaunchKernelGGL((k_x2_band<T, true, true, false>), grid, block, 0, stream, N, spans, ells, st, tau, s,
+                         fallback);
+    else
+      hipLaunchKernelGGL((k_x2_band<T, false, true, false>), grid, block, 0, stream, N, spans, ells, st, tau, s,
+                         fallback);
+  } else {
+    hipLaunchKernelGGL((k_x2_band<T, true, false, true>), grid, block, 0, stream, N, spans, ells, st, tau, s,
+                       fallback);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_x2_band<double>(int, SpanRot3<double>, Rot3<double>, const SP2State *, bool, bool,
+                                           double, const StepScratch &, int32_t *, hipStream_t);
+template hipError_t launch_x2_band<float>(int, SpanRot3<float>, Rot3<float>, const SP2State *, bool, bool, float,
+                                          const StepScratch &, int32_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_ell_extent<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, len, flags);
+  return hipGetLastError();
+}
+template hipError_t launch_ell_extent<double>(int, EllView<double>, int32_t *, int32_t *, hipStream_t);
+template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int32_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_ell_to_span<T>), dim3((N + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream, N,
+                     A, S);
+  return hipGetLastError();
+}
+template hipError_t launch_ell_to_span<double>(int, EllView<double>, SpanView<double>, hipStream_t);
+template hipError_t launch_ell_to_span<float>(int, EllView<float>, SpanView<float>, hipStream_t);
+
+template <typename TS, typename TD>
+hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_span_to_ell<TS, TD>), dim3((N + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream,
+                     N, S, A, wmax);
+  return hipGetLastError();
+}
+template hipError_t launch_span_to_ell<double, double>(int, SpanView<double>, EllView<double>, int32_t *,
+                                                       hipStream_t);
+template hipError_t launch_span_to_ell<float, double>(int, SpanView<float>, EllView<double>, int32_t *,
+                                                      hipStream_t);
+template hipError_t launch_span_to_ell<float, float>(int, SpanView<float>, EllView<float>, int32_t *, hipStream_t);
+
+template <typename TS, typename TD>
+hipError_t launch_span_copy(int N, SpanView<TS> S, SpanView<TD> D, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_span_copy<TS, TD>), dim3((N + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream, N,
+                     S, D);
+  return hipGetLastError();
+}
+template hipError_t launch_span_copy<double, double>(int, SpanView<double>, SpanView<double>, hipStream_t);
+template hipError_t launch_span_copy<float, float>(int, SpanView<float>, SpanView<float>, hipStream_t);
+template hipError_t launch_span_copy<float, double>(int, SpanView<float>, SpanView<double>, hipStream_t);
+
+}  // namespace ellsp2

@@ -23,6 +23,25 @@ struct Rot3 {
   EllView<T> b[3];
 };
 
+// Span form: row i stored densely over columns [base[i], base[i] + len[i]) at
+// val[i*SW ...] (zeros at pruned positions).  val points kSpanGuard elements
+// into its allocation, which has kSpanGuard spare elements at both ends.
+template <typename T>
+struct SpanView {
+  T *val;
+  int32_t *base;
+  int32_t *len;
+  int32_t SW;
+};
+
+template <typename T>
+struct SpanRot3 {
+  SpanView<T> b[3];
+};
+
+constexpr int kSpanGuard = 1024;  // elements; larger than any window the band kernel reads across
+constexpr int kSpanPadRows = 64;  // base/len entries past N (zero): batched loads may run past the last row
+
 // Internal status values beyond the public ELL_* codes.
 enum { ST_RUNNING = 1, ST_SWITCH = 2 };
 
@@ -37,15 +56,20 @@ struct SP2State {
   int32_t fp64_updates; // FP64-phase updates applied
   int32_t phase_start;  // iteration index where the current phase began
   int32_t need_width;   // on overflow: the width required
-  int32_t cap;          // capacity M of the working matrices
+  int32_t cap;          // capacity M of the working matrices (ELLPACK pipeline)
+  int32_t sw;           // row stride SW of the working matrices (span pipeline)
   int32_t wy_max, wu_max;
-  int32_t pad;
+  int64_t nnz_cur;      // stored entries of the current X
   double trx, trx2, eta2;
 };
+
+enum { ST_FALLBACK = 3 };  // span pipeline cannot take a row group: continue on ELLPACK
 
 struct SP2Cfg {
   double n_occ, target2, switch2;
   int32_t max_iter, tail, stall, mixed;
+  int32_t span;  // 1: working matrices are in span form (capacity = SW, not M)
+  int32_t pad;
 };
 
 struct SP2Hist {
@@ -59,12 +83,14 @@ struct SP2Hist {
 struct StepScratch {
   double *d1, *d2, *e;      // N
   int32_t *wy, *wu;         // N: true survivor counts (may exceed capacity)
+  int32_t *ly, *lu;         // N: interval lengths of X2 and U rows (span pipeline), or NULL
   double *part;             // 3 * nb partial sums
-  int32_t *partw;           // 2 * nb partial maxima
-  int64_t *partn;           // 2 * nb partial nnz totals
+  int32_t *partw;           // 4 * nb partial maxima (wy, wu, ly, lu)
+  int64_t *partn;           // 2 * nb partial nnz totals (X2, U)
   double *out;              // 3: TrX, TrX2, eta2
-  int32_t *outw;            // 2: widest X2 row, widest U row
-  int64_t *outn;            // 2: nnz(X), nnz(X2)
+  int32_t *outw;            // 4: widest X2 row, widest U row, longest X2 / U interval
+  int64_t *outn;            // 2: nnz(X2), nnz(U)
+  int32_t *flags;           // bit 0: a row group needs the ELLPACK pipeline
   int32_t nb;               // number of 1024-row reduction blocks
 };
 
@@ -73,13 +99,16 @@ constexpr int kMaxFinal = 1024;  // partials the final reduction handles in one 
 constexpr int kMaxCap = 4096;    // largest supported capacity M
 constexpr int kMaxN = kRedBlock * kMaxFinal;  // two reduction levels cover every row
 
+// Record a failed HIP call as the library's last device error; returns the
+// matching ELL_* status (ELL_ENOMEM for out-of-memory, else ELL_EDEVICE).
+int device_error(hipError_t e, const char *what);
+void set_device_error(const char *what);
+
 // ---- launchers (ell_kernels.hip) ---------------------------------------------------
 template <typename T>
 hipError_t launch_x2_step(int N, Rot3<T> bufs, const SP2State *st, bool with_u, T tau,
                           const StepScratch &s, hipStream_t stream);
-hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream,
-                         const int32_t *nnzx_rows, const int32_t *nnzy_rows_a,
-                         const int32_t *nnzy_rows_b);
+hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream);
 hipError_t launch_decide(SP2State *st, SP2Cfg cfg, SP2Hist hist, const StepScratch &s,
                          hipStream_t stream);
 hipError_t launch_final_only(const StepScratch &s, hipStream_t stream);
@@ -88,7 +117,7 @@ hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *ro
                              double *emin_emax, int32_t *flags, hipStream_t stream);
 template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau,
-                     int32_t *wmax, hipStream_t stream);
+                     int32_t *wmax, unsigned long long *total, hipStream_t stream);
 template <typename TS, typename TD>
 hipError_t launch_copy(int N, EllView<TS> src, EllView<TD> dst, hipStream_t stream);
 template <typename T>
@@ -96,5 +125,18 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
 hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hipStream_t stream);
+
+// ---- span pipeline (ell_band.hip) ------------------------------------------------------
+template <typename T>
+hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State *st, bool with_u, bool out_ell,
+                          T tau, const StepScratch &s, int32_t *fallback, hipStream_t stream);
+template <typename T>
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream);
+template <typename T>
+hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
+template <typename TS, typename TD>
+hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream);
+template <typename TS, typename TD>
+hipError_t launch_span_copy(int N, SpanView<TS> S, SpanView<TD> D, hipStream_t stream);
 
 }  // namespace ellsp2

@@ -31,8 +31,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kWin = 512;        // accumulator window per wave (entries)
-constexpr int kRing = 128;       // two 64-entry blocks of squared differences
-constexpr int kMaxBlocks = 128;  // 64-entry blocks of one row's union list
+constexpr int kMaxBlocks = 192;  // aligned 64-column blocks of one row's window (three groups of 64)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -89,36 +88,219 @@ __device__ double block_tree_1024(double a0, double a1, double a2, double a3, do
 // --------------------------------------------------------------------------
 // the fused X^2 / trace / norm / update row kernel
 // --------------------------------------------------------------------------
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float rdlane(float v, int l)
+{
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l)
+{
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+constexpr int kRowChunks = 4;  // row i held in registers when it has <= 256 entries
+constexpr int kBatch = 8;      // rows k whose entries are loaded before their updates
+
+// Running state of the ascending sweep over one output row.
+struct SweepState {
+  int cy, cu, nu;  // kept X^2 entries, kept 2X - X^2 entries, nonzero: window too wide
+};
+
+// Sweep one accumulator window in ascending column order (the window starts
+// on a multiple of 64 columns): compact the kept entries of X^2 (and of
+// 2X - X^2), and reduce each aligned 64-column block of the norm's squared
+// differences by the lane tree into bsum[block - b0].
+template <typename T, bool WITH_U>
+__device__ __forceinline__ void sweep_window(const int i, const int wlo, const int wlen, const T tau,
+                                             const T *acc, const T *xw, const int b0, double *bsum,
+                                             const EllView<T> &Y, const EllView<T> &U, SweepState &st)
+{
+  const int lane = lane_id();
+  for (int q0 = 0; q0 < wlen; q0 += kWave) {
+    const int p = q0 + lane;
+    const bool in = p < wlen;
+    const int j = wlo + p;
+    const T y = in ? acc[p] : T(0);
+    const bool ky = in && absv(y) > tau;
+    const T x = in ? xw[p] : T(0);
+    const uint64_t my = __ballot(ky);
+    if (ky) {
+      const int pos = st.cy + lanes_below(my);
+      if (pos < Y.M) {
+        Y.idx[(size_t)i * Y.M + pos] = j;
+        Y.val[(size_t)i * Y.M + pos] = y;
+      }
+    }
+    st.cy += __popcll(my);
+    const T yk = ky ? y : T(0);
+    if (WITH_U) {
+      const T v = T(2) * x - yk;
+      const bool ku = in && absv(v) > tau;
+      const uint64_t mu = __ballot(ku);
+      if (ku) {
+        const int pos = st.cu + lanes_below(mu);
+        if (pos < U.M) {
+          U.idx[(size_t)i * U.M + pos] = j;
+          U.val[(size_t)i * U.M + pos] = v;
+        }
+      }
+      st.cu += __popcll(mu);
+    }
+    const double dd = (double)yk - (double)x;
+    const double t = wave_tree(dd * dd);
+    const int rel = ((wlo + q0) >> 6) - b0;
+    if (lane == 0) {
+      if (rel < kMaxBlocks) bsum[rel] = t;
+      else st.nu = 1;  // window wider than the block table
+    }
+  }
+}
+
+// Norm row term from the block sums: bsum[r] is the aligned 64-column block
+// b0 + r (b0 a multiple of 64), so each 64-entry group of the table is a
+// perfect subtree; the (at most three) group totals meet in the tree over
+// absolute group positions.  Valid in every lane.
+__device__ __forceinline__ double finish_norm(const int b0, const double *bsum, const bool too_wide)
+{
+  const int lane = lane_id();
+  wave_sync();
+  const double g0 = __shfl(wave_tree(bsum[lane]), 0, kWave);
+  const double g1 = __shfl(wave_tree(bsum[kWave + lane]), 0, kWave);
+  const double g2 = __shfl(wave_tree(bsum[2 * kWave + lane]), 0, kWave);
+  if (too_wide) return __builtin_nan("");
+  const int G = b0 >> 6;
+  return (G & 1) ? g0 + (g1 + g2) : (g0 + g1) + g2;
+}
+
+// Accumulate the products of rows k = row i's columns into the window
+// [wlo, wlo + wlen): k ascending, the lanes over row k's entries.  Row i
+// (columns kk, values aa, widths nkk) is held in registers, lane s of chunk c
+// holding entry 64c + s; the entries of kBatch consecutive rows k are loaded
+// before any of their updates, and the updates are applied in k order.
+template <typename T>
+__device__ __forceinline__ void accumulate_window(const int wi, const int wlo, const int wlen,
+                                                  const int32_t *__restrict__ xidx,
+                                                  const T *__restrict__ xval, const int M,
+                                                  const int (&kk)[kRowChunks], const T (&aa)[kRowChunks],
+                                                  const int (&nkk)[kRowChunks], T *acc)
+{
+  const int lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < kRowChunks; ++c) {
+    const int sbeg = c * kWave;
+    if (sbeg >= wi) break;
+    const int send = min(wi, sbeg + kWave);
+    for (int s0 = sbeg; s0 < send; s0 += kBatch) {
+      int kb[kBatch], nb[kBatch];
+      T ab[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int s = s0 + u;
+        const bool ok = s < send;
+        kb[u] = ok ? rdlane(kk[c], s & 63) : 0;
+        ab[u] = ok ? rdlane(aa[c], s & 63) : T(0);
+        nb[u] = ok ? rdlane(nkk[c], s & 63) : 0;
+      }
+      int jj[kBatch][2];
+      T vv[kBatch][2];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int32_t *ck = xidx + (size_t)kb[u] * M;
+        const T *vk = xval + (size_t)kb[u] * M;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int t = lane + h * kWave;
+          const bool ok = t < nb[u];
+          jj[u][h] = ok ? ck[t] : -1;
+          vv[u][h] = ok ? vk[t] : T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int p = jj[u][h] - wlo;
+          if ((unsigned)p < (unsigned)wlen) acc[p] = fmadd(ab[u], vv[u][h], acc[p]);
+        }
+        if (nb[u] > 2 * kWave) {  // rows k wider than 128: the rest, still before row k+1
+          const int32_t *ck = xidx + (size_t)kb[u] * M;
+          const T *vk = xval + (size_t)kb[u] * M;
+          for (int t = lane + 2 * kWave; t < nb[u]; t += kWave) {
+            const int p = ck[t] - wlo;
+            if ((unsigned)p < (unsigned)wlen) acc[p] = fmadd(ab[u], vk[t], acc[p]);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename T, bool WITH_U>
 __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int32_t *__restrict__ xidx,
                        const T *__restrict__ xval, const int M, EllView<T> Y, EllView<T> U, const T tau,
-                       T *acc, T *xw, uint8_t *xp, double *ring, double *bsum, const StepScratch &s)
+                       T *acc, T *xw, double *bsum, const StepScratch &s)
 {
   const int lane = lane_id();
   const int wi = uniform_i(xnnz[i]);
   const int32_t *ci = xidx + (size_t)i * M;
   const T *vi = xval + (size_t)i * M;
+  const bool regs = wi <= kWave * kRowChunks;
 
-  // window bounds and the diagonal entry X_ii
+  // row i into registers (when it fits), the window bounds and X_ii
+  int kk[kRowChunks], nkk[kRowChunks];
+  T aa[kRowChunks];
+#pragma unroll
+  for (int c = 0; c < kRowChunks; ++c) {
+    const int sl = c * kWave + lane;
+    const bool ok = regs && sl < wi;
+    kk[c] = ok ? ci[sl] : 0;
+    aa[c] = ok ? vi[sl] : T(0);
+  }
+#pragma unroll
+  for (int c = 0; c < kRowChunks; ++c) nkk[c] = (regs && c * kWave + lane < wi) ? xnnz[kk[c]] : 0;
   int lo = INT_MAX, hi = -1;
   double d1 = 0.0;
   bool has_diag = false;
-  for (int s0 = 0; s0 < wi; s0 += kWave) {
-    const int sl = s0 + lane;
-    if (sl < wi) {
-      const int k = ci[sl];
-      const int nk = xnnz[k];
-      int f = k, l = k;
-      if (nk > 0) {
-        const int32_t *ck = xidx + (size_t)k * M;
-        f = min(f, ck[0]);
-        l = max(l, ck[nk - 1]);
+  if (regs) {
+#pragma unroll
+    for (int c = 0; c < kRowChunks; ++c) {
+      if (c * kWave + lane < wi) {
+        const int k = kk[c];
+        int f = k, l = k;
+        if (nkk[c] > 0) {
+          const int32_t *ck = xidx + (size_t)k * M;
+          f = min(f, ck[0]);
+          l = max(l, ck[nkk[c] - 1]);
+        }
+        lo = min(lo, f);
+        hi = max(hi, l);
+        if (k == i) {
+          has_diag = true;
+          d1 = (double)aa[c];
+        }
       }
-      lo = min(lo, f);
-      hi = max(hi, l);
-      if (k == i) {
-        has_diag = true;
-        d1 = (double)vi[sl];
+    }
+  } else {
+    for (int s0 = 0; s0 < wi; s0 += kWave) {
+      const int sl = s0 + lane;
+      if (sl < wi) {
+        const int k = ci[sl];
+        const int nk = xnnz[k];
+        int f = k, l = k;
+        if (nk > 0) {
+          const int32_t *ck = xidx + (size_t)k * M;
+          f = min(f, ck[0]);
+          l = max(l, ck[nk - 1]);
+        }
+        lo = min(lo, f);
+        hi = max(hi, l);
+        if (k == i) {
+          has_diag = true;
+          d1 = (double)vi[sl];
+        }
       }
     }
   }
@@ -127,111 +309,54 @@ __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int3
   const uint64_t dm = __ballot(has_diag);
   if (dm) d1 = __shfl(d1, __builtin_ctzll(dm), kWave);
 
-  int cy = 0, cu = 0, nu = 0;
+  SweepState st{0, 0, 0};
   double d2 = 0.0;
-  for (int wlo = lo; wlo <= hi; wlo += kWin) {
+  // windows start on multiples of 64 columns, so every 64-wide step of the
+  // sweep is one aligned block of the norm's column tree
+  const int lo_al = lo == INT_MAX ? lo : (lo & ~63);
+  const int b0 = lo == INT_MAX ? 0 : ((lo_al >> 6) & ~63);
+  for (int r = lane; r < kMaxBlocks; r += kWave) bsum[r] = 0.0;
+  for (int wlo = lo_al; wlo <= hi; wlo += kWin) {
     const int wlen = min(kWin, hi - wlo + 1);
     for (int p = lane; p < wlen; p += kWave) {
       acc[p] = T(0);
-      xp[p] = 0;
+      xw[p] = T(0);
     }
+    wave_sync();
     for (int s0 = 0; s0 < wi; s0 += kWave) {
       const int sl = s0 + lane;
       if (sl < wi) {
         const int p = ci[sl] - wlo;
-        if ((unsigned)p < (unsigned)wlen) {
-          xw[p] = vi[sl];
-          xp[p] = 1;
-        }
+        if ((unsigned)p < (unsigned)wlen) xw[p] = vi[sl];
       }
     }
     wave_sync();
-    // Gustavson: k ascending over row i, the lanes over row k
-    for (int sk = 0; sk < wi; ++sk) {
-      const int k = uniform_i(ci[sk]);
-      const T a = vi[sk];
-      const int nk = uniform_i(xnnz[k]);
-      const int32_t *ck = xidx + (size_t)k * M;
-      const T *vk = xval + (size_t)k * M;
-      for (int t = lane; t < nk; t += kWave) {
-        const int p = ck[t] - wlo;
-        if ((unsigned)p < (unsigned)wlen) acc[p] = fmadd(a, vk[t], acc[p]);
+    if (regs) {
+      accumulate_window<T>(wi, wlo, wlen, xidx, xval, M, kk, aa, nkk, acc);
+    } else {
+      for (int sk = 0; sk < wi; ++sk) {
+        const int k = uniform_i(ci[sk]);
+        const T a = vi[sk];
+        const int nk = uniform_i(xnnz[k]);
+        const int32_t *ck = xidx + (size_t)k * M;
+        const T *vk = xval + (size_t)k * M;
+        for (int t = lane; t < nk; t += kWave) {
+          const int p = ck[t] - wlo;
+          if ((unsigned)p < (unsigned)wlen) acc[p] = fmadd(a, vk[t], acc[p]);
+        }
       }
     }
     wave_sync();
     if (i >= wlo && i < wlo + wlen) d2 = (double)acc[i - wlo];
-    // ascending sweep: compaction of X^2 and 2X - X^2, squared differences
-    for (int q0 = 0; q0 < wlen; q0 += kWave) {
-      const int p = q0 + lane;
-      const bool in = p < wlen;
-      const int j = wlo + p;
-      const T y = in ? acc[p] : T(0);
-      const bool ky = in && absv(y) > tau;
-      const bool hx = in && xp[p] != 0;
-      const T x = hx ? xw[p] : T(0);
-      const uint64_t my = __ballot(ky);
-      if (ky) {
-        const int pos = cy + lanes_below(my);
-        if (pos < Y.M) {
-          Y.idx[(size_t)i * Y.M + pos] = j;
-          Y.val[(size_t)i * Y.M + pos] = y;
-        }
-      }
-      cy += __popcll(my);
-      const T yk = ky ? y : T(0);
-      if (WITH_U) {
-        const T v = T(2) * x - yk;
-        const bool ku = in && absv(v) > tau;
-        const uint64_t mu = __ballot(ku);
-        if (ku) {
-          const int pos = cu + lanes_below(mu);
-          if (pos < U.M) {
-            U.idx[(size_t)i * U.M + pos] = j;
-            U.val[(size_t)i * U.M + pos] = v;
-          }
-        }
-        cu += __popcll(mu);
-      }
-      const bool un = ky || hx;
-      const uint64_t mn = __ballot(un);
-      if (un) {
-        const double dd = (double)yk - (double)x;
-        ring[(nu + lanes_below(mn)) & (kRing - 1)] = dd * dd;
-      }
-      const int nu_next = nu + __popcll(mn);
-      if ((nu_next >> 6) != (nu >> 6)) {
-        wave_sync();
-        const int b = nu >> 6;
-        const double t = wave_tree(ring[((b & 1) << 6) + lane]);
-        if (lane == 0 && b < kMaxBlocks) bsum[b] = t;
-      }
-      nu = nu_next;
-    }
+    sweep_window<T, WITH_U>(i, wlo, wlen, tau, acc, xw, b0, bsum, Y, U, st);
   }
-  // the last, partial block of the union list, then the tree over block sums
-  wave_sync();
-  if (nu & 63) {
-    const int b = nu >> 6;
-    const double v = lane < (nu & 63) ? ring[((b & 1) << 6) + lane] : -0.0;
-    const double t = wave_tree(v);
-    if (lane == 0 && b < kMaxBlocks) bsum[b] = t;
-  }
-  wave_sync();
-  const int nb = (nu + 63) >> 6;
-  double ev = 0.0;
-  if (nb > kMaxBlocks) {
-    ev = __builtin_nan("");  // row wider than the supported union length
-  } else if (nb > 0) {
-    const double v0 = wave_tree(lane < nb ? bsum[lane] : -0.0);
-    const double v1 = wave_tree(lane + kWave < nb ? bsum[lane + kWave] : -0.0);
-    ev = nb > kWave ? v0 + v1 : v0;
-  }
+  const double ev = finish_norm(b0, bsum, st.nu != 0);
   if (lane == 0) {
-    Y.nnz[i] = min(cy, Y.M);
-    s.wy[i] = cy;
+    Y.nnz[i] = min(st.cy, Y.M);
+    s.wy[i] = st.cy;
     if (WITH_U) {
-      U.nnz[i] = min(cu, U.M);
-      s.wu[i] = cu;
+      U.nnz[i] = min(st.cu, U.M);
+      s.wu[i] = st.cu;
     } else {
       s.wu[i] = 0;
     }
@@ -241,14 +366,23 @@ __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int3
   }
 }
 
+// Block b runs on XCD b % 8; give each XCD a contiguous range of row groups so
+// that the rows k its waves share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks)
+{
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd;            // full share of every XCD
+  const int full = per * kXcd;
+  if (b >= full) return b;                   // the tail keeps its order
+  return (b % kXcd) * per + b / kXcd;
+}
+
 template <typename T, bool WITH_U>
 __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2State *st, T tau,
                                                  StepScratch s)
 {
   __shared__ T acc_s[kWavesPerBlock][kWin];
   __shared__ T xw_s[kWavesPerBlock][kWin];
-  __shared__ uint8_t xp_s[kWavesPerBlock][kWin];
-  __shared__ double ring_s[kWavesPerBlock][kRing];
   __shared__ double bsum_s[kWavesPerBlock][kMaxBlocks];
   int cur = 0;
   if (st) {
@@ -256,35 +390,27 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
     cur = st->cur;
   }
   const int w = uniform_i(threadIdx.x >> 6);
-  const int i = blockIdx.x * kWavesPerBlock + w;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
   if (i >= N) return;
   const EllView<T> X = bufs.b[cur];
   const EllView<T> Y = bufs.b[cur == 2 ? 0 : cur + 1];
   const EllView<T> U = bufs.b[cur == 0 ? 2 : cur - 1];
-  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, acc_s[w], xw_s[w], xp_s[w], ring_s[w],
-                    bsum_s[w], s);
+  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, acc_s[w], xw_s[w], bsum_s[w], s);
 }
 
 // --------------------------------------------------------------------------
 // deterministic reductions of the step outputs
 // --------------------------------------------------------------------------
-struct Nnz3 {
-  const int32_t *p[3];
-};
-
-__global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st, StepScratch s, Nnz3 nz)
+__global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st, StepScratch s)
 {
   __shared__ double ws[4];
-  __shared__ int32_t wsi[2][4];
+  __shared__ int32_t wsi[4][4];
   __shared__ long long wsl[2][4];
   if (st && st->stop) return;
-  const int cur = st ? st->cur : 0;
-  const int32_t *nx = nz.p[cur];
-  const int32_t *ny = nz.p[cur == 2 ? 0 : cur + 1];
   const int base = blockIdx.x * kRedBlock + threadIdx.x * 4;
   double a[3][4];
-  int32_t wy = 0, wu = 0;
-  long long sx = 0, sy = 0;
+  int32_t mx[4] = {0, 0, 0, 0};
+  long long sy = 0, su = 0;
   for (int q = 0; q < 4; ++q) {
     const int r = base + q;
     const bool in = r < N;
@@ -292,32 +418,32 @@ __global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st,
     a[1][q] = in ? s.d2[r] : -0.0;
     a[2][q] = in ? s.e[r] : -0.0;
     if (in) {
-      wy = max(wy, s.wy[r]);
-      wu = max(wu, s.wu[r]);
-      if (nx) sx += nx[r];
-      if (ny) sy += ny[r];
+      mx[0] = max(mx[0], s.wy[r]);
+      mx[1] = max(mx[1], s.wu[r]);
+      if (s.ly) mx[2] = max(mx[2], s.ly[r]);
+      if (s.lu) mx[3] = max(mx[3], s.lu[r]);
+      sy += s.wy[r];
+      su += s.wu[r];
     }
   }
   double t[3];
   for (int c = 0; c < 3; ++c) t[c] = block_tree_1024(a[c][0], a[c][1], a[c][2], a[c][3], ws);
   for (int o = 32; o > 0; o >>= 1) {
-    wy = max(wy, __shfl_xor(wy, o, kWave));
-    wu = max(wu, __shfl_xor(wu, o, kWave));
-    sx += __shfl_xor(sx, o, kWave);
+    for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], __shfl_xor(mx[c], o, kWave));
     sy += __shfl_xor(sy, o, kWave);
+    su += __shfl_xor(su, o, kWave);
   }
   const int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
-    wsi[0][w] = wy;
-    wsi[1][w] = wu;
-    wsl[0][w] = sx;
-    wsl[1][w] = sy;
+    for (int c = 0; c < 4; ++c) wsi[c][w] = mx[c];
+    wsl[0][w] = sy;
+    wsl[1][w] = su;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int c = 0; c < 3; ++c) s.part[c * s.nb + blockIdx.x] = t[c];
-    s.partw[blockIdx.x] = max(max(wsi[0][0], wsi[0][1]), max(wsi[0][2], wsi[0][3]));
-    s.partw[s.nb + blockIdx.x] = max(max(wsi[1][0], wsi[1][1]), max(wsi[1][2], wsi[1][3]));
+    for (int c = 0; c < 4; ++c)
+      s.partw[c * s.nb + blockIdx.x] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
     s.partn[blockIdx.x] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
     s.partn[s.nb + blockIdx.x] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
   }
@@ -335,18 +461,16 @@ __device__ void final_reduce(const StepScratch &s, double *ws)
     if (threadIdx.x == 0) s.out[c] = t;
   }
   if (threadIdx.x == 0) {
-    int32_t wy = 0, wu = 0;
-    long long sx = 0, sy = 0;
+    int32_t mx[4] = {0, 0, 0, 0};
+    long long sy = 0, su = 0;
     for (int b = 0; b < s.nb; ++b) {
-      wy = max(wy, s.partw[b]);
-      wu = max(wu, s.partw[s.nb + b]);
-      sx += s.partn[b];
-      sy += s.partn[s.nb + b];
+      for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], s.partw[c * s.nb + b]);
+      sy += s.partn[b];
+      su += s.partn[s.nb + b];
     }
-    s.outw[0] = wy;
-    s.outw[1] = wu;
-    s.outn[0] = sx;
-    s.outn[1] = sy;
+    for (int c = 0; c < 4; ++c) s.outw[c] = mx[c];
+    s.outn[0] = sy;
+    s.outn[1] = su;
   }
 }
 
@@ -363,6 +487,11 @@ __device__ bool stalled(const double *h, int n)
 __device__ void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s)
 {
   const int n = st->iter;
+  if (s.flags && (*s.flags & 1)) {  // some row group was not computed: redo on the ELLPACK pipeline
+    st->status = ST_FALLBACK;
+    st->stop = 1;
+    return;
+  }
   const double trx = s.out[0], trx2 = s.out[1], eta2 = s.out[2];
   st->trx = trx;
   st->trx2 = trx2;
@@ -375,8 +504,8 @@ __device__ void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const 
   h.maxw[n] = s.outw[0];
   h.prec[n] = (int8_t)st->phase32;
   h.up[n] = -1;
-  h.nnzx[n] = s.outn[0];
-  h.nnzy[n] = s.outn[1];
+  h.nnzx[n] = st->nnz_cur;
+  h.nnzy[n] = s.outn[0];
   const bool stall = cfg.stall && stalled(h.eta2 + st->phase_start, n - st->phase_start);
   if (st->phase32) {
     if (eta2 < cfg.switch2 || stall) {
@@ -409,8 +538,8 @@ __device__ void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const 
   const double a = fabs(2.0 * trx - trx2 - cfg.n_occ);
   const double b = fabs(trx2 - cfg.n_occ);
   const bool up = a < b;
-  const int need = up ? s.outw[1] : s.outw[0];
-  if (need > st->cap) {
+  const int need = cfg.span ? (up ? s.outw[3] : s.outw[2]) : (up ? s.outw[1] : s.outw[0]);
+  if (need > (cfg.span ? st->sw : st->cap)) {
     st->status = ELL_EOVERFLOW;
     st->need_width = need;
     st->stop = 1;
@@ -420,6 +549,7 @@ __device__ void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const 
   const int c = st->cur;
   st->cur = up ? (c == 0 ? 2 : c - 1) : (c == 2 ? 0 : c + 1);
   if (!st->phase32) st->fp64_updates += 1;
+  st->nnz_cur = up ? s.outn[1] : s.outn[0];
   st->iter = n + 1;
 }
 
@@ -498,7 +628,7 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv,
-                                            T tau, int32_t *wmax)
+                                            T tau, int32_t *wmax, unsigned long long *total)
 {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
@@ -531,6 +661,7 @@ __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T>
   }
   X.nnz[i] = min(c, X.M);
   atomicMax(wmax, c);
+  atomicAdd(total, (unsigned long long)c);
 }
 
 // Row copy between capacities and precisions (widening float -> double is exact).
@@ -613,11 +744,9 @@ template hipError_t launch_x2_step<double>(int, Rot3<double>, const SP2State *, 
 template hipError_t launch_x2_step<float>(int, Rot3<float>, const SP2State *, bool, float,
                                           const StepScratch &, hipStream_t);
 
-hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream,
-                         const int32_t *nnz0, const int32_t *nnz1, const int32_t *nnz2)
+hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream)
 {
-  Nnz3 nz{{nnz0, nnz1, nnz2}};
-  hipLaunchKernelGGL(k_step_partial, dim3(s.nb), dim3(256), 0, stream, N, st, s, nz);
+  hipLaunchKernelGGL(k_step_partial, dim3(s.nb), dim3(256), 0, stream, N, st, s);
   return hipGetLastError();
 }
 
@@ -646,15 +775,16 @@ hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *ro
 
 template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau, int32_t *wmax,
-                     hipStream_t stream)
+                     unsigned long long *total, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_x0<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, H, X, emax, inv, tau, wmax);
+  hipLaunchKernelGGL((k_x0<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, H, X, emax, inv, tau, wmax,
+                     total);
   return hipGetLastError();
 }
 template hipError_t launch_x0<double>(int, EllView<double>, EllView<double>, double, double, double,
-                                      int32_t *, hipStream_t);
+                                      int32_t *, unsigned long long *, hipStream_t);
 template hipError_t launch_x0<float>(int, EllView<double>, EllView<float>, double, double, float, int32_t *,
-                                     hipStream_t);
+                                     unsigned long long *, hipStream_t);
 
 template <typename TS, typename TD>
 hipError_t launch_copy(int N, EllView<TS> src, EllView<TD> dst, hipStream_t stream)

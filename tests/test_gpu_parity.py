@@ -260,3 +260,29 @@ def test_wrapped_result_too_narrow_reports_width():
     rc, rep = E.sp2_solve(Hd.h, D, E.sp2_params(N // 4, 1e-10, 1e-8))
     assert rc == E.ELL_EOVERFLOW and rep["final_M"] > M
     E.ellpack_free(D)
+
+
+def test_sp2_span_stride_grows_mid_solve():
+    """tau = 0 on N = 300: rows fill in to 300 columns, past the initial
+    256-column interval stride, so the stride grows and the step is redone."""
+    o, g = sp2_both(300, 6, 0.0, 1e-9, M=32, max_iter=200)
+    assert_same_trajectory(o, g)
+    assert g[2]["final_M"] >= 300
+
+
+def test_sp2_long_range_coupling_falls_back_to_ellpack():
+    """A coupling between rows 10 and 900 makes X0's row 10 span 890 columns:
+    the band kernel cannot hold that window and the solve continues on the
+    ELLPACK kernel, with the same bits as the oracle."""
+    N = 1024
+    nnz, idx, val, M = synth.banded_hamiltonian(N, 4, seed=7)
+    D = synth.ell_to_dense(N, M, nnz, idx, val)
+    D[10, 900] = D[900, 10] = 0.3
+    nnz, idx, val, M = synth.dense_to_ell(D)
+    H = oracle.Ell(N, M, nnz, idx, val)
+    po = oracle.make_params(N // 4, 1e-7, 1e-6, max_iter=120)
+    o = oracle.sp2(H, po, Mo=N)
+    Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    Dd = E.DeviceEll(N, 64, E.ELL_F64)
+    rc_g, rep_g = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-7, 1e-6, max_iter=120))
+    assert_same_trajectory(o, (rc_g, Dd, rep_g))
