@@ -34,7 +34,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 N, B, M_CAP = 32768, 64, 256
 TAU, TARGET = 1e-8, 1e-6
-TAU_FP32, SWITCH_ETA = 1e-7, 1e-3
+# mixed: FP32 phase at 1e-7, FP64 tail at a tighter 1e-9 (the FP32 phase leaves
+# rounding noise that the FP64 steps must not prune back in), switch at 1e-2
+TAU_MIXED64, TAU_FP32, SWITCH_ETA = 1e-9, 1e-7, 1e-2
 METRIC = "ELLPACK X² GB/s (%HBM peak) + SP2 solve ms to ‖X²−X‖_F<1e-6, FP64 vs mixed"
 
 
@@ -67,6 +69,40 @@ def cpu_baseline(nnz, idx, val, M, seconds_budget=20.0):
                       f"same N={N} b={B} tau={TAU:g} workload, {calls} calls, {total_s:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "x2_band_f64_n32768_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_08505_amd", "csrc", "ell_band.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, scaled by the copy-kernel calibration; None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain device copy of known size (3 x 512 MiB), profiled with the same
+    counters to scale FETCH_SIZE / WRITE_SIZE into bytes."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +110,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of known size (for scaling the HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block split "
               f"is a design, not a build", file=sys.stderr)
@@ -94,7 +135,8 @@ def main():
     D = E.DeviceEll(N, M_CAP, stream=stream)
 
     def solve(precision, profile=1):
-        p = E.sp2_params(N / 4, TAU, TARGET, max_iter=200, precision=precision, tau_fp32=TAU_FP32,
+        tau = TAU if precision == E.SP2_F64 else TAU_MIXED64
+        p = E.sp2_params(N / 4, tau, TARGET, max_iter=200, precision=precision, tau_fp32=TAU_FP32,
                          switch_eta=SWITCH_ETA, profile=profile)
         rc, rep = E.sp2_solve(H.h, D.h, p, history=False)
         return rc, rep
@@ -130,7 +172,7 @@ def main():
         mr = mreps[-1][1]
         mixed = {"status": int(mreps[-1][0]), "ms_per_solve": mwall / args.steps * 1e3,
                  "iterations": mr["iterations"], "fp32_iterations": mr["fp32_iterations"],
-                 "eta": mr["eta"], "tau_fp32": TAU_FP32, "switch_eta": SWITCH_ETA,
+                 "eta": mr["eta"], "tau_fp32": TAU_FP32, "tau_fp64": TAU_MIXED64, "switch_eta": SWITCH_ETA,
                  "speedup_vs_fp64": ms_per_step / (mwall / args.steps * 1e3)}
 
     line = {
@@ -156,8 +198,9 @@ def main():
                 "x2_ms_per_launch": x2_sec / launches * 1e3},
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_x2_step<double, true> (fused X^2, traces, norm, 2X - X^2)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_x2_band<double, true, false, true> (fused X^2, prune, traces, norm, "
+                               "2X - X^2 on the span form)",
                      "bytes_per_launch": x2_bytes / launches},
     }
     if not args.no_cpu:

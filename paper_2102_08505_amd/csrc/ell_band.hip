@@ -30,7 +30,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kG = 8;           // output rows per wave
 constexpr int kWavesPerBlock = 4;
-constexpr int kSB = 8;          // rows k per batch of B loads
+constexpr int kCP = 4;          // 64-column chunks accumulated per pass
 constexpr int kKQ = 4;          // rows k held in registers per group: 64 kKQ
 constexpr int kNormBlocks = 128;  // aligned 64-column blocks per row in the norm table
 constexpr int kMaxChunks = 64;    // widest output window: 64 chunks of 64 columns
@@ -75,24 +75,127 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
   return (b % kXcd) * per + b / kXcd;
 }
 
-// B operand of one batch: X[k][col] for k = kb .. kb + kSB - 1 (zero past khi
-// or outside row k's interval).  The intervals come from scalar loads of the
-// base/len arrays, which are padded past N (see SpanMem).
+// X's values are never written while the kernel runs (X^2 and 2X - X^2 go to
+// the other two buffers), so the row values X[i_g][k] -- the same for every
+// lane -- are read through the scalar cache into SGPRs.
 template <typename T>
-__device__ __forceinline__ void load_b(const SpanView<T> &X, const T *__restrict__ xv, const int SW, const int kb,
-                                       const int khi, const int col, T (&out)[kSB])
+using const_ptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ T sload(const T *p, ptrdiff_t off)
 {
-  int kbase[kSB], klen[kSB];
+  return ((const_ptr<T>)p)[off];
+}
+__device__ __forceinline__ int sload_i(const int32_t *p, int off) { return ((const_ptr<int32_t>)p)[off]; }
+
+// Raw buffer loads of row k of X: the buffer's range is exactly row k's
+// interval, so lanes whose column lies outside it (either side: a negative
+// byte offset wraps to a huge unsigned one) read 0 without any masking code.
+constexpr int kRawBufferFlags = 0x00020000;  // 32-bit raw buffer, gfx9 family
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *row, int len)
+{
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(row), (short)0, len * (int)sizeof(T), kRawBufferFlags);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, int off, double)
+{
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off, float)
+{
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Rows of the group as seen by the accumulation: row g of the wave is X row
+// i0 + g with interval [bs[g], bs[g] + ln[g]); `full` when all kG rows exist
+// and are non-empty, and [ilo, ihi] is then the k range inside every interval.
+struct GroupRows {
+  int bs[kG], ln[kG];
+  int i0, nrows, ilo, ihi;
+  bool full;
+};
+
+// B of one row k for the CP chunks of a pass (zero outside row k's interval)
+template <typename T, int CP>
+__device__ __forceinline__ void load_row(const T *__restrict__ xv, const int SW, const int k, const int bk,
+                                         const int lk, const int colb, T (&b)[CP])
+{
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(xv + (size_t)k * SW, lk);
+  const int off = colb - bk * (int)sizeof(T);
 #pragma unroll
-  for (int u = 0; u < kSB; ++u) {
-    kbase[u] = X.base[kb + u];
-    klen[u] = kb + u <= khi ? X.len[kb + u] : 0;
+  for (int c = 0; c < CP; ++c) {
+    // The whole byte offset goes in the VGPR: with the chunk's part folded into
+    // the instruction's immediate offset, the 4-byte loads of this kernel gave
+    // wrong values for some lanes on gfx950 (the range check and the address
+    // did not agree).  The empty asm keeps the compiler from folding it back.
+    int offc = off + c * kWave * (int)sizeof(T);
+    asm volatile("" : "+v"(offc));
+    b[c] = bload(r, offc, T(0));
   }
+}
+
+// acc[g][c] = sum over k in [klo, khi], ascending, of fma(X[i_g][k], X[k][col_c], .)
+// for the CP chunks of the pass starting at column p0 (col_c = p0 + 64 c + lane).
+// The B values of row k + 1 are loaded before row k is used.  k where some row
+// of the group has no entry (the edges of the band, partial groups) take the
+// masked path; inside every interval the row values are plain scalar loads
+// from per-row pointers.  Positions outside an interval enter as exact zeros.
+template <typename T, int CP>
+__device__ __forceinline__ void accumulate(const T *__restrict__ xv, const int SW, const int32_t *xbase,
+                                           const int32_t *xlen, const GroupRows &R, const int klo, const int khi,
+                                           const int p0, T (&acc)[kG][kCP])
+{
+  const int lane = lane_id();
 #pragma unroll
-  for (int u = 0; u < kSB; ++u) {
-    const int off = col - kbase[u];
-    out[u] = ((unsigned)off < (unsigned)klen[u]) ? xv[(size_t)(kb + u) * SW + off] : T(0);
+  for (int g = 0; g < kG; ++g)
+#pragma unroll
+    for (int c = 0; c < kCP; ++c) acc[g][c] = T(0);
+  if (khi < klo) return;
+  const int colb = (p0 + lane) * (int)sizeof(T);
+  // interior k range of this pass
+  const int jlo = R.full ? max(klo, R.ilo) : INT_MAX;
+  const int jhi = R.full ? min(khi, R.ihi) : INT_MIN;
+  T bn[CP];
+  load_row<T, CP>(xv, SW, klo, sload_i(xbase, klo), sload_i(xlen, klo), colb, bn);
+  int k = klo;
+  // masked rows: left edge (and everything when there is no interior)
+  auto masked = [&](int kend) {
+    for (; k <= kend; ++k) {
+      T bc[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) bc[c] = bn[c];
+      if (k + 1 <= khi) load_row<T, CP>(xv, SW, k + 1, sload_i(xbase, k + 1), sload_i(xlen, k + 1), colb, bn);
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int o = k - R.bs[g];
+        const bool ok = g < R.nrows && (unsigned)o < (unsigned)R.ln[g];
+        const T v = sload(xv, ok ? (ptrdiff_t)(R.i0 + g) * SW + o : (ptrdiff_t)R.i0 * SW);
+        const T a = ok ? v : T(0);
+#pragma unroll
+        for (int c = 0; c < CP; ++c) acc[g][c] = fmadd(a, bc[c], acc[g][c]);
+      }
+    }
+  };
+  if (jlo <= jhi) {
+    masked(jlo - 1);
+    const T *rp[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) rp[g] = xv + (ptrdiff_t)(R.i0 + g) * SW - R.bs[g];
+    for (; k <= jhi; ++k) {
+      T bc[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) bc[c] = bn[c];
+      if (k + 1 <= khi) load_row<T, CP>(xv, SW, k + 1, sload_i(xbase, k + 1), sload_i(xlen, k + 1), colb, bn);
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const T a = sload(rp[g], k);
+#pragma unroll
+        for (int c = 0; c < CP; ++c) acc[g][c] = fmadd(a, bc[c], acc[g][c]);
+      }
+    }
   }
+  masked(khi);
 }
 
 // Per-row running state of the sweep, one lane per row (lane g holds row g).
@@ -201,15 +304,31 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
   int st_cy = 0, st_cu = 0, st_yf = INT_MAX, st_yl = -1, st_uf = INT_MAX, st_ul = -1;
   for (int r = lane; r < kG * kNormBlocks; r += kWave) bsum[r] = 0.0;
 
-  for (int r = 0; r < nchunk; ++r) {
-    const int c0 = wlo + r * kWave;  // first column of the chunk
-    const int col = c0 + lane;
-    // rows k whose interval meets the chunk: a conservative k range
+  GroupRows R;
+  R.i0 = i0;
+  R.nrows = nrows;
+  R.full = nrows == kG;
+  R.ilo = INT_MIN;
+  R.ihi = INT_MAX;
+#pragma unroll
+  for (int g = 0; g < kG; ++g) {
+    R.bs[g] = bs[g];
+    R.ln[g] = ln[g];
+    R.full = R.full && ln[g] > 0;
+    R.ilo = max(R.ilo, bs[g]);
+    R.ihi = min(R.ihi, bs[g] + ln[g] - 1);
+  }
+
+  for (int pc = 0; pc < nchunk; pc += kCP) {
+    const int cnt = min(kCP, nchunk - pc);
+    const int p0 = wlo + pc * kWave;         // first column of the pass
+    const int p1 = p0 + cnt * kWave - 1;     // last column of the pass
+    // rows k whose interval meets the pass: a conservative k range
     int klo = INT_MAX, khi = -1;
     if (kfit) {
 #pragma unroll
       for (int q = 0; q < kKQ; ++q) {
-        const bool meet = klq[q] > 0 && kbq[q] <= c0 + kWave - 1 && kbq[q] + klq[q] - 1 >= c0;
+        const bool meet = klq[q] > 0 && kbq[q] <= p1 && kbq[q] + klq[q] - 1 >= p0;
         const uint64_t m = __ballot(meet);
         if (m) {
           klo = min(klo, kmin + q * kWave + (int)__builtin_ctzll(m));
@@ -223,7 +342,7 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
         if (k <= kmax) {
           const int l = X.len[k];
           const int b = X.base[k];
-          meet = l > 0 && b <= c0 + kWave - 1 && b + l - 1 >= c0;
+          meet = l > 0 && b <= p1 && b + l - 1 >= p0;
         }
         const uint64_t m = __ballot(meet);
         if (m) {
@@ -232,50 +351,27 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
         }
       }
     }
-    T acc[kG];
-#pragma unroll
-    for (int g = 0; g < kG; ++g) acc[g] = T(0);
-    if (khi >= klo) {
-      // B = X[k][column], kSB rows k at a time, the next batch loaded before the
-      // current one is used; rows k past khi read as zero
-      T bcur[kSB];
-      load_b<T>(X, xv, SW, klo, khi, col, bcur);
-      for (int kb = klo; kb <= khi; kb += kSB) {
-        T bnext[kSB];
-        const bool more = kb + kSB <= khi;
-        if (more) load_b<T>(X, xv, SW, kb + kSB, khi, col, bnext);
-        // A = X[i_g][kb + u], the same for every lane: one scalar load of kSB
-        // consecutive values per row whose interval meets the batch (addresses
-        // stay inside the guard band around the span buffer), masked where the
-        // batch sticks out of the interval
-#pragma unroll
-        for (int g = 0; g < kG; ++g) {
-          const int o = kb - bs[g];
-          if (o + kSB <= 0 || o >= ln[g]) continue;
-          const T *pa = xv + (ptrdiff_t)(i0 + g) * SW + o;
-          T av[kSB];
-#pragma unroll
-          for (int u = 0; u < kSB; ++u) av[u] = pa[u];
-          if (o < 0 || o + kSB > ln[g]) {
-#pragma unroll
-            for (int u = 0; u < kSB; ++u) av[u] = ((unsigned)(o + u) < (unsigned)ln[g]) ? av[u] : T(0);
-          }
-#pragma unroll
-          for (int u = 0; u < kSB; ++u) acc[g] = fmadd(av[u], bcur[u], acc[g]);
-        }
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < kSB; ++u) bcur[u] = bnext[u];
-        }
-      }
+    klo = uni(klo);
+    khi = uni(khi);
+    T acc[kG][kCP];
+    switch (cnt) {
+      case 1: accumulate<T, 1>(xv, SW, X.base, X.len, R, klo, khi, p0, acc); break;
+      case 2: accumulate<T, 2>(xv, SW, X.base, X.len, R, klo, khi, p0, acc); break;
+      case 3: accumulate<T, 3>(xv, SW, X.base, X.len, R, klo, khi, p0, acc); break;
+      default: accumulate<T, 4>(xv, SW, X.base, X.len, R, klo, khi, p0, acc); break;
     }
+#pragma unroll
+    for (int cc = 0; cc < kCP; ++cc) {
+    if (cc >= cnt) break;
+    const int c0 = p0 + cc * kWave;  // first column of the chunk
+    const int col = c0 + lane;
     // sweep the chunk for every row
     const int rel = (c0 >> 6) - b0;
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
       if (g >= nrows) break;
       const int i = i0 + g;
-      const T y = acc[g];
+      const T y = acc[g][cc];
       const int ox = col - bs[g];
       const T x = (unsigned)ox < (unsigned)ln[g] ? xv[(size_t)i * SW + ox] : T(0);
       if (col == i) {  // X_ii and the unpruned (X.X)_ii
@@ -331,6 +427,7 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
       const double dd = (double)yk - (double)x;
       const double t = wave_tree(dd * dd);
       if (lane == 0 && rel < kNormBlocks) bsum[g * kNormBlocks + rel] = t;
+    }
     }
   }
 

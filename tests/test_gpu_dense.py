@@ -145,9 +145,13 @@ def test_dense_sp2_bf16x3_reaches_fp64_accuracy(N, b):
     k = rep["fp32_iterations"]
     assert np.all(prec[:k] == 1) and np.all(prec[k:] == 0)
     assert rep["eta"] < 1e-8
+    # The FP32 phase leaves X a projector onto a subspace rotated by rounding
+    # (the FP64 steps restore idempotency, not the subspace), so the distance to
+    # the exact projector is at the FP32 level for both implementations.
     P = _projector(H, n_occ)
-    assert np.linalg.norm(D - P) < 1e-6
-    assert np.linalg.norm(Do - P) < 1e-6
+    eg, eo = np.linalg.norm(D - P), np.linalg.norm(Do - P)
+    assert eg < 1e-3 and eo < 1e-3
+    assert eg <= 10 * eo + 1e-9, (eg, eo)
     assert abs(np.trace(D) - n_occ) < 1e-6
 
 
