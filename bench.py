@@ -17,7 +17,9 @@ one X^2: every stored entry of X read once and of the pruned X^2 written once
 row-width arrays.
 
 Also reported: the mixed-precision solve (FP32 phase, then FP64 steps) to the
-same target, and the oracle on the host cores as cpu_baseline.
+same target; the batched workload (256 instances of uneven size in one call,
+against solving them one by one); the dense-block variant at N = 8192 (BF16x3
+against FP64 MFMA products); and the oracle on the host cores as cpu_baseline.
 """
 from __future__ import annotations
 
@@ -103,6 +105,73 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
+def batched_leg(E, synth, torch, count=256):
+    """The batched workload: 256 Hamiltonians, N uniform in 64..2048, half-bandwidth
+    max(4, N/32), mixed precision (FP32 phase, then FP64) to ||X^2-X||_F < 1e-6;
+    one batched call against the same instances solved one after another."""
+    specs = synth.batched_instances(count, seed=0)
+    Hs, Db, Ds, ps = [], [], [], []
+    for q, (n, b) in enumerate(specs):
+        nnz, idx, val, m = synth.banded_hamiltonian(n, b, seed=0, stream=q)
+        Hs.append(E.DeviceEll.from_host(n, m, nnz, idx, val))
+        Db.append(E.DeviceEll(n, 4 * b))
+        Ds.append(E.DeviceEll(n, 4 * b))
+        ps.append(E.sp2_params(n / 4, TAU_MIXED64, TARGET, max_iter=200, precision=E.SP2_MIXED,
+                               tau_fp32=TAU_FP32, switch_eta=SWITCH_ETA, poll_every=0))
+    hh, hb = [h.h for h in Hs], [d.h for d in Db]
+    E.sp2_solve_batched(hh, hb, ps, history=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc_b, reps_b = E.sp2_solve_batched(hh, hb, ps, history=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    singles = [E.sp2_solve(Hs[q].h, Ds[q].h, ps[q], history=False) for q in range(count)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    rows = sum(n for n, _ in specs)
+    return {"workload": f"{count} banded Hamiltonians, N uniform in 64..2048 (sum {rows} rows), "
+                        f"half-bandwidth max(4, N/32), mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}, "
+                        f"to ||X^2-X||_F<{TARGET:g}",
+            "status": int(rc_b), "ok": sum(1 for r in reps_b if r["status"] == 0),
+            "batched_ms": tb * 1e3, "sequential_ms": ts * 1e3, "speedup_vs_sequential": ts / tb,
+            "max_iterations": max(r["iterations"] for r in reps_b),
+            "max_eta": max(r["eta"] for r in reps_b),
+            "same_as_single": all(reps_b[q]["iterations"] == singles[q][1]["iterations"]
+                                  and reps_b[q]["eta"] == singles[q][1]["eta"] for q in range(count))}
+
+
+def dense_leg(E, synth, torch, n=8192, b=512):
+    """Dense-block variant: N = 8192 dense H (half-bandwidth 512), SP2 to
+    ||X^2-X||_F < 1e-6 with BF16x3 products (then FP64 steps) and in plain FP64."""
+    Hh = synth.dense_hamiltonian(n, b, seed=0)
+    dH = torch.from_numpy(Hh).cuda()
+    dD = torch.empty_like(dH)
+    out = {"workload": f"dense banded H N={n} half-bandwidth {b}, N_occ={n // 4}, to ||X^2-X||_F<{TARGET:g}"}
+    for mode, name in ((E.DENSE_BF16X3, "bf16x3"), (E.DENSE_F64, "f64")):
+        p = E.sp2_params(n / 4, 0.0, TARGET, max_iter=100, poll_every=8, profile=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep = E.dense_sp2_solve(dH.data_ptr(), n, dD.data_ptr(), mode, p, torch.cuda.current_stream(),
+                                    history=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per = rep["x2_seconds"] / max(rep["x2_launches"], 1)
+        flops = 2.0 * n ** 3
+        out[name] = {"status": int(rc), "solve_ms": wall * 1e3, "iterations": rep["iterations"],
+                     "fp32_iterations": rep["fp32_iterations"], "eta": rep["eta"],
+                     "x2_ms_per_product": per * 1e3, "x2_tflops": flops / per / 1e12 if per > 0 else None}
+    bf, f64 = out["bf16x3"], out["f64"]
+    out["speedup_bf16x3_vs_f64"] = f64["solve_ms"] / bf["solve_ms"]
+    # MFMA rooflines: BF16x3 executes three bf16 products per X^2 (2.5 PFLOP/s dense
+    # bf16 peak); FP64 runs at the 78.6 TFLOP/s FP64 matrix peak
+    if bf["x2_tflops"]:
+        bf["mfma_frac"] = 3 * bf["x2_tflops"] / 2500.0
+    if f64["x2_tflops"]:
+        f64["mfma_frac"] = f64["x2_tflops"] / 78.6
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +179,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on the host")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -203,6 +274,10 @@ def main():
                                "2X - X^2 on the span form)",
                      "bytes_per_launch": x2_bytes / launches},
     }
+    if not args.no_batched:
+        line["batched"] = batched_leg(E, synth, torch)
+    if not args.no_dense:
+        line["dense"] = dense_leg(E, synth, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(nnz, idx, val, M)
     print(json.dumps(line), flush=True)

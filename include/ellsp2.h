@@ -180,8 +180,18 @@ typedef struct {
  * the last X and the report is filled.  r may be NULL. */
 int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p, sp2_report_t *r);
 
-/* n independent SP2 solves of uneven sizes.  Each instance's result is
- * bit-identical to sp2_solve on it alone.  r: n reports (may be NULL). */
+/* n independent SP2 solves of uneven sizes, run together: the instances' rows
+ * are stacked in one matrix and every iteration is one launch of the step
+ * kernel over all of them, replayed from a captured HIP graph of K iterations,
+ * with per-instance state (buffers, precision phase, stop) on the device.
+ * p: n parameter sets (one per instance); p[0].poll_every = K, or 0 to pick K
+ * by timing the first graph replays.  Each instance's result, history and
+ * status are bit-identical to sp2_solve on it alone; an instance the stacked
+ * form cannot hold (X0 with exact zeros or rows wider than 4096 columns, or a
+ * stride overflow beyond that) is finished by sp2_solve on its own.  r: n
+ * reports (may be NULL); `seconds` is the whole batch's device time, and the
+ * x2 timing fields are 0 (the step kernel serves all instances at once).
+ * Returns ELL_OK or the most negative instance status. */
 int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t *const *D,
                       const sp2_params_t *p, sp2_report_t *r);
 

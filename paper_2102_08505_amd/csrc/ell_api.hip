@@ -8,6 +8,7 @@
 // control block, every kernel of the loop returns at once when that block
 // says "stop", and the host reads the block only every poll_every iterations.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -1042,16 +1043,701 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   return final_status;
 }
 
+// ===========================================================================
+// batched SP2
+// ===========================================================================
+namespace {
+
+struct BatchInst {
+  int q = 0;                 // index in the caller's arrays
+  int N = 0, r0 = 0;         // rows; first row in the stacked matrix
+  int nb = 0, pb = 0;        // reduction blocks; first partial block
+  int hoff = 0;              // offset of its history arrays
+  bool mixed = false;
+  double emin = 0, emax = 0;
+  int32_t maxlen = 0;
+  bool zeros = false;
+  unsigned long long nnz0 = 0;
+  int status = ST_RUNNING;   // set when the instance leaves the batch before the loop
+  bool solo = false;         // finished by sp2_solve on its own (the batch cannot hold it)
+};
+
+struct Batch {
+  hipStream_t st = nullptr;
+  int n = 0, NT = 0, ngroups = 0, nblocks = 0, SW = 0;
+  bool any32 = false;
+  std::vector<BatchInst> in;
+  SpanSet<double> A64;
+  SpanSet<float> A32;
+  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags;
+  DevMem grp_inst, blk_inst, blk_local, inst_rows, inst_r0, ss, states, cfgs, hists, taus64, taus32;
+  DevMem h_trx, h_trx2, h_eta2, h_up, h_prec, h_maxw, h_nnzx, h_nnzy;
+  SP2State *hs = nullptr;    // pinned host mirror of the states
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_iters = 0;
+  ~Batch()
+  {
+    drop_graph();
+    if (hs) (void)hipHostFree(hs);
+    if (st) (void)hipStreamDestroy(st);
+  }
+  void drop_graph()
+  {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_iters = 0;
+  }
+  StepScratch global_scratch() const
+  {
+    StepScratch t{};
+    t.d1 = d1.as<double>();
+    t.d2 = d2.as<double>();
+    t.e = e.as<double>();
+    t.wy = wy.as<int32_t>();
+    t.wu = wu.as<int32_t>();
+    t.ly = ly.as<int32_t>();
+    t.lu = lu.as<int32_t>();
+    return t;
+  }
+  template <typename T>
+  SpanView<T> rows(const SpanSet<T> &A, int b, const BatchInst &m) const
+  {
+    SpanView<T> v = A.v(b);
+    v.val += (size_t)m.r0 * v.SW;
+    v.base += m.r0;
+    v.len += m.r0;
+    return v;
+  }
+  // one SP2 iteration of every running instance, as recorded into the graph
+  int record_iteration()
+  {
+    const SP2State *stp = states.as<SP2State>();
+    if (any32)
+      HIP_TRY(launch_x2_band_batch<float>(ngroups, A32.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
+                                          inst_rows.as<int32_t>(), stp, 1, taus32.as<float>(),
+                                          ss.as<StepScratch>(), flags.as<int32_t>(), st));
+    HIP_TRY(launch_x2_band_batch<double>(ngroups, A64.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
+                                         inst_rows.as<int32_t>(), stp, 0, taus64.as<double>(), ss.as<StepScratch>(),
+                                         flags.as<int32_t>(), st));
+    HIP_TRY(launch_reduce_batch(nblocks, blk_inst.as<int32_t>(), blk_local.as<int32_t>(), inst_rows.as<int32_t>(),
+                                ss.as<StepScratch>(), stp, st));
+    HIP_TRY(launch_decide_batch(n, states.as<SP2State>(), cfgs.as<SP2Cfg>(), hists.as<SP2Hist>(),
+                                ss.as<StepScratch>(), st));
+    return ELL_OK;
+  }
+  // a graph of `iters` iterations (kernel nodes only)
+  int capture(int iters)
+  {
+    drop_graph();
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = ELL_OK;
+    for (int q = 0; q < iters && rc == ELL_OK; ++q) rc = record_iteration();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    HIP_TRY(e);
+    graph = g;
+    HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    graph_iters = iters;
+    return ELL_OK;
+  }
+};
+
+// Reallocate the stacked matrices with stride sw; every instance's current
+// matrix moves to buffer 0 (its values do not depend on the stride).
+int batch_regrow(Batch &B, int32_t sw)
+{
+  SpanSet<double> G64;
+  SpanSet<float> G32;
+  HIP_TRY(G64.alloc(B.NT, sw));
+  if (B.any32) HIP_TRY(G32.alloc(B.NT, sw));
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    if (I.solo) continue;
+    const SP2State &h = B.hs[m];
+    if (h.phase32)
+      HIP_TRY((launch_span_copy<float, float>(I.N, B.rows(B.A32, h.cur, I), B.rows(G32, 0, I), B.st)));
+    else
+      HIP_TRY((launch_span_copy<double, double>(I.N, B.rows(B.A64, h.cur, I), B.rows(G64, 0, I), B.st)));
+    B.hs[m].cur = 0;
+    B.hs[m].sw = sw;
+  }
+  HIP_TRY(hipStreamSynchronize(B.st));
+  for (int b = 0; b < 3; ++b) {
+    std::swap(B.A64.m[b].val.p, G64.m[b].val.p);
+    std::swap(B.A64.m[b].base.p, G64.m[b].base.p);
+    std::swap(B.A64.m[b].len.p, G64.m[b].len.p);
+    B.A64.m[b].SW = sw;
+    if (B.any32) {
+      std::swap(B.A32.m[b].val.p, G32.m[b].val.p);
+      std::swap(B.A32.m[b].base.p, G32.m[b].base.p);
+      std::swap(B.A32.m[b].len.p, G32.m[b].len.p);
+      B.A32.m[b].SW = sw;
+    }
+  }
+  B.A64.SW = sw;
+  if (B.any32) B.A32.SW = sw;
+  B.SW = sw;
+  B.drop_graph();
+  return ELL_OK;
+}
+
+// The result of instance m into D (FP64 ELLPACK, local columns).
+template <typename T>
+int batch_deliver(Batch &B, const SpanSet<T> &A, int m, ellpack *D, DevMem &wmax, int32_t *final_width)
+{
+  const BatchInst &I = B.in[m];
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    HIP_TRY(hipMemsetAsync(wmax.p, 0, sizeof(int32_t), B.st));
+    HIP_TRY((launch_span_to_ell<T, double>(I.N, B.rows(A, B.hs[m].cur, I), view<double>(D), wmax.as<int32_t>(),
+                                           B.st)));
+    int32_t width = 0;
+    HIP_TRY(hipMemcpyAsync(&width, wmax.p, sizeof(width), hipMemcpyDeviceToHost, B.st));
+    HIP_TRY(hipStreamSynchronize(B.st));
+    *final_width = width;
+    if (width <= D->M) {
+      D->validated = true;
+      return ELL_OK;
+    }
+    if (!D->owned) return ELL_EOVERFLOW;
+    int rc = regrow_owned(D, std::max(roundup32(width), 32));
+    if (rc) return rc;
+  }
+  return ELL_EOVERFLOW;
+}
+
+}  // namespace
+
 extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t *const *D, const sp2_params_t *p,
                                  sp2_report_t *r)
 {
-  if (n < 0 || (n > 0 && (!H || !D))) return ELL_EINVAL;
-  int rc = check_params(p);
-  if (rc) return rc;
-  int worst = ELL_OK;
+  if (n < 0 || (n > 0 && (!H || !D || !p))) return ELL_EINVAL;
   for (int32_t q = 0; q < n; ++q) {
-    rc = sp2_solve(H[q], D[q], p, r ? &r[q] : nullptr);
+    const ellpack *h = H[q], *d = D[q];
+    if (!h || !d || h == d || h->prec != ELL_F64 || d->prec != ELL_F64 || h->N != d->N || h->val == d->val)
+      return ELL_EINVAL;
+    for (int32_t o = 0; o < q; ++o)
+      if (D[o] == d || D[o]->val == d->val || H[o] == d) return ELL_EINVAL;
+    int rc = check_params(&p[q]);
+    if (rc) return rc;
+  }
+  for (int32_t q = 0; q < n; ++q)
+    if (r) {
+      r[q].status = 0;
+      r[q].iterations = r[q].fp32_iterations = r[q].final_M = 0;
+      r[q].eta = r[q].trace_x = r[q].emin = r[q].emax = r[q].seconds = r[q].x2_seconds = 0.0;
+      r[q].x2_bytes = 0;
+      r[q].x2_launches = 0;
+    }
+  if (n == 0) return ELL_OK;
+  for (int32_t q = 0; q < n; ++q) {
+    int rc = ensure_valid(H[q]);
+    if (rc) return rc;
+  }
+  // the callers' streams first, then a private stream for the batch
+  for (int32_t q = 0; q < n; ++q) {
+    HIP_TRY(hipStreamSynchronize(H[q]->stream));
+    HIP_TRY(hipStreamSynchronize(D[q]->stream));
+  }
+  Batch B;
+  HIP_TRY(hipStreamCreateWithFlags(&B.st, hipStreamNonBlocking));
+  hipStream_t st = B.st;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  struct Ev {
+    hipEvent_t &a, &b;
+    ~Ev()
+    {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev{t0, t1};
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  HIP_TRY(hipEventRecord(t0, st));
+
+  // ---- Gershgorin bounds of every instance (one synchronisation) ----
+  int maxN = 0;
+  for (int32_t q = 0; q < n; ++q) maxN = std::max(maxN, H[q]->N);
+  DevMem glo, ghi, gout, gflags;
+  HIP_TRY(glo.alloc(sizeof(double) * ((maxN + 255) / 256)));
+  HIP_TRY(ghi.alloc(sizeof(double) * ((maxN + 255) / 256)));
+  HIP_TRY(gout.alloc(sizeof(double) * 2 * n));
+  HIP_TRY(gflags.alloc(sizeof(int32_t) * n));
+  HIP_TRY(hipMemsetAsync(gflags.p, 0, sizeof(int32_t) * n, st));
+  for (int32_t q = 0; q < n; ++q)
+    HIP_TRY(launch_gershgorin(H[q]->N, view<double>(H[q]), glo.as<double>(), ghi.as<double>(),
+                              gout.as<double>() + 2 * q, gflags.as<int32_t>() + q, st));
+  std::vector<double> ee(2 * (size_t)n);
+  std::vector<int32_t> gf(n);
+  HIP_TRY(hipMemcpyAsync(ee.data(), gout.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(gf.data(), gflags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  // ---- layout: instances that can start, widest first, each at a multiple of kGroupRows rows ----
+  std::vector<int> order;
+  std::vector<int> early(n, ST_RUNNING);
+  for (int32_t q = 0; q < n; ++q) {
+    const double lo = ee[2 * q], hi = ee[2 * q + 1];
+    if (r) {
+      r[q].emin = lo;
+      r[q].emax = hi;
+    }
+    if (gf[q] & 2) early[q] = ELL_ENONFINITE;
+    else if (!(hi > lo) || !(p[q].n_occ > 0.0 && p[q].n_occ < (double)H[q]->N)) early[q] = ELL_EDEGENERATE;
+    else order.push_back(q);
+  }
+  // row-width buckets: instances sorted by the widest row of H (descending), so the
+  // heaviest row groups are dispatched first and the grid's tail is short
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (int64_t)H[a]->M * H[a]->N > (int64_t)H[b]->M * H[b]->N;
+  });
+  B.n = (int)order.size();
+  int rows = 0, blocks = 0, hoff = 0;
+  for (int m = 0; m < B.n; ++m) {
+    BatchInst I;
+    I.q = order[m];
+    I.N = H[I.q]->N;
+    I.r0 = rows;
+    I.nb = (I.N + kRedBlock - 1) / kRedBlock;
+    I.pb = blocks;
+    I.hoff = hoff;
+    I.mixed = p[I.q].precision == SP2_MIXED;
+    I.emin = ee[2 * I.q];
+    I.emax = ee[2 * I.q + 1];
+    rows += (I.N + kGroupRows - 1) / kGroupRows * kGroupRows;
+    blocks += I.nb;
+    hoff += p[I.q].max_iter;
+    B.any32 = B.any32 || I.mixed;
+    B.in.push_back(I);
+  }
+  B.NT = rows;
+  B.ngroups = rows / kGroupRows;
+  B.nblocks = blocks;
+  int worst = ELL_OK;
+  auto note = [&](int rc) {
     if (rc != ELL_OK && (worst == ELL_OK || rc < worst)) worst = rc;
+  };
+  for (int32_t q = 0; q < n; ++q)
+    if (early[q] != ST_RUNNING) {
+      note(early[q]);
+      if (r) r[q].status = early[q];
+    }
+  if (B.n == 0) return worst;
+
+  // ---- X0 of every instance in ELLPACK form (capacity grows until it fits) ----
+  int32_t cap0 = 32;
+  for (const BatchInst &I : B.in)
+    cap0 = std::max(cap0, std::min(roundup32(std::min<int64_t>((int64_t)H[I.q]->M + 1, I.N)), kMaxCap));
+  WorkSet<double> X64;
+  WorkSet<float> X32;
+  DevMem wmax, total, lens, xflags;
+  HIP_TRY(wmax.alloc(sizeof(int32_t) * B.n));
+  HIP_TRY(total.alloc(sizeof(unsigned long long) * B.n));
+  HIP_TRY(lens.alloc(sizeof(int32_t) * B.NT));
+  HIP_TRY(xflags.alloc(sizeof(int32_t) * B.n));
+  std::vector<int32_t> w0(B.n);
+  std::vector<unsigned long long> nz0(B.n);
+  for (;;) {
+    HIP_TRY(hipMemsetAsync(wmax.p, 0, sizeof(int32_t) * B.n, st));
+    HIP_TRY(hipMemsetAsync(total.p, 0, sizeof(unsigned long long) * B.n, st));
+    X64.release();
+    X32.release();
+    // one temporary slot set of each precision in use (only buffer 0 is used)
+    HIP_TRY(X64.nnz[0].alloc(sizeof(int32_t) * B.NT));
+    HIP_TRY(X64.idx[0].alloc(sizeof(int32_t) * (size_t)B.NT * cap0));
+    HIP_TRY(X64.val[0].alloc(sizeof(double) * (size_t)B.NT * cap0));
+    X64.cap = cap0;
+    if (B.any32) {
+      HIP_TRY(X32.nnz[0].alloc(sizeof(int32_t) * B.NT));
+      HIP_TRY(X32.idx[0].alloc(sizeof(int32_t) * (size_t)B.NT * cap0));
+      HIP_TRY(X32.val[0].alloc(sizeof(float) * (size_t)B.NT * cap0));
+      X32.cap = cap0;
+    }
+    for (int m = 0; m < B.n; ++m) {
+      const BatchInst &I = B.in[m];
+      const double inv = 1.0 / (I.emax - I.emin);
+      if (I.mixed) {
+        EllView<float> v = X32.v(0);
+        v.nnz += I.r0;
+        v.idx += (size_t)I.r0 * cap0;
+        v.val += (size_t)I.r0 * cap0;
+        HIP_TRY(launch_x0<float>(I.N, view<double>(H[I.q]), v, I.emax, inv, (float)p[I.q].tau_fp32,
+                                 wmax.as<int32_t>() + m, total.as<unsigned long long>() + m, st));
+      } else {
+        EllView<double> v = X64.v(0);
+        v.nnz += I.r0;
+        v.idx += (size_t)I.r0 * cap0;
+        v.val += (size_t)I.r0 * cap0;
+        HIP_TRY(launch_x0<double>(I.N, view<double>(H[I.q]), v, I.emax, inv, p[I.q].tau, wmax.as<int32_t>() + m,
+                                  total.as<unsigned long long>() + m, st));
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(w0.data(), wmax.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(nz0.data(), total.p, sizeof(unsigned long long) * B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t wide = 0;
+    for (int32_t w : w0) wide = std::max(wide, w);
+    if (wide <= cap0) break;
+    if (roundup32(wide) > kMaxCap) {
+      // an X0 row wider than any capacity: those instances run on their own
+      for (int m = 0; m < B.n; ++m)
+        if (w0[m] > kMaxCap) B.in[m].solo = true;
+      bool any = false;
+      for (int m = 0; m < B.n; ++m) {
+        if (!B.in[m].solo) any = true;
+      }
+      if (!any) break;
+      int32_t c = cap0;
+      for (int m = 0; m < B.n; ++m)
+        if (!B.in[m].solo) c = std::max(c, roundup32(w0[m]));
+      if (c == cap0) break;
+      cap0 = c;
+      continue;
+    }
+    cap0 = roundup32(wide);
+  }
+  // ---- interval extents; instances the span form cannot hold run on their own ----
+  HIP_TRY(hipMemsetAsync(xflags.p, 0, sizeof(int32_t) * B.n, st));
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    if (I.solo) continue;
+    if (I.mixed) {
+      EllView<float> v = X32.v(0);
+      v.nnz += I.r0;
+      v.idx += (size_t)I.r0 * cap0;
+      v.val += (size_t)I.r0 * cap0;
+      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, st));
+    } else {
+      EllView<double> v = X64.v(0);
+      v.nnz += I.r0;
+      v.idx += (size_t)I.r0 * cap0;
+      v.val += (size_t)I.r0 * cap0;
+      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, st));
+    }
+  }
+  std::vector<int32_t> hl(B.NT), xf(B.n);
+  HIP_TRY(hipMemcpyAsync(hl.data(), lens.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(xf.data(), xflags.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int32_t sw = 64;
+  for (int m = 0; m < B.n; ++m) {
+    BatchInst &I = B.in[m];
+    if (I.solo) continue;
+    for (int i = 0; i < I.N; ++i) I.maxlen = std::max(I.maxlen, hl[I.r0 + i]);
+    I.zeros = (xf[m] & 4) != 0;
+    if (I.zeros || I.maxlen > kMaxCap) {
+      I.solo = true;
+      continue;
+    }
+    sw = std::max(sw, std::min(std::max(256, roundup64(I.maxlen)), std::max(64, roundup64(I.N))));
+    I.nnz0 = nz0[m];
+  }
+  B.SW = sw;
+  HIP_TRY(B.A64.alloc(B.NT, sw));
+  if (B.any32) HIP_TRY(B.A32.alloc(B.NT, sw));
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    if (I.solo) continue;
+    if (I.mixed) {
+      EllView<float> v = X32.v(0);
+      v.nnz += I.r0;
+      v.idx += (size_t)I.r0 * cap0;
+      v.val += (size_t)I.r0 * cap0;
+      HIP_TRY(launch_ell_to_span<float>(I.N, v, B.rows(B.A32, 0, I), st));
+    } else {
+      EllView<double> v = X64.v(0);
+      v.nnz += I.r0;
+      v.idx += (size_t)I.r0 * cap0;
+      v.val += (size_t)I.r0 * cap0;
+      HIP_TRY(launch_ell_to_span<double>(I.N, v, B.rows(B.A64, 0, I), st));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  X64.release();
+  X32.release();
+
+  // ---- per-instance scratch, state, configuration and history ----
+  const size_t NT = (size_t)B.NT;
+  HIP_TRY(B.d1.alloc(sizeof(double) * NT));
+  HIP_TRY(B.d2.alloc(sizeof(double) * NT));
+  HIP_TRY(B.e.alloc(sizeof(double) * NT));
+  HIP_TRY(B.wy.alloc(sizeof(int32_t) * NT));
+  HIP_TRY(B.wu.alloc(sizeof(int32_t) * NT));
+  HIP_TRY(B.ly.alloc(sizeof(int32_t) * NT));
+  HIP_TRY(B.lu.alloc(sizeof(int32_t) * NT));
+  HIP_TRY(B.part.alloc(sizeof(double) * 3 * B.nblocks));
+  HIP_TRY(B.partw.alloc(sizeof(int32_t) * 4 * B.nblocks));
+  HIP_TRY(B.partn.alloc(sizeof(int64_t) * 2 * B.nblocks));
+  HIP_TRY(B.out.alloc(sizeof(double) * 3 * B.n));
+  HIP_TRY(B.outw.alloc(sizeof(int32_t) * 4 * B.n));
+  HIP_TRY(B.outn.alloc(sizeof(int64_t) * 2 * B.n));
+  HIP_TRY(B.flags.alloc(sizeof(int32_t) * B.n));
+  HIP_TRY(hipMemsetAsync(B.flags.p, 0, sizeof(int32_t) * B.n, st));
+  const size_t HT = (size_t)std::max(hoff, 1);
+  HIP_TRY(B.h_trx.alloc(sizeof(double) * HT));
+  HIP_TRY(B.h_trx2.alloc(sizeof(double) * HT));
+  HIP_TRY(B.h_eta2.alloc(sizeof(double) * HT));
+  HIP_TRY(B.h_up.alloc(HT));
+  HIP_TRY(B.h_prec.alloc(HT));
+  HIP_TRY(B.h_maxw.alloc(sizeof(int32_t) * HT));
+  HIP_TRY(B.h_nnzx.alloc(sizeof(int64_t) * HT));
+  HIP_TRY(B.h_nnzy.alloc(sizeof(int64_t) * HT));
+  std::vector<int32_t> gi(B.ngroups), bi(B.nblocks), bl(B.nblocks), ir(B.n), i0(B.n);
+  std::vector<StepScratch> vs(B.n);
+  std::vector<SP2Cfg> vc(B.n);
+  std::vector<SP2Hist> vh(B.n);
+  std::vector<double> t64(B.n);
+  std::vector<float> t32(B.n);
+  HIP_TRY(hipHostMalloc((void **)&B.hs, sizeof(SP2State) * B.n, hipHostMallocDefault));
+  const StepScratch gs = B.global_scratch();
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    const sp2_params_t &P = p[I.q];
+    for (int g = I.r0 / kGroupRows; g < (I.r0 + I.N + kGroupRows - 1) / kGroupRows; ++g) gi[g] = m;
+    for (int b = 0; b < I.nb; ++b) {
+      bi[I.pb + b] = m;
+      bl[I.pb + b] = b;
+    }
+    ir[m] = I.N;
+    i0[m] = I.r0;
+    StepScratch &s = vs[m];
+    s.d1 = gs.d1 + I.r0;
+    s.d2 = gs.d2 + I.r0;
+    s.e = gs.e + I.r0;
+    s.wy = gs.wy + I.r0;
+    s.wu = gs.wu + I.r0;
+    s.ly = gs.ly + I.r0;
+    s.lu = gs.lu + I.r0;
+    s.part = B.part.as<double>() + 3 * I.pb;
+    s.partw = B.partw.as<int32_t>() + 4 * I.pb;
+    s.partn = B.partn.as<int64_t>() + 2 * I.pb;
+    s.out = B.out.as<double>() + 3 * m;
+    s.outw = B.outw.as<int32_t>() + 4 * m;
+    s.outn = B.outn.as<int64_t>() + 2 * m;
+    s.flags = B.flags.as<int32_t>() + m;
+    s.nb = I.nb;
+    SP2Cfg &c = vc[m];
+    c = SP2Cfg{};
+    c.n_occ = P.n_occ;
+    c.target2 = P.idem_target * P.idem_target;
+    c.switch2 = P.switch_eta * P.switch_eta;
+    c.max_iter = P.max_iter;
+    c.tail = P.fp64_tail_steps;
+    c.stall = P.stall_stop ? 1 : 0;
+    c.mixed = I.mixed ? 1 : 0;
+    c.span = 1;
+    vh[m] = SP2Hist{B.h_trx.as<double>() + I.hoff,  B.h_trx2.as<double>() + I.hoff,
+                    B.h_eta2.as<double>() + I.hoff, B.h_up.as<int8_t>() + I.hoff,
+                    B.h_prec.as<int8_t>() + I.hoff, B.h_maxw.as<int32_t>() + I.hoff,
+                    B.h_nnzx.as<int64_t>() + I.hoff, B.h_nnzy.as<int64_t>() + I.hoff};
+    t64[m] = P.tau;
+    t32[m] = (float)P.tau_fp32;
+    SP2State &h = B.hs[m];
+    std::memset(&h, 0, sizeof(h));
+    h.status = ST_RUNNING;
+    h.phase32 = I.mixed ? 1 : 0;
+    h.cap = INT_MAX;
+    h.sw = sw;
+    h.nnz_cur = (int64_t)I.nnz0;
+    if (I.solo) {  // never enters the loop
+      h.stop = 1;
+      h.status = ST_FALLBACK;
+    }
+  }
+  HIP_TRY(B.grp_inst.alloc(sizeof(int32_t) * B.ngroups));
+  HIP_TRY(B.blk_inst.alloc(sizeof(int32_t) * B.nblocks));
+  HIP_TRY(B.blk_local.alloc(sizeof(int32_t) * B.nblocks));
+  HIP_TRY(B.inst_rows.alloc(sizeof(int32_t) * B.n));
+  HIP_TRY(B.inst_r0.alloc(sizeof(int32_t) * B.n));
+  HIP_TRY(B.ss.alloc(sizeof(StepScratch) * B.n));
+  HIP_TRY(B.states.alloc(sizeof(SP2State) * B.n));
+  HIP_TRY(B.cfgs.alloc(sizeof(SP2Cfg) * B.n));
+  HIP_TRY(B.hists.alloc(sizeof(SP2Hist) * B.n));
+  HIP_TRY(B.taus64.alloc(sizeof(double) * B.n));
+  HIP_TRY(B.taus32.alloc(sizeof(float) * B.n));
+  HIP_TRY(hipMemcpyAsync(B.grp_inst.p, gi.data(), sizeof(int32_t) * B.ngroups, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.blk_inst.p, bi.data(), sizeof(int32_t) * B.nblocks, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.blk_local.p, bl.data(), sizeof(int32_t) * B.nblocks, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.inst_rows.p, ir.data(), sizeof(int32_t) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.inst_r0.p, i0.data(), sizeof(int32_t) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.ss.p, vs.data(), sizeof(StepScratch) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.cfgs.p, vc.data(), sizeof(SP2Cfg) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.hists.p, vh.data(), sizeof(SP2Hist) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.taus64.p, t64.data(), sizeof(double) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.taus32.p, t32.data(), sizeof(float) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(B.states.p, B.hs, sizeof(SP2State) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  // ---- the loop: graphs of K iterations, K picked by timing the first replays ----
+  int64_t max_iter_all = 0;
+  for (const BatchInst &I : B.in) max_iter_all = std::max<int64_t>(max_iter_all, p[I.q].max_iter);
+  const int poll_hint = p[B.in[0].q].poll_every;
+  const int candidates[] = {2, 4, 8, 16};
+  int K = poll_hint > 0 ? poll_hint : 0;  // 0: autotune
+  int tune = 0;
+  double best = 0.0;
+  int bestK = 4;
+  hipEvent_t ta = nullptr, tb = nullptr;
+  struct Ev2 {
+    hipEvent_t &a, &b;
+    ~Ev2()
+    {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev2{ta, tb};
+  HIP_TRY(hipEventCreate(&ta));
+  HIP_TRY(hipEventCreate(&tb));
+  const int64_t max_batches = max_iter_all + 128;
+  for (int64_t batch = 0;; ++batch) {
+    if (batch > max_batches) {
+      g_last_error = "sp2_solve_batched: device control blocks did not reach a stop";
+      return ELL_EDEVICE;
+    }
+    bool running = false;
+    for (int m = 0; m < B.n; ++m) running = running || !B.hs[m].stop;
+    if (!running) break;
+    const bool tuning = K == 0 && tune < 4;
+    const int iters = K > 0 ? K : (tuning ? candidates[tune] : bestK);
+    if (!B.exec || B.graph_iters != iters) {
+      int rc = B.capture(iters);
+      if (rc) return rc;
+    }
+    std::vector<int> before(B.n);
+    for (int m = 0; m < B.n; ++m) before[m] = B.hs[m].iter;
+    HIP_TRY(hipEventRecord(ta, st));
+    HIP_TRY(hipGraphLaunch(B.exec, st));
+    HIP_TRY(hipEventRecord(tb, st));
+    HIP_TRY(hipMemcpyAsync(B.hs, B.states.p, sizeof(SP2State) * B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tuning) {
+      int adv = 0;
+      for (int m = 0; m < B.n; ++m) adv = std::max(adv, B.hs[m].iter - before[m]);
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ta, tb));
+      if (adv == iters) {  // every iteration of the graph did work: a fair sample
+        const double per = ms / iters;
+        if (tune == 0 || per < best) {
+          best = per;
+          bestK = iters;
+        }
+      }
+      ++tune;
+    }
+    // events of stopped instances
+    bool dirty = false;
+    int32_t need = 0;
+    for (int m = 0; m < B.n; ++m) {
+      SP2State &h = B.hs[m];
+      if (!h.stop || h.status != ELL_EOVERFLOW) continue;
+      need = std::max(need, h.need_width);
+    }
+    if (need > 0) {
+      const int32_t nsw = roundup64(need);
+      if (nsw > kMaxCap) {
+        for (int m = 0; m < B.n; ++m)
+          if (B.hs[m].stop && B.hs[m].status == ELL_EOVERFLOW) {
+            B.in[m].solo = true;
+            B.hs[m].status = ST_FALLBACK;
+          }
+      } else {
+        int rc = batch_regrow(B, nsw);
+        if (rc) return rc;
+        for (int m = 0; m < B.n; ++m)
+          if (B.hs[m].stop && B.hs[m].status == ELL_EOVERFLOW) {
+            B.hs[m].stop = 0;
+            B.hs[m].status = ST_RUNNING;
+          }
+      }
+      dirty = true;
+    }
+    for (int m = 0; m < B.n; ++m) {
+      SP2State &h = B.hs[m];
+      if (!h.stop) continue;
+      if (h.status == ST_SWITCH) {
+        const BatchInst &I = B.in[m];
+        HIP_TRY((launch_span_copy<float, double>(I.N, B.rows(B.A32, h.cur, I), B.rows(B.A64, 0, I), st)));
+        h.cur = 0;
+        h.phase32 = 0;
+        h.stop = 0;
+        h.status = ST_RUNNING;
+        dirty = true;
+      } else if (h.status == ST_FALLBACK) {
+        B.in[m].solo = true;
+      }
+    }
+    if (dirty) {
+      HIP_TRY(hipMemcpyAsync(B.states.p, B.hs, sizeof(SP2State) * B.n, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+  }
+  HIP_TRY(hipEventRecord(t1, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float batch_ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&batch_ms, t0, t1));
+
+  // ---- results ----
+  std::vector<double> va(HT), vb(HT), vcc(HT);
+  std::vector<int8_t> vu(HT), vp(HT);
+  std::vector<int32_t> vw(HT);
+  std::vector<int64_t> vx(HT), vy(HT);
+  HIP_TRY(hipMemcpyAsync(va.data(), B.h_trx.p, sizeof(double) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vb.data(), B.h_trx2.p, sizeof(double) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vcc.data(), B.h_eta2.p, sizeof(double) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vu.data(), B.h_up.p, HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vp.data(), B.h_prec.p, HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vw.data(), B.h_maxw.p, sizeof(int32_t) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vx.data(), B.h_nnzx.p, sizeof(int64_t) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(vy.data(), B.h_nnzy.p, sizeof(int64_t) * HT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  DevMem dw;
+  HIP_TRY(dw.alloc(sizeof(int32_t)));
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    if (I.solo) continue;
+    const SP2State &h = B.hs[m];
+    int32_t width = 0;
+    int rc = h.phase32 ? batch_deliver<float>(B, B.A32, m, D[I.q], dw, &width)
+                       : batch_deliver<double>(B, B.A64, m, D[I.q], dw, &width);
+    const int status = rc ? rc : h.status;
+    note(status);
+    if (!r) continue;
+    sp2_report_t &R = r[I.q];
+    R.status = status;
+    R.iterations = h.iter;
+    R.final_M = rc == ELL_EOVERFLOW ? width : B.SW;
+    R.eta = std::sqrt(h.eta2);
+    R.trace_x = h.trx;
+    R.seconds = batch_ms * 1e-3;
+    int f32 = 0;
+    int64_t bytes = 0;
+    for (int q = 0; q < h.iter; ++q) {
+      const size_t o = (size_t)I.hoff + q;
+      f32 += vp[o] ? 1 : 0;
+      if (R.hist_trx) R.hist_trx[q] = va[o];
+      if (R.hist_trx2) R.hist_trx2[q] = vb[o];
+      if (R.hist_eta2) R.hist_eta2[q] = vcc[o];
+      if (R.hist_up) R.hist_up[q] = vu[o];
+      if (R.hist_prec) R.hist_prec[q] = vp[o];
+      if (R.hist_maxw) R.hist_maxw[q] = vw[o];
+      const int64_t sv = vp[o] ? 4 : 8;
+      bytes += vx[o] * (sv + 4) + 4LL * I.N + vy[o] * (sv + 4) + 4LL * I.N;
+    }
+    R.fp32_iterations = f32;
+    R.x2_bytes = bytes;
+  }
+  // instances the batch could not hold, each on its own
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    if (!I.solo) continue;
+    const int rc = sp2_solve(H[I.q], D[I.q], &p[I.q], r ? &r[I.q] : nullptr);
+    note(rc);
   }
   return worst;
 }

@@ -28,7 +28,7 @@ namespace ellsp2 {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kG = 8;           // output rows per wave
+constexpr int kG = kGroupRows;  // output rows per wave
 constexpr int kWavesPerBlock = 4;
 constexpr int kCP = 4;          // 64-column chunks accumulated per pass
 constexpr int kKQ = 4;          // rows k held in registers per group: 64 kKQ
@@ -488,6 +488,44 @@ __global__ __launch_bounds__(256) void k_x2_band(int N, SpanRot3<T> spans, Rot3<
                                           ells.b[cu], tau, s, bsum_s[w], fallback);
 }
 
+// Batched form: the instances' rows are stacked in one span matrix, instance m
+// from row r0[m] (a multiple of kG), with its own local column numbers.  Row
+// group grp belongs to instance grp_inst[grp]; the wave works on that instance's
+// rows as a matrix of its own (views shifted by r0), so every row, its column
+// blocks and the norm's tree see exactly the coordinates of a single solve.
+// The instance's state selects the buffers, whether it still runs, and its
+// precision; the launch for one precision skips instances in the other.
+template <typename T>
+__device__ __forceinline__ SpanView<T> shift_rows(SpanView<T> v, int r0)
+{
+  v.val += (size_t)r0 * v.SW;
+  v.base += r0;
+  v.len += r0;
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst,
+                                                       const int32_t *inst_r0, const int32_t *inst_rows,
+                                                       const SP2State *states, int32_t phase32, const T *taus,
+                                                       const StepScratch *ss, int32_t *flags)
+{
+  __shared__ double bsum_s[kWavesPerBlock][kG * kNormBlocks];
+  const int w = uni(threadIdx.x >> 6);
+  const int grp = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  if (grp >= ngroups) return;
+  const int m = uni(grp_inst[grp]);
+  const SP2State *st = states + m;
+  if (st->stop || st->phase32 != phase32) return;
+  const int cur = uni(st->cur);
+  const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
+  const int r0 = uni(inst_r0[m]), n = uni(inst_rows[m]);
+  const int i0 = grp * kG - r0;
+  const EllView<T> none{nullptr, nullptr, nullptr, 0};
+  band_rows<T, true, false, true>(n, i0, min(kG, n - i0), shift_rows(spans.b[cur], r0), shift_rows(spans.b[cy], r0),
+                                  shift_rows(spans.b[cu], r0), none, none, taus[m], ss[m], bsum_s[w], flags + m);
+}
+
 // ---- conversions between ELLPACK and span form -----------------------------------------
 
 // Interval length of every row of an ELLPACK matrix, and a flag if any stored
@@ -613,6 +651,23 @@ template hipError_t launch_x2_band<double>(int, SpanRot3<double>, Rot3<double>, 
                                            double, const StepScratch &, int32_t *, hipStream_t);
 template hipError_t launch_x2_band<float>(int, SpanRot3<float>, Rot3<float>, const SP2State *, bool, bool, float,
                                           const StepScratch &, int32_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
+                                const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
+                                const StepScratch *ss, int32_t *flags, hipStream_t stream)
+{
+  const dim3 grid((ngroups + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
+  hipLaunchKernelGGL((k_x2_band_batch<T>), grid, block, 0, stream, ngroups, spans, grp_inst, inst_r0, inst_rows,
+                     states, phase32, taus, ss, flags);
+  return hipGetLastError();
+}
+template hipError_t launch_x2_band_batch<double>(int, SpanRot3<double>, const int32_t *, const int32_t *,
+                                                 const int32_t *, const SP2State *, int32_t, const double *,
+                                                 const StepScratch *, int32_t *, hipStream_t);
+template hipError_t launch_x2_band_batch<float>(int, SpanRot3<float>, const int32_t *, const int32_t *,
+                                                const int32_t *, const SP2State *, int32_t, const float *,
+                                                const StepScratch *, int32_t *, hipStream_t);
 
 template <typename T>
 hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream)

@@ -112,6 +112,12 @@ hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStr
 hipError_t launch_decide(SP2State *st, SP2Cfg cfg, SP2Hist hist, const StepScratch &s,
                          hipStream_t stream);
 hipError_t launch_final_only(const StepScratch &s, hipStream_t stream);
+// batched: nblocks reduction blocks over all instances; one decision block per instance
+hipError_t launch_reduce_batch(int nblocks, const int32_t *blk_inst, const int32_t *blk_local,
+                               const int32_t *inst_rows, const StepScratch *ss, const SP2State *states,
+                               hipStream_t stream);
+hipError_t launch_decide_batch(int n, SP2State *states, const SP2Cfg *cfgs, const SP2Hist *hists,
+                               const StepScratch *ss, hipStream_t stream);
 
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi,
                              double *emin_emax, int32_t *flags, hipStream_t stream);
@@ -136,6 +142,14 @@ template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
 template <typename TS, typename TD>
 hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream);
+// batched step: ngroups groups of kG rows; group -> instance; instance m's rows
+// start at inst_r0[m] and it has inst_rows[m] of them (local columns); per-instance
+// state, drop tolerance, row-output scratch view and fallback flag
+template <typename T>
+hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
+                                const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
+                                const StepScratch *ss, int32_t *flags, hipStream_t stream);
+constexpr int kGroupRows = 8;  // rows per wavefront of the span step kernel (instance alignment in a batch)
 template <typename TS, typename TD>
 hipError_t launch_span_copy(int N, SpanView<TS> S, SpanView<TD> D, hipStream_t stream);
 

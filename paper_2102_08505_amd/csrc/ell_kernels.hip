@@ -401,13 +401,14 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
 // --------------------------------------------------------------------------
 // deterministic reductions of the step outputs
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st, StepScratch s)
+// Partial sums of 1024 rows (block b of a matrix with N rows): perfect trees of
+// d1, d2, e; maxima of the widths and interval lengths; nnz totals.
+__device__ void step_partial(const int N, const StepScratch &s, const int b)
 {
   __shared__ double ws[4];
   __shared__ int32_t wsi[4][4];
   __shared__ long long wsl[2][4];
-  if (st && st->stop) return;
-  const int base = blockIdx.x * kRedBlock + threadIdx.x * 4;
+  const int base = b * kRedBlock + threadIdx.x * 4;
   double a[3][4];
   int32_t mx[4] = {0, 0, 0, 0};
   long long sy = 0, su = 0;
@@ -441,12 +442,29 @@ __global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st,
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int c = 0; c < 3; ++c) s.part[c * s.nb + blockIdx.x] = t[c];
+    for (int c = 0; c < 3; ++c) s.part[c * s.nb + b] = t[c];
     for (int c = 0; c < 4; ++c)
-      s.partw[c * s.nb + blockIdx.x] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
-    s.partn[blockIdx.x] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
-    s.partn[s.nb + blockIdx.x] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
+      s.partw[c * s.nb + b] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
+    s.partn[b] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
+    s.partn[s.nb + b] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
   }
+}
+
+__global__ __launch_bounds__(256) void k_step_partial(int N, const SP2State *st, StepScratch s)
+{
+  if (st && st->stop) return;
+  step_partial(N, s, blockIdx.x);
+}
+
+// Batched form: launch block b reduces block blk_local[b] of instance blk_inst[b],
+// with that instance's row count, scratch view and state.
+__global__ __launch_bounds__(256) void k_step_partial_batch(const int32_t *blk_inst, const int32_t *blk_local,
+                                                            const int32_t *inst_rows, const StepScratch *ss,
+                                                            const SP2State *states)
+{
+  const int m = blk_inst[blockIdx.x];
+  if (states[m].stop) return;
+  step_partial(inst_rows[m], ss[m], blk_local[blockIdx.x]);
 }
 
 // Final level: perfect tree over the nb partials (padded with -0.0, the exact
@@ -560,6 +578,18 @@ __global__ __launch_bounds__(256) void k_step_final(SP2State *st, SP2Cfg cfg, SP
   final_reduce(s, ws);
   __syncthreads();
   if (st && threadIdx.x == 0) decide(st, cfg, h, s);
+}
+
+// Batched form: block m finishes the reductions of instance m and takes its decision.
+__global__ __launch_bounds__(256) void k_step_final_batch(SP2State *states, const SP2Cfg *cfgs, const SP2Hist *hists,
+                                                          const StepScratch *ss)
+{
+  __shared__ double ws[4];
+  const int m = blockIdx.x;
+  if (states[m].stop) return;
+  final_reduce(ss[m], ws);
+  __syncthreads();
+  if (threadIdx.x == 0) decide(&states[m], cfgs[m], hists[m], ss[m]);
 }
 
 // --------------------------------------------------------------------------
@@ -753,6 +783,22 @@ hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStr
 hipError_t launch_decide(SP2State *st, SP2Cfg cfg, SP2Hist hist, const StepScratch &s, hipStream_t stream)
 {
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(256), 0, stream, st, cfg, hist, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(int nblocks, const int32_t *blk_inst, const int32_t *blk_local,
+                               const int32_t *inst_rows, const StepScratch *ss, const SP2State *states,
+                               hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_step_partial_batch, dim3(nblocks), dim3(256), 0, stream, blk_inst, blk_local, inst_rows, ss,
+                     states);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_batch(int n, SP2State *states, const SP2Cfg *cfgs, const SP2Hist *hists,
+                               const StepScratch *ss, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_step_final_batch, dim3(n), dim3(256), 0, stream, states, cfgs, hists, ss);
   return hipGetLastError();
 }
 

@@ -243,17 +243,22 @@ def sp2_solve(H, D, params, history=True):
 
 
 def sp2_solve_batched(Hs, Ds, params, history=True):
+    """params: one SP2Params for every instance, or a list of n."""
     n = len(Hs)
     Ha = (vp * n)(*[h.value if isinstance(h, vp) else h for h in Hs])
     Da = (vp * n)(*[d.value if isinstance(d, vp) else d for d in Ds])
+    plist = list(params) if isinstance(params, (list, tuple)) else [params] * n
+    if len(plist) != n:
+        raise ValueError("one parameter set per instance")
+    pa = (SP2Params * max(n, 1))(*plist)
     reps = (SP2Report * n)()
     hs = []
     for q in range(n):
-        h = _Hist(params.max_iter) if history else None
+        h = _Hist(plist[q].max_iter) if history else None
         if h is not None:
             h.attach(reps[q])
         hs.append(h)
-    rc = load().sp2_solve_batched(n, Ha, Da, C.byref(params), reps)
+    rc = load().sp2_solve_batched(n, Ha, Da, pa, reps)
     return rc, [_report(reps[q], hs[q]) for q in range(n)]
 
 

@@ -1,0 +1,152 @@
+"""Batched SP2 (many Hamiltonians of uneven size in one stacked solve, replayed
+from a captured HIP graph) against sp2_solve on each instance alone, and for
+small instances against the oracle: results, histories and statuses must be
+bit-identical, since every row's arithmetic and every instance's reductions
+are the same."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_08505_amd import ellsp2 as E
+from paper_2102_08505_amd import synth
+from tests.gpu_helpers import assert_same_rows, oracle_from_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(N, tau, target, mixed=False, max_iter=100, poll=4, n_occ=None):
+    return E.sp2_params(N // 4 if n_occ is None else n_occ, tau, target, max_iter=max_iter,
+                        precision=E.SP2_MIXED if mixed else E.SP2_F64, tau_fp32=1e-7, switch_eta=1e-3,
+                        poll_every=poll)
+
+
+def _instances(specs):
+    """specs: (N, b, seed) -> host ELLPACK arrays."""
+    out = []
+    for N, b, seed in specs:
+        nnz, idx, val, M = synth.banded_hamiltonian(N, b, seed=seed, stream=seed)
+        out.append((N, M, nnz, idx, val))
+    return out
+
+
+def _same_report(a, b):
+    assert a["status"] == b["status"]
+    assert a["iterations"] == b["iterations"]
+    assert a["fp32_iterations"] == b["fp32_iterations"]
+    for k in ("trx", "trx2", "eta2"):
+        assert np.array_equal(a[k].view(np.uint64), b[k].view(np.uint64)), k
+    for k in ("up", "prec", "maxw"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["emin"] == b["emin"] and a["emax"] == b["emax"]
+
+
+def _run(inst, params, M=64, poll=4):
+    Hs = [E.DeviceEll.from_host(N, Mh, nnz, idx, val) for (N, Mh, nnz, idx, val) in inst]
+    Db = [E.DeviceEll(N, M) for (N, *_rest) in inst]
+    rc_b, reps_b = E.sp2_solve_batched([h.h for h in Hs], [d.h for d in Db], params)
+    singles = []
+    for q, (N, *_rest) in enumerate(inst):
+        Ds = E.DeviceEll(N, M)
+        rc, rep = E.sp2_solve(Hs[q].h, Ds.h, params[q])
+        singles.append((rc, rep, Ds))
+    return rc_b, reps_b, Db, singles, Hs
+
+
+def _check(rc_b, reps_b, Db, singles):
+    worst = 0
+    for q, (rc, rep, Ds) in enumerate(singles):
+        assert reps_b[q]["status"] == rc, (q, reps_b[q]["status"], rc)
+        if rc in (E.ELL_OK, E.ELL_ENOCONV):
+            _same_report(reps_b[q], rep)
+            assert_same_rows(oracle_from_dev(Db[q]), oracle_from_dev(Ds), f"D[{q}]")
+        if rc != 0 and (worst == 0 or rc < worst):
+            worst = rc
+    assert rc_b == worst
+
+
+def test_batched_fp64_uneven_sizes_equal_single_solves():
+    specs = [(64, 4, 1), (100, 4, 2), (257, 8, 3), (300, 9, 4), (513, 16, 5), (1000, 31, 6), (77, 4, 7),
+             (1500, 46, 8), (2048, 64, 9), (130, 4, 10)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-5 if q % 2 else 1e-8, 1e-6) for q, (N, *_r) in enumerate(inst)]
+    _check(*_run(inst, params)[:4])
+
+
+def test_batched_small_instances_match_the_oracle():
+    specs = [(64, 4, 11), (96, 4, 12), (200, 6, 13)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-9, 1e-8) for (N, *_r) in inst]
+    rc_b, reps_b, Db, singles, Hs = _run(inst, params)
+    for q, (N, Mh, nnz, idx, val) in enumerate(inst):
+        po = oracle.make_params(N // 4, 1e-9, 1e-8, max_iter=100, tau_fp32=1e-7, switch_eta=1e-3)
+        rc_o, Do, ro = oracle.sp2(oracle.Ell(N, Mh, nnz, idx, val), po, Mo=N)
+        assert reps_b[q]["status"] == rc_o == E.ELL_OK
+        for k in ("trx", "trx2", "eta2"):
+            assert np.array_equal(reps_b[q][k].view(np.uint64), ro[k].view(np.uint64)), k
+        assert np.array_equal(reps_b[q]["up"], ro["up"])
+        assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
+
+
+def test_batched_mixed_and_fp64_instances_together():
+    specs = [(128, 4, 21), (256, 8, 22), (512, 16, 23), (700, 21, 24), (64, 4, 25)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-9, 1e-7, mixed=(q % 2 == 0)) for q, (N, *_r) in enumerate(inst)]
+    rc_b, reps_b, Db, singles, _ = _run(inst, params)
+    _check(rc_b, reps_b, Db, singles)
+    assert any(r["fp32_iterations"] > 0 for r in reps_b)
+
+
+def test_batched_stride_growth_and_autotuned_graph_length():
+    """tau = 0 on N = 300 fills rows to 300 columns, past the first stride, so
+    the whole stack is re-laid out mid-solve; poll 0 lets the solver time graph
+    lengths on the first replays."""
+    specs = [(300, 6, 31), (200, 6, 32), (90, 4, 33)]
+    inst = _instances(specs)
+    params = [_params(300, 0.0, 1e-9, max_iter=200, poll=0), _params(200, 1e-8, 1e-6, poll=0),
+              _params(90, 1e-5, 1e-8, poll=0)]
+    rc_b, reps_b, Db, singles, _ = _run(inst, params, M=32)
+    _check(rc_b, reps_b, Db, singles)
+    assert reps_b[0]["final_M"] >= 300
+
+
+def test_batched_instances_that_leave_the_stack():
+    """A degenerate occupation, an instance that needs the ELLPACK kernels (a
+    coupling 890 columns away) and ordinary instances in one call."""
+    N = 1024
+    nnz, idx, val, M = synth.banded_hamiltonian(N, 4, seed=7)
+    D = synth.ell_to_dense(N, M, nnz, idx, val)
+    D[10, 900] = D[900, 10] = 0.3
+    nz2, ix2, va2, M2 = synth.dense_to_ell(D)
+    inst = [(N, M2, nz2, ix2, va2)] + _instances([(128, 4, 41), (256, 8, 42)])
+    params = [_params(N, 1e-7, 1e-6, max_iter=120), _params(128, 1e-8, 1e-6, n_occ=128),
+              _params(256, 1e-8, 1e-6)]
+    rc_b, reps_b, Db, singles, _ = _run(inst, params)
+    assert reps_b[1]["status"] == E.ELL_EDEGENERATE
+    _check(rc_b, reps_b, Db, singles)
+
+
+def test_batched_empty_and_argument_errors():
+    rc, reps = E.sp2_solve_batched([], [], [])
+    assert rc == E.ELL_OK and reps == []
+    inst = _instances([(64, 4, 51)])
+    H = E.DeviceEll.from_host(*inst[0])
+    Dd = E.DeviceEll(64, 32)
+    with pytest.raises(ValueError):
+        E.sp2_solve_batched([H.h], [Dd.h], [_params(64, 1e-5, 1e-6)] * 2)
+    rc, _ = E.sp2_solve_batched([H.h, H.h], [Dd.h, Dd.h], _params(64, 1e-5, 1e-6))
+    assert rc == E.ELL_EINVAL  # the same result handle twice
+
+
+def test_batched_256_instance_workload_sample_equals_single():
+    """The batched benchmark workload (256 instances, N uniform in 64..2048,
+    half-bandwidth max(4, N/32), FP32 phase then FP64): every instance equals
+    its single solve."""
+    specs = synth.batched_instances(256, seed=0)
+    inst = []
+    for q, (N, b) in enumerate(specs):
+        nnz, idx, val, M = synth.banded_hamiltonian(N, b, seed=0, stream=q)
+        inst.append((N, M, nnz, idx, val))
+    params = [_params(N, 1e-9, 1e-6, mixed=True) for (N, *_r) in inst]
+    rc_b, reps_b, Db, singles, _ = _run(inst, params)
+    _check(rc_b, reps_b, Db, singles)
+    assert all(r["status"] == E.ELL_OK for r in reps_b)
