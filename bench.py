@@ -116,7 +116,7 @@ def batched_leg(E, synth, torch, count=256):
         Hs.append(E.DeviceEll.from_host(n, m, nnz, idx, val))
         Db.append(E.DeviceEll(n, 4 * b))
         Ds.append(E.DeviceEll(n, 4 * b))
-        ps.append(E.sp2_params(n / 4, TAU_MIXED64, TARGET, max_iter=200, precision=E.SP2_MIXED,
+        ps.append(E.sp2_params(n // 4, TAU_MIXED64, TARGET, max_iter=200, precision=E.SP2_MIXED,
                                tau_fp32=TAU_FP32, switch_eta=SWITCH_ETA, poll_every=0))
     hh, hb = [h.h for h in Hs], [d.h for d in Db]
     E.sp2_solve_batched(hh, hb, ps, history=False)  # warm-up
