@@ -71,8 +71,8 @@ def cpu_baseline(nnz, idx, val, M, seconds_budget=20.0):
                       f"same N={N} b={B} tau={TAU:g} workload, {calls} calls, {total_s:.1f} s"}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "x2_band_f64_n32768_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_08505_amd", "csrc", "ell_band.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "x2_band16_f64_n32768_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_08505_amd", "csrc", "ell_band16.hip")
 
 
 def measured_traffic():
@@ -270,7 +270,7 @@ def main():
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_x2_band<double, true, false, true> (fused X^2, prune, traces, norm, "
+                     "kernel": "k_x2_band16 (fused X^2 on FP64 matrix cores, prune, traces, norm, "
                                "2X - X^2 on the span form)",
                      "bytes_per_launch": x2_bytes / launches},
     }

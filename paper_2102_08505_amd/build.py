@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libellsp2.so")
-SOURCES = ["ell_api.hip", "ell_kernels.hip", "ell_band.hip", "dense.hip"]
+SOURCES = ["ell_api.hip", "ell_kernels.hip", "ell_band.hip", "ell_band16.hip", "dense.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -24,6 +24,10 @@ HIPCC_FLAGS = [
     "-Wall",
 ]
 
+# The matrix-core band kernel keeps its accumulators in VGPRs: with the
+# compiler's AGPR choice they are copied between the two files every step.
+EXTRA_FLAGS = {"ell_band16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def build(verbose=False, jobs=4):
     hipcc = os.environ.get("HIPCC", "hipcc")
@@ -32,7 +36,7 @@ def build(verbose=False, jobs=4):
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, cwd=CSRC, stderr=subprocess.PIPE, text=True), src))

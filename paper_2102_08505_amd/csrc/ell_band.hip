@@ -20,14 +20,17 @@
 // touches memory until the row is complete.
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
+#include "band_common.h"
 #include "ell_internal.h"
 #include "../../include/ellsp2.h"
 
 namespace ellsp2 {
 namespace {
 
-constexpr int kWave = 64;
+using namespace band;
+
 constexpr int kG = kGroupRows;  // output rows per wave
 constexpr int kWavesPerBlock = 4;
 constexpr int kCP = 4;          // 64-column chunks accumulated per pass
@@ -35,45 +38,10 @@ constexpr int kKQ = 4;          // rows k held in registers per group: 64 kKQ
 constexpr int kNormBlocks = 128;  // aligned 64-column blocks per row in the norm table
 constexpr int kMaxChunks = 64;    // widest output window: 64 chunks of 64 columns
 
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int lanes_below(uint64_t m)
-{
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-__device__ __forceinline__ void wave_sync()
-{
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-__device__ __forceinline__ int wmin(int v)
-{
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-  return v;
-}
-__device__ __forceinline__ int wmax(int v)
-{
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-  return v;
-}
-__device__ __forceinline__ double wave_tree(double v)
-{
-  for (int s = 1; s < kWave; s <<= 1) v = v + __shfl_down(v, s, kWave);
-  return v;
-}
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double absv(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float absv(float a) { return __builtin_fabsf(a); }
-
-__device__ __forceinline__ int xcd_block(int b, int nblocks)
-{
-  constexpr int kXcd = 8;
-  const int per = nblocks / kXcd;
-  const int full = per * kXcd;
-  if (b >= full) return b;
-  return (b % kXcd) * per + b / kXcd;
-}
 
 // X's values are never written while the kernel runs (X^2 and 2X - X^2 go to
 // the other two buffers), so the row values X[i_g][k] -- the same for every
@@ -91,8 +59,6 @@ __device__ __forceinline__ int sload_i(const int32_t *p, int off) { return ((con
 // Raw buffer loads of row k of X: the buffer's range is exactly row k's
 // interval, so lanes whose column lies outside it (either side: a negative
 // byte offset wraps to a huge unsigned one) read 0 without any masking code.
-constexpr int kRawBufferFlags = 0x00020000;  // 32-bit raw buffer, gfx9 family
-
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T *row, int len)
 {
@@ -642,6 +608,9 @@ hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State
       hipLaunchKernelGGL((k_x2_band<T, false, true, false>), grid, block, 0, stream, N, spans, ells, st, tau, s,
                          fallback);
   } else {
+    if constexpr (std::is_same<T, double>::value) {
+      if (x2_band16_fits(N, spans.b[0].SW)) return launch_x2_band16(N, spans, st, tau, s, fallback, stream);
+    }
     hipLaunchKernelGGL((k_x2_band<T, true, false, true>), grid, block, 0, stream, N, spans, ells, st, tau, s,
                        fallback);
   }

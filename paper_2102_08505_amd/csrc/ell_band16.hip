@@ -1,0 +1,397 @@
+// FP64 X^2 of span-form matrices on the matrix cores: the product, pruning,
+// and per-row outputs of every FP64 SP2 iteration (the X^2 step of the SP2
+// algorithm of the paper's SP2 section, on the thresholded sparse product of
+// its ELLPACK section).
+//
+// In span form row i of X is stored densely over the columns
+// [base[i], base[i] + len[i]) at val[i*SW ...], with zeros at the pruned
+// positions inside the interval.  Around the diagonal, X^2 is then a product of
+// narrow dense strips.  One wavefront computes 16 consecutive output rows.  Its
+// window of output columns is cut into aligned 64-column blocks; each block is
+// four 16x16 tiles, accumulated with v_mfma_f64_16x16x4_f64 over the rows k whose
+// interval meets the block, k ascending four at a time.
+//
+// The FP64 matrix instruction forms each element as a chain of fused
+// multiply-adds in ascending k (k = 0..3 inside one instruction, instructions
+// issued in ascending k): the chain of the row-by-row sparse product.
+// Positions outside an interval enter as exact zeros and a zero product leaves
+// the accumulator unchanged, so every entry of X^2 has the bits of the sparse
+// product's ascending-k chain over the entries that exist.
+//
+// The sweep of a block -- threshold, span output of X^2 and 2X - X^2, the
+// norm's squared differences -- works in the tile layout: lane l holds column
+// l % 16 of rows l / 16 + 4 t (t = 0..3), so a row's 16 columns of one tile are
+// one 16-lane row of the wavefront.
+#include <climits>
+
+#include "band_common.h"
+#include "ell_internal.h"
+
+namespace ellsp2 {
+namespace {
+
+using namespace band;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kR = 16;                  // output rows per wave (the tile's rows)
+constexpr int kP = 4;                   // 16-column tiles per 64-column block
+constexpr int kWpb = 4;                 // waves per workgroup
+constexpr int kKQ = 4;                  // rows k whose intervals are held in registers: 64 kKQ
+constexpr int kMeta = kKQ * kWave;      // entries of the wave's LDS table of row intervals
+constexpr int kWin = 64;                // widest output window, in aligned 64-column blocks
+constexpr uint32_t kOob = 0x80000000u;  // byte offset past every buffer: loads give 0, stores are dropped
+
+__device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+  // The whole offset stays in the VGPR operand (no folding into the immediate
+  // or scalar offset fields, which the range check treats differently).
+  asm("" : "+v"(off));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+  asm("" : "+v"(off));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+// byte offset of element e when `ok`, else past the buffer
+__device__ __forceinline__ uint32_t at(bool ok, int e) { return ok ? (uint32_t)e * 8u : kOob; }
+
+// the 16 bits of a wave mask that belong to this lane's 16-lane row
+__device__ __forceinline__ uint32_t seg16(uint64_t m, int q) { return (uint32_t)(m >> (16 * q)) & 0xffffu; }
+
+// pairwise tree over the 16 lanes of a row; every lane of the row gets the total
+__device__ __forceinline__ double row_tree(double v)
+{
+  for (int m = 1; m < 16; m <<= 1) v = v + __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// Running output state of one row (first / last kept column, kept count).
+struct RowRun {
+  int first = INT_MAX, last = -1, count = 0;
+  __device__ void add(uint32_t seg, int c0)
+  {
+    count += __popc(seg);
+    const int f = seg ? c0 + __ffs(seg) - 1 : INT_MAX;
+    first = min(first, f);  // blocks come in ascending column order
+    last = seg ? c0 + 31 - __clz(seg) : last;
+  }
+  __device__ int length() const { return last >= 0 ? last - first + 1 : 0; }
+};
+
+// Accumulate one 64-column block: acc[p] += X[i0 .. i0+15][k] X[k][p0 + 16 p ..]
+// over k = klo .. khi, four k per step (a step past khi multiplies zeros).
+// A operand: lane (r, q) = (l % 16, l / 16) supplies X[i0 + r][k0 + q];
+// B operand: lane (r, q) supplies X[k0 + q][p0 + 16 p + r].
+// Two operand sets alternate: the loads of step k0 + 4 are in flight while
+// the products of step k0 issue.  Every load is range-checked (rows k past
+// khi have no entry in the block's columns, and rows k past kmax have an
+// empty interval in the table), so the step after the last needs no branch.
+template <bool LDS_META>
+__device__ __forceinline__ void mma_block(const SpanView<double> &X, const __amdgpu_buffer_rsrc_t xr,
+                                          const int2 *meta, const int kmin, const int kmax, const int klo,
+                                          const int khi, const int p0, const int arow, const int bA, const int lA,
+                                          f64x4 (&acc)[kP])
+{
+  const int lane = lane_id();
+  const int r = lane & 15, q = lane >> 4;
+  const int SW = X.SW;
+  auto interval = [&](int k0) {  // interval of row k0 + q
+    const int k = k0 + q;
+    int2 m;
+    if (LDS_META) {
+      m = meta[k - kmin];
+    } else {
+      const int kc = min(k, kmax);
+      m.x = X.base[kc];
+      m.y = k <= kmax ? X.len[kc] : 0;
+    }
+    return m;
+  };
+  auto load = [&](int k0, int2 m, double &a, double (&b)[kP]) {
+    const int k = k0 + q;
+    a = ld(xr, at((unsigned)(k - bA) < (unsigned)lA, arow + k));
+    const int brow = k * SW - m.x;
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+      const int col = p0 + 16 * p + r;
+      b[p] = ld(xr, at((unsigned)(col - m.x) < (unsigned)m.y, brow + col));
+    }
+  };
+  auto mma = [&](double a, const double (&b)[kP]) {
+#pragma unroll
+    for (int p = 0; p < kP; ++p) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p], acc[p], 0, 0, 0);
+  };
+  const int nsteps = (khi - klo) / 4 + 1;
+  double a0, b0[kP], a1, b1[kP];
+  load(klo, interval(klo), a0, b0);
+  int2 m1 = interval(klo + 4);
+  int k0 = klo;
+  // (the scheduling barriers keep each set's loads ahead of the other set's products)
+  for (int st2 = 0; st2 + 2 <= nsteps; st2 += 2, k0 += 8) {
+    load(k0 + 4, m1, a1, b1);
+    const int2 m0 = interval(k0 + 8);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(k0 + 8, m0, a0, b0);
+    m1 = interval(k0 + 12);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (nsteps & 1) mma(a0, b0);
+}
+
+// One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
+__device__ void rows16(const int N, const int i0, const int nrows, const SpanView<double> X,
+                       const SpanView<double> SY, const SpanView<double> SU, const double tau, const StepScratch &s,
+                       double *bsum, int2 *meta, int32_t *fallback)
+{
+  const int lane = lane_id();
+  const int r = lane & 15, q = lane >> 4;
+  // the three matrices share one row stride (they rotate roles every iteration)
+  const int SW = X.SW;
+  const int bytes = N * SW * 8;  // < 2^31: the launcher takes this kernel only then
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(X.val, (short)0, bytes, kRawBufferFlags);
+  const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(SY.val, (short)0, bytes, kRawBufferFlags);
+  const __amdgpu_buffer_rsrc_t ur = __builtin_amdgcn_make_buffer_rsrc(SU.val, (short)0, bytes, kRawBufferFlags);
+
+  // interval of row r (lane l holds row l % 16)
+  const int bA = r < nrows ? X.base[i0 + r] : 0;
+  const int lA = r < nrows ? X.len[i0 + r] : 0;
+  const int kmin = wmin(lA > 0 ? bA : INT_MAX);
+  const int kmax = wmax(lA > 0 ? bA + lA - 1 : -1);
+  if (kmax < 0) {
+    // every row of the group is empty, and so are its rows of X^2 and 2X - X^2
+    if (q == 0 && r < nrows) {
+      const int i = i0 + r;
+      SY.base[i] = 0;
+      SY.len[i] = 0;
+      SU.base[i] = 0;
+      SU.len[i] = 0;
+      s.wy[i] = 0;
+      s.wu[i] = 0;
+      if (s.ly) s.ly[i] = 0;
+      if (s.lu) s.lu[i] = 0;
+      s.d1[i] = 0.0;
+      s.d2[i] = 0.0;
+      s.e[i] = 0.0;
+    }
+    return;
+  }
+  // intervals of the rows k in [kmin, kmax], lane-distributed: k = kmin + 64 j + lane
+  int kbq[kKQ], klq[kKQ];
+#pragma unroll
+  for (int j = 0; j < kKQ; ++j) {
+    const int k = kmin + j * kWave + lane;
+    const bool ok = k <= kmax;
+    klq[j] = ok ? X.len[k] : 0;
+    kbq[j] = ok ? X.base[k] : 0;
+  }
+  // the table holds rows kmin .. kmin + kMeta - 1 (empty past kmax); the
+  // accumulation reads up to 15 rows past the last row k it uses
+  const bool kfit = kmax - kmin < kMeta - 16;
+  // output window: the rows' own intervals and every row k's interval, from
+  // an aligned 64-column block on
+  int wlo = kmin, whi = kmax;
+  if (kfit) {
+#pragma unroll
+    for (int j = 0; j < kKQ; ++j)
+      if (klq[j] > 0) {
+        wlo = min(wlo, kbq[j]);
+        whi = max(whi, kbq[j] + klq[j] - 1);
+      }
+  } else {
+    for (int k0 = kmin; k0 <= kmax; k0 += kWave) {
+      const int k = k0 + lane;
+      if (k <= kmax) {
+        const int l = X.len[k];
+        if (l > 0) {
+          wlo = min(wlo, X.base[k]);
+          whi = max(whi, X.base[k] + l - 1);
+        }
+      }
+    }
+  }
+  wlo = wmin(wlo) & ~63;
+  whi = wmax(whi);
+  const int nblk = (whi - wlo + kWave) / kWave;
+  if (nblk > kWin) {
+    if (lane == 0) atomicOr(fallback, 1);
+    return;
+  }
+  if (kfit) {
+#pragma unroll
+    for (int j = 0; j < kKQ; ++j) meta[j * kWave + lane] = make_int2(kbq[j], klq[j]);
+    wave_sync();
+  }
+
+  // this lane's output rows q + 4 t
+  int bC[4], lC[4], xrow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bC[t] = __shfl(bA, q + 4 * t, kWave);
+    lC[t] = __shfl(lA, q + 4 * t, kWave);
+    xrow[t] = (i0 + q + 4 * t) * SW - bC[t];
+  }
+  const int arow = (i0 + r) * SW - bA;
+  RowRun ry[4], ru[4];
+
+  for (int pc = 0; pc < nblk; ++pc) {
+    const int p0 = wlo + pc * kWave, p1 = p0 + kWave - 1;
+    // rows k whose interval meets the block
+    int klo = INT_MAX, khi = -1;
+    if (kfit) {
+#pragma unroll
+      for (int j = 0; j < kKQ; ++j) {
+        const uint64_t m = __ballot(klq[j] > 0 && kbq[j] <= p1 && kbq[j] + klq[j] - 1 >= p0);
+        if (m) {
+          klo = min(klo, kmin + j * kWave + (int)__builtin_ctzll(m));
+          khi = max(khi, kmin + j * kWave + 63 - (int)__builtin_clzll(m));
+        }
+      }
+    } else {
+      for (int k0 = kmin; k0 <= kmax; k0 += kWave) {
+        const int k = k0 + lane;
+        bool meet = false;
+        if (k <= kmax) {
+          const int l = X.len[k], b = X.base[k];
+          meet = l > 0 && b <= p1 && b + l - 1 >= p0;
+        }
+        const uint64_t m = __ballot(meet);
+        if (m) {
+          klo = min(klo, k0 + (int)__builtin_ctzll(m));
+          khi = max(khi, k0 + 63 - (int)__builtin_clzll(m));
+        }
+      }
+    }
+    klo = uni(klo);
+    khi = uni(khi);
+    f64x4 acc[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) acc[p] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if (klo <= khi) {
+      if (kfit) mma_block<true>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
+      else mma_block<false>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
+    }
+
+    // sweep the block, row quad by row quad
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rr = q + 4 * t;
+      const int i = i0 + rr;
+      const bool act = rr < nrows;
+      double tsum[kP];
+#pragma unroll
+      for (int p = 0; p < kP; ++p) {
+        const int c0 = p0 + 16 * p;
+        const int col = c0 + r;
+        const double y = acc[p][t];
+        const double x = ld(xr, at((unsigned)(col - bC[t]) < (unsigned)lC[t], xrow[t] + col));
+        if (act && col == i) {  // X_ii and the unpruned (X.X)_ii
+          s.d1[i] = x;
+          s.d2[i] = y;
+        }
+        const bool ky = act && __builtin_fabs(y) > tau;
+        const double yk = ky ? y : 0.0;
+        ry[t].add(seg16(__ballot(ky), q), c0);
+        {
+          const int o = col - ry[t].first;
+          st(yr, at(act && ry[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), yk);
+        }
+        const double v = 2.0 * x - yk;
+        const bool ku = act && __builtin_fabs(v) > tau;
+        ru[t].add(seg16(__ballot(ku), q), c0);
+        {
+          const int o = col - ru[t].first;
+          st(ur, at(act && ru[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), ku ? v : 0.0);
+        }
+        const double d = yk - x;
+        tsum[p] = row_tree(d * d);
+      }
+      // the aligned block's pairwise tree: levels 5 and 6 join the tiles
+      if (r == 0) bsum[rr * kWin + pc] = (tsum[0] + tsum[1]) + (tsum[2] + tsum[3]);
+    }
+  }
+  wave_sync();
+
+  // Norm row term: the pairwise tree over the 128 aligned blocks from b0 (two
+  // 64-block subtrees; every block outside the window holds 0).  Four lanes per
+  // row, 32 leaves each, then two butterfly levels.
+  {
+    const int row = lane >> 2, j = lane & 3;
+    const int sh = (wlo >> 6) - ((wlo >> 6) & ~63);  // window's first block within the 128
+    double v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int sl = 32 * j + u - sh;
+      const bool in = (unsigned)sl < (unsigned)nblk;
+      v[u] = in ? bsum[row * kWin + (in ? sl : 0)] : 0.0;
+    }
+#pragma unroll
+    for (int w = 1; w < 32; w <<= 1)
+#pragma unroll
+      for (int u = 0; u < 32; u += 2 * w) v[u] = v[u] + v[u + w];
+    double g = v[0];
+    g = g + __shfl_xor(g, 1, kWave);
+    g = g + __shfl_xor(g, 2, kWave);
+    if (j == 0 && row < nrows) s.e[i0 + row] = g;
+  }
+  if (r == 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rr = q + 4 * t;
+      if (rr >= nrows) break;
+      const int i = i0 + rr;
+      const int ylen = ry[t].length(), ulen = ru[t].length();
+      SY.base[i] = ylen ? ry[t].first : 0;
+      SY.len[i] = ylen;
+      SU.base[i] = ulen ? ru[t].first : 0;
+      SU.len[i] = ulen;
+      s.wy[i] = ry[t].count;
+      s.wu[i] = ru[t].count;
+      if (s.ly) s.ly[i] = ylen;
+      if (s.lu) s.lu[i] = ulen;
+      if (i < wlo || i >= wlo + nblk * kWave) {  // column i never swept
+        s.d1[i] = 0.0;
+        s.d2[i] = 0.0;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<double> spans, const SP2State *st, double tau,
+                                                   StepScratch s, int32_t *fallback)
+{
+  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ int2 meta_s[kWpb][kMeta];
+  int cur = 0;
+  if (st) {
+    if (st->stop) return;
+    cur = st->cur;
+  }
+  const int w = uni(threadIdx.x >> 6);
+  const int grp = xcd_block(blockIdx.x, gridDim.x) * kWpb + w;
+  const int i0 = grp * kR;
+  if (i0 >= N) return;
+  const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
+  rows16(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], meta_s[w], fallback);
+}
+
+}  // namespace
+
+bool x2_band16_fits(int N, int SW) { return (int64_t)N * SW * 8 < ((int64_t)1 << 31); }
+
+hipError_t launch_x2_band16(int N, SpanRot3<double> spans, const SP2State *st, double tau, const StepScratch &s,
+                            int32_t *fallback, hipStream_t stream)
+{
+  const int groups = (N + kR - 1) / kR;
+  const dim3 grid((groups + kWpb - 1) / kWpb), block(kWpb * kWave);
+  hipLaunchKernelGGL(k_x2_band16, grid, block, 0, stream, N, spans, st, tau, s, fallback);
+  return hipGetLastError();
+}
+
+}  // namespace ellsp2
