@@ -13,7 +13,6 @@
 #include <cstring>
 #include <new>
 #include <string>
-#include <type_traits>
 #include <vector>
 
 #include "../../include/ellsp2.h"
@@ -243,24 +242,25 @@ int finish_step(const ellpack *X, ellpack *Y, ellpack *U, const StepMem &m, doub
   return ELL_OK;
 }
 
-// FP64 step through the matrix-core band kernel: span form in and out, then
-// the rows of X^2 and 2X - X^2 compacted into the ELLPACK outputs.  Returns
+// Step through the matrix-core band kernel: span form in and out, then the
+// rows of X^2 and 2X - X^2 compacted into the ELLPACK outputs.  Returns
 // kNotTaken (nothing written to Y or U) when a row group's window or an output
 // interval does not fit the span stride.
 constexpr int kNotTaken = 1;
+template <typename T>
 int run_step_band16(const ellpack *X, ellpack *Y, ellpack *U, double tau, int32_t maxlen, StepMem &m, double out[3],
                     int32_t widths[2])
 {
   const int N = X->N;
   const int32_t sw = std::max<int32_t>(256, roundup64(std::min<int64_t>(N, 3 * (int64_t)maxlen)));
-  if (!x2_band16_fits(N, sw)) return kNotTaken;
-  SpanMem<double> sx, sy, su;
+  if (!x2_band16_fits(N, sw, (int)sizeof(T))) return kNotTaken;
+  SpanMem<T> sx, sy, su;
   HIP_TRY(sx.alloc(N, sw));
   HIP_TRY(sy.alloc(N, sw));
   HIP_TRY(su.alloc(N, sw));
-  HIP_TRY(launch_ell_to_span<double>(N, view<double>(X), sx.v(), X->stream));
-  const SpanRot3<double> spans{{sx.v(), sy.v(), su.v()}};  // X^2 to slot 1, 2X - X^2 to slot 2
-  HIP_TRY(launch_x2_band16(N, spans, nullptr, tau, m.s, m.s.flags, X->stream));
+  HIP_TRY(launch_ell_to_span<T>(N, view<T>(X), sx.v(), X->stream));
+  const SpanRot3<T> spans{{sx.v(), sy.v(), su.v()}};  // X^2 to slot 1, 2X - X^2 to slot 2
+  HIP_TRY(launch_x2_band16<T>(N, spans, nullptr, (T)tau, m.s, m.s.flags, X->stream));
   HIP_TRY(launch_reduce(N, nullptr, m.s, X->stream));
   HIP_TRY(launch_final_only(m.s, X->stream));
   int32_t fb = 0, w[4];
@@ -271,15 +271,15 @@ int run_step_band16(const ellpack *X, ellpack *Y, ellpack *U, double tau, int32_
     HIP_TRY(hipMemsetAsync(m.s.flags, 0, sizeof(int32_t), X->stream));
     return kNotTaken;
   }
-  HIP_TRY((launch_span_to_ell<double, double>(N, sy.v(), view<double>(Y), nullptr, X->stream)));
-  if (U) HIP_TRY((launch_span_to_ell<double, double>(N, su.v(), view<double>(U), nullptr, X->stream)));
-  return finish_step<double>(X, Y, U, m, out, widths);
+  HIP_TRY((launch_span_to_ell<T, T>(N, sy.v(), view<T>(Y), nullptr, X->stream)));
+  if (U) HIP_TRY((launch_span_to_ell<T, T>(N, su.v(), view<T>(U), nullptr, X->stream)));
+  return finish_step<T>(X, Y, U, m, out, widths);
 }
 
 // One fused step on ELLPACK handles.  Matrices whose rows are short intervals
-// go through the band kernels after an exact conversion to span form (FP64:
-// the matrix-core kernel; FP32: the register-tiled one); anything else, or a
-// row group whose window is too wide, through the LDS-window kernel.
+// go through a band kernel after an exact conversion to span form (the
+// matrix-core kernel, else the register-tiled one); anything else, or a row
+// group whose window is too wide, through the LDS-window kernel.
 template <typename T>
 int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
 {
@@ -293,10 +293,8 @@ int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3]
   int rc = ell_extent<T>(X, lens, &maxlen, &zeros);
   if (rc) return rc;
   if (!zeros && maxlen <= kMaxCap) {
-    if constexpr (std::is_same<T, double>::value) {
-      rc = run_step_band16(X, Y, U, tau, maxlen, m, out, widths);
-      if (rc != kNotTaken) return rc;
-    }
+    rc = run_step_band16<T>(X, Y, U, tau, maxlen, m, out, widths);
+    if (rc != kNotTaken) return rc;
     SpanMem<T> sx;
     HIP_TRY(sx.alloc(N, std::max(64, roundup64(maxlen))));
     HIP_TRY(launch_ell_to_span<T>(N, view<T>(X), sx.v(), X->stream));

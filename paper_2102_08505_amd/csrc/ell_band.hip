@@ -20,7 +20,6 @@
 // touches memory until the row is complete.
 #include <climits>
 #include <cmath>
-#include <type_traits>
 
 #include "band_common.h"
 #include "ell_internal.h"
@@ -608,9 +607,8 @@ hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State
       hipLaunchKernelGGL((k_x2_band<T, false, true, false>), grid, block, 0, stream, N, spans, ells, st, tau, s,
                          fallback);
   } else {
-    if constexpr (std::is_same<T, double>::value) {
-      if (x2_band16_fits(N, spans.b[0].SW)) return launch_x2_band16(N, spans, st, tau, s, fallback, stream);
-    }
+    if (x2_band16_fits(N, spans.b[0].SW, (int)sizeof(T)))
+      return launch_x2_band16<T>(N, spans, st, tau, s, fallback, stream);
     hipLaunchKernelGGL((k_x2_band<T, true, false, true>), grid, block, 0, stream, N, spans, ells, st, tau, s,
                        fallback);
   }

@@ -1,27 +1,30 @@
-// FP64 X^2 of span-form matrices on the matrix cores: the product, pruning,
-// and per-row outputs of every FP64 SP2 iteration (the X^2 step of the SP2
-// algorithm of the paper's SP2 section, on the thresholded sparse product of
-// its ELLPACK section).
+// X^2 of span-form matrices on the matrix cores, FP64 and FP32: the product,
+// pruning, and per-row outputs of every SP2 iteration (the X^2 step of the
+// SP2 algorithm of the paper's SP2 section, on the thresholded sparse product
+// of its ELLPACK section).
 //
 // In span form row i of X is stored densely over the columns
 // [base[i], base[i] + len[i]) at val[i*SW ...], with zeros at the pruned
 // positions inside the interval.  Around the diagonal, X^2 is then a product of
 // narrow dense strips.  One wavefront computes 16 consecutive output rows.  Its
 // window of output columns is cut into aligned 64-column blocks; each block is
-// four 16x16 tiles, accumulated with v_mfma_f64_16x16x4_f64 over the rows k whose
-// interval meets the block, k ascending four at a time.
+// four 16x16 tiles, accumulated with v_mfma_f64_16x16x4_f64 (FP32:
+// v_mfma_f32_16x16x4_f32) over the rows k whose interval meets the block, k
+// ascending four at a time.
 //
-// The FP64 matrix instruction forms each element as a chain of fused
-// multiply-adds in ascending k (k = 0..3 inside one instruction, instructions
-// issued in ascending k): the chain of the row-by-row sparse product.
+// Both matrix instructions form each element as a chain of fused multiply-adds
+// in ascending k, rounded to the working precision at every step (k = 0..3
+// inside one instruction, instructions issued in ascending k): the chain of the
+// row-by-row sparse product.
 // Positions outside an interval enter as exact zeros and a zero product leaves
 // the accumulator unchanged, so every entry of X^2 has the bits of the sparse
 // product's ascending-k chain over the entries that exist.
 //
 // The sweep of a block -- threshold, span output of X^2 and 2X - X^2, the
 // norm's squared differences -- works in the tile layout: lane l holds column
-// l % 16 of rows l / 16 + 4 t (t = 0..3), so a row's 16 columns of one tile are
-// one 16-lane row of the wavefront.
+// l % 16 of four rows (FP64: rows l / 16 + 4 t; FP32: rows 4 (l / 16) + t, for
+// t = 0..3), so a row's 16 columns of one tile are one 16-lane row of the
+// wavefront.
 #include <climits>
 
 #include "band_common.h"
@@ -33,6 +36,7 @@ namespace {
 using namespace band;
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kR = 16;                  // output rows per wave (the tile's rows)
@@ -43,20 +47,58 @@ constexpr int kMeta = kKQ * kWave;      // entries of the wave's LDS table of ro
 constexpr int kWin = 64;                // widest output window, in aligned 64-column blocks
 constexpr uint32_t kOob = 0x80000000u;  // byte offset past every buffer: loads give 0, stores are dropped
 
-__device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+// Loads and stores through raw buffers.  The whole offset stays in the VGPR
+// operand (no folding into the immediate or scalar offset fields, which the
+// range check treats differently).
+__device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double)
 {
-  // The whole offset stays in the VGPR operand (no folding into the immediate
-  // or scalar offset fields, which the range check treats differently).
   asm("" : "+v"(off));
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float)
+{
+  asm("" : "+v"(off));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
 {
   asm("" : "+v"(off));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
 }
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+  asm("" : "+v"(off));
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ double absv(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float absv(float a) { return __builtin_fabsf(a); }
+
 // byte offset of element e when `ok`, else past the buffer
-__device__ __forceinline__ uint32_t at(bool ok, int e) { return ok ? (uint32_t)e * 8u : kOob; }
+template <typename T>
+__device__ __forceinline__ uint32_t at(bool ok, int e)
+{
+  return ok ? (uint32_t)e * (uint32_t)sizeof(T) : kOob;
+}
+
+// The matrix instruction of each precision, and the output row its
+// accumulator t holds in lane (r, q) = (l % 16, l / 16).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef f64x4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c)
+  {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int t) { return q + 4 * t; }
+};
+template <> struct Mfma<float> {
+  typedef f32x4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c)
+  {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int t) { return 4 * q + t; }
+};
 
 // the 16 bits of a wave mask that belong to this lane's 16-lane row
 __device__ __forceinline__ uint32_t seg16(uint64_t m, int q) { return (uint32_t)(m >> (16 * q)) & 0xffffu; }
@@ -89,11 +131,11 @@ struct RowRun {
 // the products of step k0 issue.  Every load is range-checked (rows k past
 // khi have no entry in the block's columns, and rows k past kmax have an
 // empty interval in the table), so the step after the last needs no branch.
-template <bool LDS_META>
-__device__ __forceinline__ void mma_block(const SpanView<double> &X, const __amdgpu_buffer_rsrc_t xr,
-                                          const int2 *meta, const int kmin, const int kmax, const int klo,
-                                          const int khi, const int p0, const int arow, const int bA, const int lA,
-                                          f64x4 (&acc)[kP])
+template <typename T, bool LDS_META>
+__device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_buffer_rsrc_t xr, const int2 *meta,
+                                          const int kmin, const int kmax, const int klo, const int khi, const int p0,
+                                          const int arow, const int bA, const int lA,
+                                          typename Mfma<T>::acc (&acc)[kP])
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -110,22 +152,22 @@ __device__ __forceinline__ void mma_block(const SpanView<double> &X, const __amd
     }
     return m;
   };
-  auto load = [&](int k0, int2 m, double &a, double (&b)[kP]) {
+  auto load = [&](int k0, int2 m, T &a, T (&b)[kP]) {
     const int k = k0 + q;
-    a = ld(xr, at((unsigned)(k - bA) < (unsigned)lA, arow + k));
+    a = ld(xr, at<T>((unsigned)(k - bA) < (unsigned)lA, arow + k), T(0));
     const int brow = k * SW - m.x;
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
       const int col = p0 + 16 * p + r;
-      b[p] = ld(xr, at((unsigned)(col - m.x) < (unsigned)m.y, brow + col));
+      b[p] = ld(xr, at<T>((unsigned)(col - m.x) < (unsigned)m.y, brow + col), T(0));
     }
   };
-  auto mma = [&](double a, const double (&b)[kP]) {
+  auto mma = [&](T a, const T (&b)[kP]) {
 #pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p], acc[p], 0, 0, 0);
+    for (int p = 0; p < kP; ++p) acc[p] = Mfma<T>::mma(a, b[p], acc[p]);
   };
   const int nsteps = (khi - klo) / 4 + 1;
-  double a0, b0[kP], a1, b1[kP];
+  T a0, b0[kP], a1, b1[kP];
   load(klo, interval(klo), a0, b0);
   int2 m1 = interval(klo + 4);
   int k0 = klo;
@@ -146,15 +188,16 @@ __device__ __forceinline__ void mma_block(const SpanView<double> &X, const __amd
 }
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
-__device__ void rows16(const int N, const int i0, const int nrows, const SpanView<double> X,
-                       const SpanView<double> SY, const SpanView<double> SU, const double tau, const StepScratch &s,
-                       double *bsum, int2 *meta, int32_t *fallback)
+template <typename T>
+__device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
+                       const SpanView<T> SU, const T tau, const StepScratch &s, double *bsum, int2 *meta,
+                       int32_t *fallback)
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
   // the three matrices share one row stride (they rotate roles every iteration)
   const int SW = X.SW;
-  const int bytes = N * SW * 8;  // < 2^31: the launcher takes this kernel only then
+  const int bytes = N * SW * (int)sizeof(T);  // < 2^31: the launcher takes this kernel only then
   const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(X.val, (short)0, bytes, kRawBufferFlags);
   const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(SY.val, (short)0, bytes, kRawBufferFlags);
   const __amdgpu_buffer_rsrc_t ur = __builtin_amdgcn_make_buffer_rsrc(SU.val, (short)0, bytes, kRawBufferFlags);
@@ -229,13 +272,14 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
     wave_sync();
   }
 
-  // this lane's output rows q + 4 t
+  // this lane's output rows
   int bC[4], lC[4], xrow[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    bC[t] = __shfl(bA, q + 4 * t, kWave);
-    lC[t] = __shfl(lA, q + 4 * t, kWave);
-    xrow[t] = (i0 + q + 4 * t) * SW - bC[t];
+    const int rr = Mfma<T>::row(q, t);
+    bC[t] = __shfl(bA, rr, kWave);
+    lC[t] = __shfl(lA, rr, kWave);
+    xrow[t] = (i0 + rr) * SW - bC[t];
   }
   const int arow = (i0 + r) * SW - bA;
   RowRun ry[4], ru[4];
@@ -270,18 +314,18 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
     }
     klo = uni(klo);
     khi = uni(khi);
-    f64x4 acc[kP];
+    typename Mfma<T>::acc acc[kP];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < kP; ++p) acc[p] = typename Mfma<T>::acc{T(0), T(0), T(0), T(0)};
     if (klo <= khi) {
-      if (kfit) mma_block<true>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
-      else mma_block<false>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
+      if (kfit) mma_block<T, true>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
+      else mma_block<T, false>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
     }
 
     // sweep the block, row quad by row quad
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int rr = q + 4 * t;
+      const int rr = Mfma<T>::row(q, t);
       const int i = i0 + rr;
       const bool act = rr < nrows;
       double tsum[kP];
@@ -289,27 +333,27 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
       for (int p = 0; p < kP; ++p) {
         const int c0 = p0 + 16 * p;
         const int col = c0 + r;
-        const double y = acc[p][t];
-        const double x = ld(xr, at((unsigned)(col - bC[t]) < (unsigned)lC[t], xrow[t] + col));
+        const T y = acc[p][t];
+        const T x = ld(xr, at<T>((unsigned)(col - bC[t]) < (unsigned)lC[t], xrow[t] + col), T(0));
         if (act && col == i) {  // X_ii and the unpruned (X.X)_ii
-          s.d1[i] = x;
-          s.d2[i] = y;
+          s.d1[i] = (double)x;
+          s.d2[i] = (double)y;
         }
-        const bool ky = act && __builtin_fabs(y) > tau;
-        const double yk = ky ? y : 0.0;
+        const bool ky = act && absv(y) > tau;
+        const T yk = ky ? y : T(0);
         ry[t].add(seg16(__ballot(ky), q), c0);
         {
           const int o = col - ry[t].first;
-          st(yr, at(act && ry[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), yk);
+          st(yr, at<T>(act && ry[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), yk);
         }
-        const double v = 2.0 * x - yk;
-        const bool ku = act && __builtin_fabs(v) > tau;
+        const T v = T(2) * x - yk;
+        const bool ku = act && absv(v) > tau;
         ru[t].add(seg16(__ballot(ku), q), c0);
         {
           const int o = col - ru[t].first;
-          st(ur, at(act && ru[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), ku ? v : 0.0);
+          st(ur, at<T>(act && ru[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), ku ? v : T(0));
         }
-        const double d = yk - x;
+        const double d = (double)yk - (double)x;
         tsum[p] = row_tree(d * d);
       }
       // the aligned block's pairwise tree: levels 5 and 6 join the tiles
@@ -343,8 +387,8 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   if (r == 0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int rr = q + 4 * t;
-      if (rr >= nrows) break;
+      const int rr = Mfma<T>::row(q, t);
+      if (rr >= nrows) continue;
       const int i = i0 + rr;
       const int ylen = ry[t].length(), ulen = ru[t].length();
       SY.base[i] = ylen ? ry[t].first : 0;
@@ -363,8 +407,9 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   }
 }
 
-__global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<double> spans, const SP2State *st, double tau,
-                                                   StepScratch s, int32_t *fallback)
+template <typename T>
+__global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, StepScratch s,
+                                                   int32_t *fallback)
 {
   __shared__ double bsum_s[kWpb][kR * kWin];
   __shared__ int2 meta_s[kWpb][kMeta];
@@ -378,20 +423,25 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<double> spans
   const int i0 = grp * kR;
   if (i0 >= N) return;
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-  rows16(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], meta_s[w], fallback);
+  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], meta_s[w], fallback);
 }
 
 }  // namespace
 
-bool x2_band16_fits(int N, int SW) { return (int64_t)N * SW * 8 < ((int64_t)1 << 31); }
+bool x2_band16_fits(int N, int SW, int elem_bytes) { return (int64_t)N * SW * elem_bytes < ((int64_t)1 << 31); }
 
-hipError_t launch_x2_band16(int N, SpanRot3<double> spans, const SP2State *st, double tau, const StepScratch &s,
+template <typename T>
+hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
                             int32_t *fallback, hipStream_t stream)
 {
   const int groups = (N + kR - 1) / kR;
   const dim3 grid((groups + kWpb - 1) / kWpb), block(kWpb * kWave);
-  hipLaunchKernelGGL(k_x2_band16, grid, block, 0, stream, N, spans, st, tau, s, fallback);
+  hipLaunchKernelGGL(k_x2_band16<T>, grid, block, 0, stream, N, spans, st, tau, s, fallback);
   return hipGetLastError();
 }
+template hipError_t launch_x2_band16<double>(int, SpanRot3<double>, const SP2State *, double, const StepScratch &,
+                                             int32_t *, hipStream_t);
+template hipError_t launch_x2_band16<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
+                                            int32_t *, hipStream_t);
 
 }  // namespace ellsp2

@@ -136,10 +136,11 @@ hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hi
 template <typename T>
 hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State *st, bool with_u, bool out_ell,
                           T tau, const StepScratch &s, int32_t *fallback, hipStream_t stream);
-// FP64 span-form X^2 on the matrix cores (ell_band16.hip): the kernel of the
-// FP64 SP2 iteration when every matrix of the rotation fits 2^31 bytes
-bool x2_band16_fits(int N, int SW);
-hipError_t launch_x2_band16(int N, SpanRot3<double> spans, const SP2State *st, double tau, const StepScratch &s,
+// Span-form X^2 on the matrix cores (ell_band16.hip): the kernel of the SP2
+// iteration when every matrix of the rotation fits 2^31 bytes
+bool x2_band16_fits(int N, int SW, int elem_bytes);
+template <typename T>
+hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
                             int32_t *fallback, hipStream_t stream);
 template <typename T>
 hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream);
