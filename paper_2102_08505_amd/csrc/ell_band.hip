@@ -18,6 +18,7 @@
 // chain of fused multiply-adds over the entries that exist: the same bits as
 // the row-by-row sparse product.  A B load feeds 8 FMAs and no accumulator
 // touches memory until the row is complete.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -545,33 +546,41 @@ __global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanVi
   }
 }
 
-// span form -> ELLPACK (nonzero positions, ascending), one wave per row.
+// span form -> ELLPACK (nonzero positions, ascending), one wave per row, the
+// waves striding over the rows; the widest row goes to *wmax with one atomic
+// per workgroup.
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax)
 {
-  const int w = threadIdx.x >> 6;
-  const int i = blockIdx.x * kWavesPerBlock + w;
-  if (i >= N) return;
+  __shared__ int32_t bmax;
+  if (threadIdx.x == 0) bmax = 0;
+  __syncthreads();
   const int lane = lane_id();
-  const int b = S.base[i], l = S.len[i];
-  int c = 0;
-  for (int p0 = 0; p0 < l; p0 += kWave) {
-    const int p = p0 + lane;
-    const TS v = p < l ? S.val[(size_t)i * S.SW + p] : TS(0);
-    const bool keep = v != TS(0);
-    const uint64_t m = __ballot(keep);
-    if (keep) {
-      const int pos = c + lanes_below(m);
-      if (pos < A.M) {
-        A.idx[(size_t)i * A.M + pos] = b + p;
-        A.val[(size_t)i * A.M + pos] = (TD)v;
+  int cmax = 0;
+  for (int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += gridDim.x * kWavesPerBlock) {
+    const int b = S.base[i], l = S.len[i];
+    int c = 0;
+    for (int p0 = 0; p0 < l; p0 += kWave) {
+      const int p = p0 + lane;
+      const TS v = p < l ? S.val[(size_t)i * S.SW + p] : TS(0);
+      const bool keep = v != TS(0);
+      const uint64_t m = __ballot(keep);
+      if (keep) {
+        const int pos = c + lanes_below(m);
+        if (pos < A.M) {
+          A.idx[(size_t)i * A.M + pos] = b + p;
+          A.val[(size_t)i * A.M + pos] = (TD)v;
+        }
       }
+      c += __popcll(m);
     }
-    c += __popcll(m);
+    if (lane == 0) A.nnz[i] = min(c, A.M);
+    cmax = max(cmax, c);
   }
-  if (lane == 0) {
-    A.nnz[i] = min(c, A.M);
-    if (wmax) atomicMax(wmax, c);
+  if (wmax) {
+    if (lane == 0) atomicMax(&bmax, cmax);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(wmax, bmax);
   }
 }
 
@@ -658,8 +667,8 @@ template hipError_t launch_ell_to_span<float>(int, EllView<float>, SpanView<floa
 template <typename TS, typename TD>
 hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_span_to_ell<TS, TD>), dim3((N + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream,
-                     N, S, A, wmax);
+  const int blocks = std::min((N + kWavesPerBlock - 1) / kWavesPerBlock, 1024);
+  hipLaunchKernelGGL((k_span_to_ell<TS, TD>), dim3(std::max(blocks, 1)), dim3(256), 0, stream, N, S, A, wmax);
   return hipGetLastError();
 }
 template hipError_t launch_span_to_ell<double, double>(int, SpanView<double>, EllView<double>, int32_t *,

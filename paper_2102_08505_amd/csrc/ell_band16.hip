@@ -103,28 +103,61 @@ template <> struct Mfma<float> {
 // the 16 bits of a wave mask that belong to this lane's 16-lane row
 __device__ __forceinline__ uint32_t seg16(uint64_t m, int q) { return (uint32_t)(m >> (16 * q)) & 0xffffu; }
 
-// pairwise tree over the 16 lanes of a row; every lane of the row gets the total
-__device__ __forceinline__ double row_tree(double v)
+// A lane's partner value through DPP: quad_perm [1,0,3,2] (0xb1) and
+// [2,3,0,1] (0x4e) pair lanes 4m + (0,1), (2,3) and then the two pairs of a
+// quad; with a + b = b + a exactly, both lanes of a pair get the same sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
 {
-  for (int m = 1; m < 16; m <<= 1) v = v + __shfl_xor(v, m, kWave);
-  return v;
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
 
-// Running output state of one row (first / last kept column, kept count).
+// Running output state of one row: first and last kept column, kept count.
+// Tiles come in ascending column order.  A row's span output holds exactly
+// its interval [first, last]: a tile writes its columns from `first` up to
+// its own last kept column, and when a tile keeps something after a run of
+// tiles that kept nothing, the columns between get their zeros then.
 struct RowRun {
   int first = INT_MAX, last = -1, count = 0;
-  __device__ void add(uint32_t seg, int c0)
+  // seg: kept columns c0 .. c0 + 15 of this tile.  Returns the last column
+  // this tile writes (c0 - 1: none) and, in gap_lo .. c0 - 1, the earlier
+  // columns that still need zeros.
+  __device__ int add(uint32_t seg, int c0, int &gap_lo)
   {
+    gap_lo = seg && last >= 0 ? last + 1 : c0;
     count += __popc(seg);
     const int f = seg ? c0 + __ffs(seg) - 1 : INT_MAX;
-    first = min(first, f);  // blocks come in ascending column order
-    last = seg ? c0 + 31 - __clz(seg) : last;
+    first = min(first, f);
+    const int l = c0 + 31 - __clz(seg);  // c0 - 1 when seg == 0
+    last = seg ? l : last;
+    return l;
   }
   __device__ int length() const { return last >= 0 ? last - first + 1 : 0; }
 };
 
+// Span output of one tile of one row, lane column col: the tile's columns up
+// to its last kept one (lastw).
+template <typename T>
+__device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t rs, int first, int lastw, int col, int row0, int SW,
+                                    bool act, T v)
+{
+  const int o = col - first;
+  st(rs, at<T>(act && col <= lastw && (unsigned)o < (unsigned)SW, row0 + o), v);
+}
+// Zeros for the columns gap_lo .. c0 - 1 of a row (tiles that kept nothing,
+// followed by one that keeps something).
+template <typename T>
+__device__ void fill_gap(__amdgpu_buffer_rsrc_t rs, int first, int gap_lo, int c0, int r, int row0, int SW, bool act)
+{
+  for (int c = gap_lo + r; c < c0; c += 16) {
+    const int o = c - first;
+    st(rs, at<T>(act && (unsigned)o < (unsigned)SW, row0 + o), T(0));
+  }
+}
+
 // Accumulate one 64-column block: acc[p] += X[i0 .. i0+15][k] X[k][p0 + 16 p ..]
-// over k = klo .. khi, four k per step (a step past khi multiplies zeros).
+// over k = klo .. khi, four k per step (a step past khi multiplies zeros);
+// tile p takes part only in the steps that meet its own range tlo[p] .. thi[p].
 // A operand: lane (r, q) = (l % 16, l / 16) supplies X[i0 + r][k0 + q];
 // B operand: lane (r, q) supplies X[k0 + q][p0 + 16 p + r].
 // Two operand sets alternate: the loads of step k0 + 4 are in flight while
@@ -133,9 +166,9 @@ struct RowRun {
 // empty interval in the table), so the step after the last needs no branch.
 template <typename T, bool LDS_META>
 __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_buffer_rsrc_t xr, const int2 *meta,
-                                          const int kmin, const int kmax, const int klo, const int khi, const int p0,
-                                          const int arow, const int bA, const int lA,
-                                          typename Mfma<T>::acc (&acc)[kP])
+                                          const int kmin, const int kmax, const int klo, const int khi,
+                                          const int (&tlo)[kP], const int (&thi)[kP], const int p0, const int arow,
+                                          const int bA, const int lA, typename Mfma<T>::acc (&acc)[kP])
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -162,9 +195,12 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
       b[p] = ld(xr, at<T>((unsigned)(col - m.x) < (unsigned)m.y, brow + col), T(0));
     }
   };
-  auto mma = [&](T a, const T (&b)[kP]) {
+  // tile p's products are skipped at steps outside its own k range (its B
+  // operand is all zeros there)
+  auto mma = [&](int k0, T a, const T (&b)[kP]) {
 #pragma unroll
-    for (int p = 0; p < kP; ++p) acc[p] = Mfma<T>::mma(a, b[p], acc[p]);
+    for (int p = 0; p < kP; ++p)
+      if (k0 <= thi[p] && k0 + 3 >= tlo[p]) acc[p] = Mfma<T>::mma(a, b[p], acc[p]);
   };
   const int nsteps = (khi - klo) / 4 + 1;
   T a0, b0[kP], a1, b1[kP];
@@ -176,22 +212,22 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
     load(k0 + 4, m1, a1, b1);
     const int2 m0 = interval(k0 + 8);
     __builtin_amdgcn_sched_barrier(0);
-    mma(a0, b0);
+    mma(k0, a0, b0);
     __builtin_amdgcn_sched_barrier(0);
     load(k0 + 8, m0, a0, b0);
     m1 = interval(k0 + 12);
     __builtin_amdgcn_sched_barrier(0);
-    mma(a1, b1);
+    mma(k0 + 4, a1, b1);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (nsteps & 1) mma(a0, b0);
+  if (nsteps & 1) mma(k0, a0, b0);
 }
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
 template <typename T>
 __device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
-                       const SpanView<T> SU, const T tau, const StepScratch &s, double *bsum, int2 *meta,
-                       int32_t *fallback)
+                       const SpanView<T> SU, const T tau, const StepScratch &s, double *bsum, double *sq,
+                       int2 *meta, int32_t *fallback)
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -286,79 +322,132 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
 
   for (int pc = 0; pc < nblk; ++pc) {
     const int p0 = wlo + pc * kWave, p1 = p0 + kWave - 1;
-    // rows k whose interval meets the block
-    int klo = INT_MAX, khi = -1;
-    if (kfit) {
+    // rows k whose interval meets each tile of the block, and the block
+    int tlo[kP], thi[kP];
 #pragma unroll
-      for (int j = 0; j < kKQ; ++j) {
-        const uint64_t m = __ballot(klq[j] > 0 && kbq[j] <= p1 && kbq[j] + klq[j] - 1 >= p0);
+    for (int p = 0; p < kP; ++p) {
+      tlo[p] = INT_MAX;
+      thi[p] = -1;
+    }
+    auto meet = [&](int kbase, int b, int l) {
+#pragma unroll
+      for (int p = 0; p < kP; ++p) {
+        const int c0 = p0 + 16 * p;
+        const uint64_t m = __ballot(l > 0 && b <= c0 + 15 && b + l - 1 >= c0);
         if (m) {
-          klo = min(klo, kmin + j * kWave + (int)__builtin_ctzll(m));
-          khi = max(khi, kmin + j * kWave + 63 - (int)__builtin_clzll(m));
+          tlo[p] = min(tlo[p], kbase + (int)__builtin_ctzll(m));
+          thi[p] = max(thi[p], kbase + 63 - (int)__builtin_clzll(m));
         }
       }
+    };
+    if (kfit) {
+#pragma unroll
+      for (int j = 0; j < kKQ; ++j) meet(kmin + j * kWave, kbq[j], klq[j]);
     } else {
       for (int k0 = kmin; k0 <= kmax; k0 += kWave) {
         const int k = k0 + lane;
-        bool meet = false;
-        if (k <= kmax) {
-          const int l = X.len[k], b = X.base[k];
-          meet = l > 0 && b <= p1 && b + l - 1 >= p0;
-        }
-        const uint64_t m = __ballot(meet);
-        if (m) {
-          klo = min(klo, k0 + (int)__builtin_ctzll(m));
-          khi = max(khi, k0 + 63 - (int)__builtin_clzll(m));
-        }
+        const bool in = k <= kmax;
+        meet(k0, in ? X.base[k] : 0, in ? X.len[k] : 0);
       }
     }
-    klo = uni(klo);
-    khi = uni(khi);
+    int klo = INT_MAX, khi = -1;
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+      tlo[p] = uni(tlo[p]);
+      thi[p] = uni(thi[p]);
+      klo = min(klo, tlo[p]);
+      khi = max(khi, thi[p]);
+    }
+    // X at the block's output positions, for 2X - X^2 and the norm: loaded
+    // first, so the loads complete under the block's products
+    T xv[4][kP];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int p = 0; p < kP; ++p) {
+        const int col = p0 + 16 * p + r;
+        xv[t][p] = ld(xr, at<T>((unsigned)(col - bC[t]) < (unsigned)lC[t], xrow[t] + col), T(0));
+      }
     typename Mfma<T>::acc acc[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) acc[p] = typename Mfma<T>::acc{T(0), T(0), T(0), T(0)};
     if (klo <= khi) {
-      if (kfit) mma_block<T, true>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
-      else mma_block<T, false>(X, xr, meta, kmin, kmax, klo, khi, p0, arow, bA, lA, acc);
+      if (kfit) mma_block<T, true>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, acc);
+      else mma_block<T, false>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, acc);
     }
 
     // sweep the block, row quad by row quad
+    const bool diag = p0 <= i0 + kR - 1 && p0 + kWave - 1 >= i0;  // a diagonal entry lies in the block
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int rr = Mfma<T>::row(q, t);
       const int i = i0 + rr;
       const bool act = rr < nrows;
-      double tsum[kP];
+      T yk[kP], uk[kP];
+      bool ky[kP], ku[kP];
+      double e[kP];
+#pragma unroll
+      for (int p = 0; p < kP; ++p) {
+        const T y = acc[p][t], x = xv[t][p];
+        ky[p] = act && absv(y) > tau;
+        yk[p] = ky[p] ? y : T(0);
+        const T v = T(2) * x - yk[p];
+        ku[p] = act && absv(v) > tau;
+        uk[p] = ku[p] ? v : T(0);
+        const double d = (double)yk[p] - (double)x;
+        e[p] = d * d;
+      }
+      int gy[kP], gu[kP];
 #pragma unroll
       for (int p = 0; p < kP; ++p) {
         const int c0 = p0 + 16 * p;
-        const int col = c0 + r;
-        const T y = acc[p][t];
-        const T x = ld(xr, at<T>((unsigned)(col - bC[t]) < (unsigned)lC[t], xrow[t] + col), T(0));
-        if (act && col == i) {  // X_ii and the unpruned (X.X)_ii
-          s.d1[i] = (double)x;
-          s.d2[i] = (double)y;
-        }
-        const bool ky = act && absv(y) > tau;
-        const T yk = ky ? y : T(0);
-        ry[t].add(seg16(__ballot(ky), q), c0);
-        {
-          const int o = col - ry[t].first;
-          st(yr, at<T>(act && ry[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), yk);
-        }
-        const T v = T(2) * x - yk;
-        const bool ku = act && absv(v) > tau;
-        ru[t].add(seg16(__ballot(ku), q), c0);
-        {
-          const int o = col - ru[t].first;
-          st(ur, at<T>(act && ru[t].first != INT_MAX && (unsigned)o < (unsigned)SW, i * SW + o), ku ? v : T(0));
-        }
-        const double d = (double)yk - (double)x;
-        tsum[p] = row_tree(d * d);
+        const int ly = ry[t].add(seg16(__ballot(ky[p]), q), c0, gy[p]);
+        put<T>(yr, ry[t].first, ly, c0 + r, i * SW, SW, act, yk[p]);
+        const int lu = ru[t].add(seg16(__ballot(ku[p]), q), c0, gu[p]);
+        put<T>(ur, ru[t].first, lu, c0 + r, i * SW, SW, act, uk[p]);
       }
-      // the aligned block's pairwise tree: levels 5 and 6 join the tiles
-      if (r == 0) bsum[rr * kWin + pc] = (tsum[0] + tsum[1]) + (tsum[2] + tsum[3]);
+      // the norm's squared differences, to the block table [row][column]
+#pragma unroll
+      for (int p = 0; p < kP; ++p) sq[rr * kWave + 16 * p + r] = e[p];
+      bool gap = false;
+#pragma unroll
+      for (int p = 0; p < kP; ++p) gap = gap || gy[p] < p0 + 16 * p || gu[p] < p0 + 16 * p;
+      if (__ballot(gap)) {
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+          fill_gap<T>(yr, ry[t].first, gy[p], p0 + 16 * p, r, i * SW, SW, act);
+          fill_gap<T>(ur, ru[t].first, gu[p], p0 + 16 * p, r, i * SW, SW, act);
+        }
+      }
+      if (diag) {
+#pragma unroll
+        for (int p = 0; p < kP; ++p)
+          if (act && p0 + 16 * p + r == i) {  // X_ii and the unpruned (X.X)_ii
+            s.d1[i] = (double)xv[t][p];
+            s.d2[i] = (double)acc[p][t];
+          }
+      }
     }
+    // The block's norm terms: lane 4 g + p sums row g's 16 columns of tile p
+    // in registers (tree levels 1-4), then levels 5 and 6 join the four tiles
+    // across the lane quad.
+    wave_sync();
+    {
+      const int g = lane >> 2, p = lane & 3;
+      const double *src = sq + g * kWave + 16 * p;
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = src[u];
+#pragma unroll
+      for (int w = 1; w < 16; w <<= 1)
+#pragma unroll
+        for (int u = 0; u < 16; u += 2 * w) v[u] = v[u] + v[u + w];
+      double tb = v[0];
+      tb = tb + dpp<0xb1>(tb);
+      tb = tb + dpp<0x4e>(tb);
+      if (p == 0) bsum[g * kWin + pc] = tb;
+    }
+    wave_sync();
   }
   wave_sync();
 
@@ -412,6 +501,7 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
                                                    int32_t *fallback)
 {
   __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   int cur = 0;
   if (st) {
@@ -423,7 +513,8 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
   const int i0 = grp * kR;
   if (i0 >= N) return;
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], meta_s[w], fallback);
+  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], sq_s[w], meta_s[w],
+            fallback);
 }
 
 }  // namespace
