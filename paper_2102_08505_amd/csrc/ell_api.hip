@@ -11,6 +11,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,26 +56,135 @@ size_t val_size(ell_prec_t p) { return p == ELL_F64 ? sizeof(double) : sizeof(fl
 
 int32_t roundup32(int64_t x) { return (int32_t)((x + 31) / 32 * 32); }
 
+// Scratch allocations of an API call whose device work all runs on one
+// stream (an AllocScope on the call's stack names it) come from a process-wide
+// cache of device blocks: repeated calls reuse them instead of paying for
+// hipMalloc and a device-synchronising hipFree every time.  A released block
+// carries an event recorded on its stream after the work queued before the
+// release; a new owner on another stream waits for that event first, so reuse
+// is ordered after every earlier use.  The cache holds at most kCacheBytes
+// (oldest blocks are freed beyond that).  Without a scope, allocations are
+// plain hipMalloc / hipFree.
+thread_local bool g_cache_alloc = false;
+thread_local hipStream_t g_cache_stream = nullptr;
+
+struct CachedBlock {
+  void *p;
+  size_t bytes;
+  int dev;
+  hipStream_t stream;
+  hipEvent_t done;
+};
+constexpr size_t kCacheBytes = (size_t)16 << 30;
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+size_t g_cache_total = 0;
+
+size_t size_class(size_t bytes)
+{
+  const size_t g = bytes >= ((size_t)1 << 20) ? ((size_t)1 << 16) : 256;  // 64 KiB steps above 1 MiB
+  return (std::max<size_t>(bytes, 1) + g - 1) / g * g;
+}
+
+struct AllocScope {
+  bool prev_on;
+  hipStream_t prev_stream;
+  explicit AllocScope(hipStream_t s) : prev_on(g_cache_alloc), prev_stream(g_cache_stream)
+  {
+    g_cache_alloc = true;
+    g_cache_stream = s;
+  }
+  ~AllocScope()
+  {
+    g_cache_alloc = prev_on;
+    g_cache_stream = prev_stream;
+  }
+  AllocScope(const AllocScope &) = delete;
+  AllocScope &operator=(const AllocScope &) = delete;
+};
+
 // Device allocation released on scope exit.
 struct DevMem {
   void *p = nullptr;
+  bool cached = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;  // the block's reuse event (cached blocks)
+  size_t bytes = 0;
+  int dev = 0;
   DevMem() = default;
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
   ~DevMem() { release(); }
   void release()
   {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    if (!cached) {
+      (void)hipFree(p);
+    } else if (!done && hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(p);
+    } else {
+      (void)hipEventRecord(done, stream);
+      std::vector<CachedBlock> evict;
+      {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        g_cache.push_back(CachedBlock{p, bytes, dev, stream, done});
+        g_cache_total += bytes;
+        while (g_cache_total > kCacheBytes && !g_cache.empty()) {
+          evict.push_back(g_cache.front());
+          g_cache_total -= g_cache.front().bytes;
+          g_cache.erase(g_cache.begin());
+        }
+      }
+      for (const CachedBlock &c : evict) {
+        (void)hipEventSynchronize(c.done);
+        (void)hipEventDestroy(c.done);
+        (void)hipFree(c.p);
+      }
+    }
     p = nullptr;
+    done = nullptr;
   }
-  hipError_t alloc(size_t bytes)
+  hipError_t alloc(size_t want)
   {
     release();
-    return hipMalloc(&p, bytes ? bytes : 1);
+    cached = g_cache_alloc;
+    stream = g_cache_stream;
+    if (!cached) return hipMalloc(&p, want ? want : 1);
+    bytes = size_class(want);
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+      std::lock_guard<std::mutex> lock(g_cache_mu);
+      for (size_t i = g_cache.size(); i-- > 0;) {
+        const CachedBlock &c = g_cache[i];
+        if (c.dev == dev && c.bytes == bytes) {
+          p = c.p;
+          done = c.done;
+          const hipStream_t from = c.stream;
+          g_cache_total -= c.bytes;
+          g_cache.erase(g_cache.begin() + (ptrdiff_t)i);
+          return from == stream ? hipSuccess : hipStreamWaitEvent(stream, done, 0);
+        }
+      }
+    }
+    return hipMalloc(&p, bytes);
   }
   template <typename T>
   T *as() const { return static_cast<T *>(p); }
+  // zero the first `n` bytes, ordered like the allocation
+  hipError_t zero(size_t n) const { return cached ? hipMemsetAsync(p, 0, n, stream) : hipMemset(p, 0, n); }
 };
+
+void swap_mem(DevMem &a, DevMem &b)
+{
+  std::swap(a.p, b.p);
+  std::swap(a.cached, b.cached);
+  std::swap(a.stream, b.stream);
+  std::swap(a.done, b.done);
+  std::swap(a.bytes, b.bytes);
+  std::swap(a.dev, b.dev);
+}
 
 int have_device()
 {
@@ -98,6 +208,7 @@ int validate_on_device(const ellpack *A_)
 {
   ellpack *A = const_cast<ellpack *>(A_);
   if (A->validated) return ELL_OK;
+  AllocScope scope(A->stream);
   DevMem flags;
   HIP_TRY(flags.alloc(sizeof(int32_t)));
   HIP_TRY(hipMemsetAsync(flags.p, 0, sizeof(int32_t), A->stream));
@@ -132,7 +243,7 @@ struct StepMem {
         (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
         (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))))
       return err;
-    if ((err = hipMemset(flags.p, 0, sizeof(int32_t)))) return err;
+    if ((err = flags.zero(sizeof(int32_t)))) return err;
     s.d1 = d1.as<double>();
     s.d2 = d2.as<double>();
     s.e = e.as<double>();
@@ -179,10 +290,10 @@ struct SpanMem {
         (e = len.alloc(sizeof(int32_t) * ((size_t)N + kSpanPadRows))))
       return e;
     // rows past N read as empty by the band kernel's batched interval loads
-    if ((e = hipMemset(base.p, 0, sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
-    if ((e = hipMemset(len.p, 0, sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    if ((e = base.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    if ((e = len.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
     // the guard bands are read (and masked) by the band kernel: keep them finite
-    return hipMemset(val.p, 0, sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard));
+    return val.zero(sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard));
   }
   void release()
   {
@@ -284,6 +395,7 @@ template <typename T>
 int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
 {
   const int N = X->N;
+  AllocScope scope(X->stream);
   StepMem m;
   HIP_TRY(m.alloc(N));
   Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
@@ -508,6 +620,7 @@ extern "C" int ellpack_trace(const ellpack_t *A, double *trace_out)
   if (!A || !trace_out) return ELL_EINVAL;
   int rc = ensure_valid(A);
   if (rc) return rc;
+  AllocScope scope(A->stream);
   DevMem d, part, out;
   HIP_TRY(d.alloc(sizeof(double) * A->N));
   HIP_TRY(part.alloc(sizeof(double) * ((A->N + kRedBlock - 1) / kRedBlock)));
@@ -721,6 +834,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   const int N = H->N;
   const bool mixed = p->precision == SP2_MIXED;
   const int poll = p->poll_every > 0 ? p->poll_every : 4;
+  AllocScope scope(D->stream);
   Solver S;
   S.N = N;
   S.stream = D->stream;
@@ -903,9 +1017,9 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
             HIP_TRY(hipStreamSynchronize(st));
             S32.release();
             for (int b = 0; b < 3; ++b) {
-              std::swap(S32.m[b].val.p, G.m[b].val.p);
-              std::swap(S32.m[b].base.p, G.m[b].base.p);
-              std::swap(S32.m[b].len.p, G.m[b].len.p);
+              swap_mem(S32.m[b].val, G.m[b].val);
+              swap_mem(S32.m[b].base, G.m[b].base);
+              swap_mem(S32.m[b].len, G.m[b].len);
               S32.m[b].SW = sw;
             }
             S32.SW = sw;
@@ -916,9 +1030,9 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
             HIP_TRY(hipStreamSynchronize(st));
             S64.release();
             for (int b = 0; b < 3; ++b) {
-              std::swap(S64.m[b].val.p, G.m[b].val.p);
-              std::swap(S64.m[b].base.p, G.m[b].base.p);
-              std::swap(S64.m[b].len.p, G.m[b].len.p);
+              swap_mem(S64.m[b].val, G.m[b].val);
+              swap_mem(S64.m[b].base, G.m[b].base);
+              swap_mem(S64.m[b].len, G.m[b].len);
               S64.m[b].SW = sw;
             }
             S64.SW = sw;
@@ -941,9 +1055,9 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
           HIP_TRY(hipStreamSynchronize(st));
           W32.release();
           for (int b = 0; b < 3; ++b) {
-            std::swap(W32.nnz[b].p, G.nnz[b].p);
-            std::swap(W32.idx[b].p, G.idx[b].p);
-            std::swap(W32.val[b].p, G.val[b].p);
+            swap_mem(W32.nnz[b], G.nnz[b]);
+            swap_mem(W32.idx[b], G.idx[b]);
+            swap_mem(W32.val[b], G.val[b]);
           }
           W32.cap = newcap;
         } else {
@@ -953,9 +1067,9 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
           HIP_TRY(hipStreamSynchronize(st));
           W64.release();
           for (int b = 0; b < 3; ++b) {
-            std::swap(W64.nnz[b].p, G.nnz[b].p);
-            std::swap(W64.idx[b].p, G.idx[b].p);
-            std::swap(W64.val[b].p, G.val[b].p);
+            swap_mem(W64.nnz[b], G.nnz[b]);
+            swap_mem(W64.idx[b], G.idx[b]);
+            swap_mem(W64.val[b], G.val[b]);
           }
           W64.cap = newcap;
         }
@@ -1206,14 +1320,14 @@ int batch_regrow(Batch &B, int32_t sw)
   }
   HIP_TRY(hipStreamSynchronize(B.st));
   for (int b = 0; b < 3; ++b) {
-    std::swap(B.A64.m[b].val.p, G64.m[b].val.p);
-    std::swap(B.A64.m[b].base.p, G64.m[b].base.p);
-    std::swap(B.A64.m[b].len.p, G64.m[b].len.p);
+    swap_mem(B.A64.m[b].val, G64.m[b].val);
+    swap_mem(B.A64.m[b].base, G64.m[b].base);
+    swap_mem(B.A64.m[b].len, G64.m[b].len);
     B.A64.m[b].SW = sw;
     if (B.any32) {
-      std::swap(B.A32.m[b].val.p, G32.m[b].val.p);
-      std::swap(B.A32.m[b].base.p, G32.m[b].base.p);
-      std::swap(B.A32.m[b].len.p, G32.m[b].len.p);
+      swap_mem(B.A32.m[b].val, G32.m[b].val);
+      swap_mem(B.A32.m[b].base, G32.m[b].base);
+      swap_mem(B.A32.m[b].len, G32.m[b].len);
       B.A32.m[b].SW = sw;
     }
   }

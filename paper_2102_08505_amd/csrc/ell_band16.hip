@@ -321,7 +321,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   RowRun ry[4], ru[4];
 
   for (int pc = 0; pc < nblk; ++pc) {
-    const int p0 = wlo + pc * kWave, p1 = p0 + kWave - 1;
+    const int p0 = wlo + pc * kWave;
     // rows k whose interval meets each tile of the block, and the block
     int tlo[kP], thi[kP];
 #pragma unroll

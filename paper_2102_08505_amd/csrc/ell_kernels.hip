@@ -478,17 +478,32 @@ __device__ void final_reduce(const StepScratch &s, double *ws)
     const double t = block_tree_1024(a[0], a[1], a[2], a[3], ws);
     if (threadIdx.x == 0) s.out[c] = t;
   }
+  // maxima and integer totals: exact in any order, so spread over the block
+  __shared__ int32_t wsi[4][4];
+  __shared__ long long wsl[2][4];
+  int32_t mx[4] = {0, 0, 0, 0};
+  long long sy = 0, su = 0;
+  for (int b = threadIdx.x; b < s.nb; b += 256) {
+    for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], s.partw[c * s.nb + b]);
+    sy += s.partn[b];
+    su += s.partn[s.nb + b];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], __shfl_xor(mx[c], o, kWave));
+    sy += __shfl_xor(sy, o, kWave);
+    su += __shfl_xor(su, o, kWave);
+  }
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    for (int c = 0; c < 4; ++c) wsi[c][w] = mx[c];
+    wsl[0][w] = sy;
+    wsl[1][w] = su;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int32_t mx[4] = {0, 0, 0, 0};
-    long long sy = 0, su = 0;
-    for (int b = 0; b < s.nb; ++b) {
-      for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], s.partw[c * s.nb + b]);
-      sy += s.partn[b];
-      su += s.partn[s.nb + b];
-    }
-    for (int c = 0; c < 4; ++c) s.outw[c] = mx[c];
-    s.outn[0] = sy;
-    s.outn[1] = su;
+    for (int c = 0; c < 4; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
+    s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
+    s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
   }
 }
 
