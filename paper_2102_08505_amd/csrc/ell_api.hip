@@ -1429,7 +1429,7 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   HIP_TRY(hipMemcpyAsync(gf.data(), gflags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
 
-  // ---- layout: instances that can start, widest first, each at a multiple of kGroupRows rows ----
+  // ---- layout: instances that can start, widest first, each at a multiple of kBatchAlign rows ----
   std::vector<int> order;
   std::vector<int> early(n, ST_RUNNING);
   for (int32_t q = 0; q < n; ++q) {
@@ -1460,7 +1460,7 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     I.mixed = p[I.q].precision == SP2_MIXED;
     I.emin = ee[2 * I.q];
     I.emax = ee[2 * I.q + 1];
-    rows += (I.N + kGroupRows - 1) / kGroupRows * kGroupRows;
+    rows += (I.N + kBatchAlign - 1) / kBatchAlign * kBatchAlign;
     blocks += I.nb;
     hoff += p[I.q].max_iter;
     B.any32 = B.any32 || I.mixed;
@@ -1649,7 +1649,8 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   for (int m = 0; m < B.n; ++m) {
     const BatchInst &I = B.in[m];
     const sp2_params_t &P = p[I.q];
-    for (int g = I.r0 / kGroupRows; g < (I.r0 + I.N + kGroupRows - 1) / kGroupRows; ++g) gi[g] = m;
+    const int rows_m = (I.N + kBatchAlign - 1) / kBatchAlign * kBatchAlign;
+    for (int g = I.r0 / kGroupRows; g < (I.r0 + rows_m) / kGroupRows; ++g) gi[g] = m;
     for (int b = 0; b < I.nb; ++b) {
       bi[I.pb + b] = m;
       bl[I.pb + b] = b;

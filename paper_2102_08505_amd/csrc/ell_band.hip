@@ -487,6 +487,7 @@ __global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> 
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
   const int r0 = uni(inst_r0[m]), n = uni(inst_rows[m]);
   const int i0 = grp * kG - r0;
+  if (i0 >= n) return;  // alignment rows after the instance's last row
   const EllView<T> none{nullptr, nullptr, nullptr, 0};
   band_rows<T, true, false, true>(n, i0, min(kG, n - i0), shift_rows(spans.b[cur], r0), shift_rows(spans.b[cy], r0),
                                   shift_rows(spans.b[cu], r0), none, none, taus[m], ss[m], bsum_s[w], flags + m);
@@ -633,6 +634,10 @@ hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *g
                                 const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
                                 const StepScratch *ss, int32_t *flags, hipStream_t stream)
 {
+  static_assert(kBatchAlign % kGroupRows == 0, "batch alignment is a whole number of row groups");
+  if (x2_band16_fits(ngroups * kGroupRows, spans.b[0].SW, (int)sizeof(T)))
+    return launch_x2_band16_batch<T>(ngroups * kGroupRows / 16, spans, grp_inst, inst_r0, inst_rows, states, phase32,
+                                     taus, ss, flags, stream);
   const dim3 grid((ngroups + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
   hipLaunchKernelGGL((k_x2_band_batch<T>), grid, block, 0, stream, ngroups, spans, grp_inst, inst_r0, inst_rows,
                      states, phase32, taus, ss, flags);

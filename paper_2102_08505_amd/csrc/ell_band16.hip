@@ -517,6 +517,46 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
             fallback);
 }
 
+// Batched form: the instances' rows are stacked in one span matrix, instance m
+// from row r0[m] (a multiple of 16), with its own local column numbers.  Group
+// grp (16 rows) belongs to the instance of its first 8-row group; the wave
+// works on that instance's rows as a matrix of its own, so every row, its
+// column blocks and the norm's tree see exactly the coordinates of a single
+// solve.  The instance's state selects the buffers, whether it still runs and
+// its precision; the launch for one precision skips instances in the other.
+template <typename T>
+__device__ __forceinline__ SpanView<T> rows_from(SpanView<T> v, int r0)
+{
+  v.val += (size_t)r0 * v.SW;
+  v.base += r0;
+  v.len += r0;
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst,
+                                                         const int32_t *inst_r0, const int32_t *inst_rows,
+                                                         const SP2State *states, int32_t phase32, const T *taus,
+                                                         const StepScratch *ss, int32_t *flags)
+{
+  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double sq_s[kWpb][kR * kWave];
+  __shared__ int2 meta_s[kWpb][kMeta];
+  const int w = uni(threadIdx.x >> 6);
+  const int grp = xcd_block(blockIdx.x, gridDim.x) * kWpb + w;
+  if (grp >= ngroups) return;
+  const int m = uni(grp_inst[grp * (kR / kGroupRows)]);
+  const SP2State *st = states + m;
+  if (st->stop || st->phase32 != phase32) return;
+  const int cur = uni(st->cur);
+  const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
+  const int r0 = uni(inst_r0[m]), n = uni(inst_rows[m]);
+  const int i0 = grp * kR - r0;
+  if (i0 >= n) return;  // alignment rows after the instance's last row
+  rows16<T>(n, i0, min(kR, n - i0), rows_from(spans.b[cur], r0), rows_from(spans.b[cy], r0),
+            rows_from(spans.b[cu], r0), taus[m], ss[m], bsum_s[w], sq_s[w], meta_s[w], flags + m);
+}
+
 }  // namespace
 
 bool x2_band16_fits(int N, int SW, int elem_bytes) { return (int64_t)N * SW * elem_bytes < ((int64_t)1 << 31); }
@@ -534,5 +574,23 @@ template hipError_t launch_x2_band16<double>(int, SpanRot3<double>, const SP2Sta
                                              int32_t *, hipStream_t);
 template hipError_t launch_x2_band16<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
                                             int32_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
+                                  const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
+                                  const StepScratch *ss, int32_t *flags, hipStream_t stream)
+{
+  static_assert(kR % kGroupRows == 0, "a 16-row group is a whole number of 8-row groups");
+  const dim3 grid((ngroups16 + kWpb - 1) / kWpb), block(kWpb * kWave);
+  hipLaunchKernelGGL(k_x2_band16_batch<T>, grid, block, 0, stream, ngroups16, spans, grp_inst, inst_r0, inst_rows,
+                     states, phase32, taus, ss, flags);
+  return hipGetLastError();
+}
+template hipError_t launch_x2_band16_batch<double>(int, SpanRot3<double>, const int32_t *, const int32_t *,
+                                                   const int32_t *, const SP2State *, int32_t, const double *,
+                                                   const StepScratch *, int32_t *, hipStream_t);
+template hipError_t launch_x2_band16_batch<float>(int, SpanRot3<float>, const int32_t *, const int32_t *,
+                                                  const int32_t *, const SP2State *, int32_t, const float *,
+                                                  const StepScratch *, int32_t *, hipStream_t);
 
 }  // namespace ellsp2

@@ -143,19 +143,26 @@ template <typename T>
 hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
                             int32_t *fallback, hipStream_t stream);
 template <typename T>
+hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
+                                  const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
+                                  const StepScratch *ss, int32_t *flags, hipStream_t stream);
+template <typename T>
 hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream);
 template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
 template <typename TS, typename TD>
 hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream);
-// batched step: ngroups groups of kG rows; group -> instance; instance m's rows
-// start at inst_r0[m] and it has inst_rows[m] of them (local columns); per-instance
-// state, drop tolerance, row-output scratch view and fallback flag
+// batched step: ngroups groups of kGroupRows rows; group -> instance; instance m's
+// rows start at inst_r0[m] (a multiple of kBatchAlign) and it has inst_rows[m]
+// of them (local columns); per-instance state, drop tolerance, row-output
+// scratch view and fallback flag.  Takes the matrix-core kernel when the stack
+// fits its 2^31-byte buffer range.
 template <typename T>
 hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                 const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
                                 const StepScratch *ss, int32_t *flags, hipStream_t stream);
-constexpr int kGroupRows = 8;  // rows per wavefront of the span step kernel (instance alignment in a batch)
+constexpr int kGroupRows = 8;   // rows per wavefront of the register-tiled span step kernel
+constexpr int kBatchAlign = 16; // instance alignment in a batch: a whole number of both kernels' row groups
 template <typename TS, typename TD>
 hipError_t launch_span_copy(int N, SpanView<TS> S, SpanView<TD> D, hipStream_t stream);
 
