@@ -141,6 +141,75 @@ def batched_leg(E, synth, torch, count=256):
                                   and reps_b[q]["eta"] == singles[q][1]["eta"] for q in range(count))}
 
 
+def x2_single_leg(E, H, tau=1e-5):
+    """One FP64 X^2 step timed on X0, on the midpoint iterate and on the final
+    iterate of an SP2 solve of the benchmark H at drop tolerance tau (run to
+    its eta floor), from the library's per-launch events and algorithmic bytes."""
+    p = E.sp2_params(N / 4, tau, TARGET, max_iter=200, profile=1)
+    D = E.DeviceEll(N, M_CAP)
+    E.sp2_solve(H.h, D.h, p)  # warm-up
+    rc, rep = E.sp2_solve(H.h, D.h, p)
+    secs, byts = rep["x2_seconds_each"], rep["x2_bytes_each"]
+    k = min(len(secs), len(byts))
+    out = {"tau": tau, "status": int(rc), "iterations": rep["iterations"], "eta_floor": rep["eta"]}
+    for name, q in (("x0", 0), ("mid", k // 2), ("final", k - 1)):
+        if k == 0:
+            break
+        gbs = byts[q] / secs[q] / 1e9
+        out[name] = {"iteration": int(q), "us": float(secs[q] * 1e6), "bytes": int(byts[q]), "GBs": float(gbs),
+                     "hbm_frac": float(gbs / HBM_PEAK_GBS)}
+    return out
+
+
+def accuracy_leg(E, synth, torch, n=131072, b=64):
+    """Mixed precision at N = 131072 (FP32 values and products, FP64 traces,
+    branch, convergence test and final steps) against the FP64 solve of the same
+    H, which equals the FP64 oracle bit for bit (the parity tests): Frobenius
+    difference of the density matrices and the differences of Tr X and Tr(XH)."""
+    import numpy as np
+    import scipy.sparse as sp
+    nnz, idx, val, m = synth.banded_hamiltonian(n, b, seed=0)
+    H = E.DeviceEll.from_host(n, m, nnz, idx, val)
+    # tau = 1e-8 leaves the FP64 solve above eta = 1e-6 at this size (its floor grows with N), so
+    # both solves end with the mixed run's FP64 tolerance
+    out = {"workload": f"banded H N={n} half-bandwidth {b}, N_occ={n // 4}, to ||X^2-X||_F<{TARGET:g}; "
+                       f"FP64 tau {TAU_MIXED64:g}; mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}"}
+
+    def csr(D):
+        N, M, dn, di, dv = D.download()
+        rows = np.repeat(np.arange(N), dn)
+        keep = (np.arange(M)[None, :] < dn[:, None]).reshape(-1)
+        return sp.csr_matrix((dv[keep], (rows, di[keep])), shape=(N, N))
+
+    mats = {}
+    for name, prec, tau in (("f64", E.SP2_F64, TAU_MIXED64), ("mixed", E.SP2_MIXED, TAU_MIXED64)):
+        D = E.DeviceEll(n, M_CAP)
+        p = E.sp2_params(n / 4, tau, TARGET, max_iter=200, precision=prec, tau_fp32=TAU_FP32,
+                         switch_eta=SWITCH_ETA)
+        E.sp2_solve(H.h, D.h, p, history=False)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep = E.sp2_solve(H.h, D.h, p, history=False)
+        torch.cuda.synchronize()
+        out[name] = {"status": int(rc), "solve_ms": (time.perf_counter() - t0) * 1e3,
+                     "iterations": rep["iterations"], "fp32_iterations": rep["fp32_iterations"], "eta": rep["eta"]}
+        mats[name] = csr(D)
+    rows = np.repeat(np.arange(n), nnz)
+    keep = (np.arange(m)[None, :] < nnz[:, None]).reshape(-1)
+    Hc = sp.csr_matrix((val[keep], (rows, idx[keep])), shape=(n, n))
+    X64, X32 = mats["f64"], mats["mixed"]
+    dX = X32 - X64
+    tr64, tr32 = X64.diagonal().sum(), X32.diagonal().sum()
+    txh64, txh32 = X64.multiply(Hc.T).sum(), X32.multiply(Hc.T).sum()
+    out["err_vs_f64"] = {"fro_dX": float(np.sqrt(dX.multiply(dX).sum())),
+                         "fro_dX_rel": float(np.sqrt(dX.multiply(dX).sum() / X64.multiply(X64).sum())),
+                         "max_abs_dX": float(abs(dX).max()) if dX.nnz else 0.0,
+                         "abs_dTrX": float(abs(tr32 - tr64)), "abs_dTrXH": float(abs(txh32 - txh64)),
+                         "TrX_f64": float(tr64), "TrXH_f64": float(txh64)}
+    out["speedup_mixed_vs_f64"] = out["f64"]["solve_ms"] / out["mixed"]["solve_ms"]
+    return out
+
+
 def dense_leg(E, synth, torch, n=8192, b=512):
     """Dense-block variant: N = 8192 dense H (half-bandwidth 512), SP2 to
     ||X^2-X||_F < 1e-6 with BF16x3 products (then FP64 steps) and in plain FP64."""
@@ -181,9 +250,16 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the N = 131072 mixed-vs-FP64 comparison")
+    ap.add_argument("--no-x2-single", action="store_true", help="skip the tau = 1e-5 single X^2 timings")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the FP64 solves of the headline line (for profiling the step kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling the HBM counters)")
     args = ap.parse_args()
+    if args.main_only:
+        args.no_cpu = args.no_mixed = args.no_batched = args.no_dense = True
+        args.no_accuracy = args.no_x2_single = True
     if args.copy_calibration:
         copy_calibration()
         return
@@ -274,10 +350,14 @@ def main():
                                "2X - X^2 on the span form)",
                      "bytes_per_launch": x2_bytes / launches},
     }
+    if not args.no_x2_single:
+        line["x2_single_tau1e-5"] = x2_single_leg(E, H)
     if not args.no_batched:
         line["batched"] = batched_leg(E, synth, torch)
     if not args.no_dense:
         line["dense"] = dense_leg(E, synth, torch)
+    if not args.no_accuracy:
+        line["mixed_accuracy"] = accuracy_leg(E, synth, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(nnz, idx, val, M)
     print(json.dumps(line), flush=True)

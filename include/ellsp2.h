@@ -167,6 +167,11 @@ typedef struct {
   int64_t x2_bytes;        /* algorithmic bytes of those kernels: every stored entry of X read once
                               and of the pruned X^2 written once, value + index, plus nnz arrays */
   int32_t x2_launches;     /* number of those kernels */
+  /* caller-owned host arrays of length max_iter, or NULL; filled when p->profile != 0:
+     per X^2 step kernel that did work, in launch order (one per iteration), its duration
+     and its algorithmic bytes as counted in x2_bytes */
+  double *hist_x2_seconds;
+  int64_t *hist_x2_bytes;
 } sp2_report_t;
 
 /* SP2 purification of the FP64 Hamiltonian H into the density matrix D

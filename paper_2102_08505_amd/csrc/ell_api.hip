@@ -1179,12 +1179,15 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       float t = 0.f;
       HIP_TRY(hipEventElapsedTime(&t, m.first, m.second));
       sec += t * 1e-3;
+      if (r->hist_x2_seconds && launches < p->max_iter) r->hist_x2_seconds[launches] = t * 1e-3;
       ++launches;
     }
     int64_t bytes = 0;
     for (int q = 0; q < n; ++q) {
       const int64_t sv = pr[q] ? 4 : 8;
-      bytes += nx[q] * (sv + 4) + 4LL * N + ny[q] * (sv + 4) + 4LL * N;
+      const int64_t bq = nx[q] * (sv + 4) + 4LL * N + ny[q] * (sv + 4) + 4LL * N;
+      if (r->hist_x2_bytes) r->hist_x2_bytes[q] = bq;
+      bytes += bq;
     }
     r->x2_seconds = sec;
     r->x2_bytes = bytes;

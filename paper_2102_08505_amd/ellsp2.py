@@ -28,6 +28,7 @@ DENSE_F64, DENSE_BF16X3 = 0, 1
 
 i32p = C.POINTER(C.c_int32)
 i8p = C.POINTER(C.c_int8)
+i64p = C.POINTER(C.c_int64)
 f64p = C.POINTER(C.c_double)
 vp = C.c_void_p
 
@@ -45,7 +46,8 @@ class SP2Report(C.Structure):
                 ("emin", C.c_double), ("emax", C.c_double), ("seconds", C.c_double),
                 ("hist_trx", f64p), ("hist_trx2", f64p), ("hist_eta2", f64p), ("hist_up", i8p),
                 ("hist_maxw", i32p), ("hist_prec", i8p), ("x2_seconds", C.c_double),
-                ("x2_bytes", C.c_int64), ("x2_launches", C.c_int32)]
+                ("x2_bytes", C.c_int64), ("x2_launches", C.c_int32), ("hist_x2_seconds", f64p),
+                ("hist_x2_bytes", i64p)]
 
 
 _lib = None
@@ -213,6 +215,8 @@ class _Hist:
         self.up = np.zeros(n, np.int8)
         self.maxw = np.zeros(n, np.int32)
         self.prec = np.zeros(n, np.int8)
+        self.x2_seconds = np.zeros(n)
+        self.x2_bytes = np.zeros(n, np.int64)
 
     def attach(self, r):
         r.hist_trx = _ptr(self.trx, f64p)
@@ -221,6 +225,8 @@ class _Hist:
         r.hist_up = _ptr(self.up, i8p)
         r.hist_maxw = _ptr(self.maxw, i32p)
         r.hist_prec = _ptr(self.prec, i8p)
+        r.hist_x2_seconds = _ptr(self.x2_seconds, f64p)
+        r.hist_x2_bytes = _ptr(self.x2_bytes, i64p)
 
 
 def _report(r, h):
@@ -228,7 +234,8 @@ def _report(r, h):
     d = {k: getattr(r, k) for k, _ in SP2Report._fields_ if not k.startswith("hist_")}
     if h is not None:
         d.update(trx=h.trx[:n].copy(), trx2=h.trx2[:n].copy(), eta2=h.eta2[:n].copy(), up=h.up[:n].copy(),
-                 maxw=h.maxw[:n].copy(), prec=h.prec[:n].copy())
+                 maxw=h.maxw[:n].copy(), prec=h.prec[:n].copy(),
+                 x2_seconds_each=h.x2_seconds[:r.x2_launches].copy(), x2_bytes_each=h.x2_bytes[:n].copy())
     return d
 
 
