@@ -113,30 +113,38 @@ __device__ __forceinline__ double dpp(double v)
 }
 
 // Running output state of one row: first and last kept column, kept count.
-// Tiles come in ascending column order.  A row's span output holds exactly
-// its interval [first, last]: a tile writes its columns from `first` up to
-// its own last kept column, and when a tile keeps something after a run of
-// tiles that kept nothing, the columns between get their zeros then.
+// Blocks come in ascending column order.  A row's span output holds exactly
+// its interval [first, last]: a block writes its columns from `first` up to
+// its own last kept column, and when a block keeps something after blocks
+// that kept nothing, the columns between get their zeros then.
 struct RowRun {
   int first = INT_MAX, last = -1, count = 0;
-  // seg: kept columns c0 .. c0 + 15 of this tile.  Returns the last column
-  // this tile writes (c0 - 1: none) and, in gap_lo .. c0 - 1, the earlier
-  // columns that still need zeros.
-  __device__ int add(uint32_t seg, int c0, int &gap_lo)
+  // lo, hi: kept columns p0 .. p0 + 31 and p0 + 32 .. p0 + 63 of this block.
+  // Returns the last column the block writes (p0 - 1: none) and, in
+  // gap_lo .. p0 - 1, the earlier columns that still need zeros.
+  __device__ int add(uint32_t lo, uint32_t hi, int p0, int &gap_lo)
   {
-    gap_lo = seg && last >= 0 ? last + 1 : c0;
-    count += __popc(seg);
-    const int f = seg ? c0 + __ffs(seg) - 1 : INT_MAX;
+    const bool any = (lo | hi) != 0;
+    gap_lo = any && last >= 0 ? last + 1 : p0;
+    count += __popc(lo) + __popc(hi);
+    const int f = lo ? p0 + __ffs(lo) - 1 : hi ? p0 + 31 + __ffs(hi) : INT_MAX;
     first = min(first, f);
-    const int l = c0 + 31 - __clz(seg);  // c0 - 1 when seg == 0
-    last = seg ? l : last;
+    const int l = hi ? p0 + 63 - __clz(hi) : p0 + 31 - __clz(lo);  // p0 - 1 when none
+    last = any ? l : last;
     return l;
   }
   __device__ int length() const { return last >= 0 ? last - first + 1 : 0; }
 };
 
-// Span output of one tile of one row, lane column col: the tile's columns up
-// to its last kept one (lastw).
+// This lane's row's kept columns of a block from the four tiles' wave masks.
+__device__ __forceinline__ void row_bits(const uint64_t (&m)[4], int q, uint32_t &lo, uint32_t &hi)
+{
+  lo = seg16(m[0], q) | seg16(m[1], q) << 16;
+  hi = seg16(m[2], q) | seg16(m[3], q) << 16;
+}
+
+// Span output of one tile of one row, lane column col: the columns from the
+// row's first kept one up to the block's last kept one (lastw).
 template <typename T>
 __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t rs, int first, int lastw, int col, int row0, int SW,
                                     bool act, T v)
@@ -144,8 +152,8 @@ __device__ __forceinline__ void put(__amdgpu_buffer_rsrc_t rs, int first, int la
   const int o = col - first;
   st(rs, at<T>(act && col <= lastw && (unsigned)o < (unsigned)SW, row0 + o), v);
 }
-// Zeros for the columns gap_lo .. c0 - 1 of a row (tiles that kept nothing,
-// followed by one that keeps something).
+// Zeros for the columns gap_lo .. c0 - 1 of a row (blocks that kept nothing
+// after its last kept column, followed by one that keeps something).
 template <typename T>
 __device__ void fill_gap(__amdgpu_buffer_rsrc_t rs, int first, int gap_lo, int c0, int r, int row0, int SW, bool act)
 {
@@ -397,27 +405,29 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
         const double d = (double)yk[p] - (double)x;
         e[p] = d * d;
       }
-      int gy[kP], gu[kP];
+      uint64_t my[kP], mu[kP];
 #pragma unroll
       for (int p = 0; p < kP; ++p) {
-        const int c0 = p0 + 16 * p;
-        const int ly = ry[t].add(seg16(__ballot(ky[p]), q), c0, gy[p]);
-        put<T>(yr, ry[t].first, ly, c0 + r, i * SW, SW, act, yk[p]);
-        const int lu = ru[t].add(seg16(__ballot(ku[p]), q), c0, gu[p]);
-        put<T>(ur, ru[t].first, lu, c0 + r, i * SW, SW, act, uk[p]);
+        my[p] = __ballot(ky[p]);
+        mu[p] = __ballot(ku[p]);
+      }
+      uint32_t lo, hi;
+      int gy, gu;
+      row_bits(my, q, lo, hi);
+      const int ly = ry[t].add(lo, hi, p0, gy);
+      row_bits(mu, q, lo, hi);
+      const int lu = ru[t].add(lo, hi, p0, gu);
+#pragma unroll
+      for (int p = 0; p < kP; ++p) {
+        put<T>(yr, ry[t].first, ly, p0 + 16 * p + r, i * SW, SW, act, yk[p]);
+        put<T>(ur, ru[t].first, lu, p0 + 16 * p + r, i * SW, SW, act, uk[p]);
       }
       // the norm's squared differences, to the block table [row][column]
 #pragma unroll
       for (int p = 0; p < kP; ++p) sq[rr * kWave + 16 * p + r] = e[p];
-      bool gap = false;
-#pragma unroll
-      for (int p = 0; p < kP; ++p) gap = gap || gy[p] < p0 + 16 * p || gu[p] < p0 + 16 * p;
-      if (__ballot(gap)) {
-#pragma unroll
-        for (int p = 0; p < kP; ++p) {
-          fill_gap<T>(yr, ry[t].first, gy[p], p0 + 16 * p, r, i * SW, SW, act);
-          fill_gap<T>(ur, ru[t].first, gu[p], p0 + 16 * p, r, i * SW, SW, act);
-        }
+      if (__ballot(gy < p0 || gu < p0)) {
+        fill_gap<T>(yr, ry[t].first, gy, p0, r, i * SW, SW, act);
+        fill_gap<T>(ur, ru[t].first, gu, p0, r, i * SW, SW, act);
       }
       if (diag) {
 #pragma unroll
