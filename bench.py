@@ -9,17 +9,21 @@ seed 0, N_occ = N/4, capacity M = 256, drop tolerance 1e-8, run until
 region starts.
 
 value = algorithmic X^2 bytes of every step kernel in the timed steps divided
-by the wall time of those steps (GB/s); the roofline object gives the step
-kernel alone (bytes per launch / mean launch time from hipEvents recorded by
+by the wall time of those steps (GB/s); the timed solves record no events.  The
+roofline object gives the step kernel alone, from one more solve outside the
+timed region (bytes per launch / mean launch time from hipEvents recorded by
 the library around every launch on the solve's stream).  Algorithmic bytes of
 one X^2: every stored entry of X read once and of the pruned X^2 written once
 (8-byte value + 4-byte index; 4-byte values in FP32 steps) plus the two
 row-width arrays.
 
 Also reported: the mixed-precision solve (FP32 phase, then FP64 steps) to the
-same target; the batched workload (256 instances of uneven size in one call,
-against solving them one by one); the dense-block variant at N = 8192 (BF16x3
-against FP64 MFMA products); and the oracle on the host cores as cpu_baseline.
+same target; single X^2 steps at tau = 1e-5 on X0, the midpoint and the final
+iterate; the mixed solve at N = 131072 against the FP64 solve (differences of
+X, Tr X and Tr(XH)); the batched workload (256 instances of uneven size in one
+call, against solving them one by one); the dense-block variant at N = 8192
+(BF16x3 against FP64 MFMA products); and the oracle on the host cores as
+cpu_baseline.
 """
 from __future__ import annotations
 
@@ -281,7 +285,7 @@ def main():
     H = E.DeviceEll.from_host(N, M, nnz, idx, val, stream=stream)
     D = E.DeviceEll(N, M_CAP, stream=stream)
 
-    def solve(precision, profile=1):
+    def solve(precision, profile=0):
         tau = TAU if precision == E.SP2_F64 else TAU_MIXED64
         p = E.sp2_params(N / 4, tau, TARGET, max_iter=200, precision=precision, tau_fp32=TAU_FP32,
                          switch_eta=SWITCH_ETA, profile=profile)
@@ -300,12 +304,15 @@ def main():
     wall = time.perf_counter() - t0
     rcs = {rc for rc, _ in reps}
     x2_bytes = sum(r["x2_bytes"] for _, r in reps)
-    x2_sec = sum(r["x2_seconds"] for _, r in reps)
-    launches = sum(r["x2_launches"] for _, r in reps)
     last = reps[-1][1]
     ms_per_step = wall / args.steps * 1e3
     value = x2_bytes / wall / 1e9
-    achieved = (x2_bytes / launches) / (x2_sec / launches) / 1e9
+    # the step kernel's own rate: one more solve, outside the timed region, with
+    # hipEvents around every X^2 launch on the solve's stream
+    _, prof = solve(E.SP2_F64, profile=1)
+    launches = prof["x2_launches"]
+    x2_sec = prof["x2_seconds"]
+    achieved = (prof["x2_bytes"] / launches) / (x2_sec / launches) / 1e9
 
     mixed = None
     if not args.no_mixed:
@@ -341,14 +348,14 @@ def main():
                    "N": N, "bandwidth": B, "M": M_CAP, "tau": TAU, "idem_target": TARGET, "n_occ": N // 4},
         "sp2": {"status": sorted(rcs), "iterations": last["iterations"], "eta": last["eta"],
                 "final_M": last["final_M"], "solve_ms_device": last["seconds"] * 1e3,
-                "x2_launches_per_solve": last["x2_launches"],
+                "x2_launches_per_solve": launches,
                 "x2_ms_per_launch": x2_sec / launches * 1e3},
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_x2_band16 (fused X^2 on FP64 matrix cores, prune, traces, norm, "
                                "2X - X^2 on the span form)",
-                     "bytes_per_launch": x2_bytes / launches},
+                     "bytes_per_launch": prof["x2_bytes"] / launches},
     }
     if not args.no_x2_single:
         line["x2_single_tau1e-5"] = x2_single_leg(E, H)

@@ -162,14 +162,13 @@ typedef struct {
   int8_t *hist_up;         /* 1: 2X - X^2 taken, 0: X^2 taken, -1: no update (stop) */
   int32_t *hist_maxw;      /* widest row of the pruned X^2 */
   int8_t *hist_prec;       /* 1: FP32 step, 0: FP64 step */
-  /* filled when p->profile != 0 (zero otherwise) */
-  double x2_seconds;       /* summed duration of the X^2 step kernels that did work */
-  int64_t x2_bytes;        /* algorithmic bytes of those kernels: every stored entry of X read once
-                              and of the pruned X^2 written once, value + index, plus nnz arrays */
-  int32_t x2_launches;     /* number of those kernels */
-  /* caller-owned host arrays of length max_iter, or NULL; filled when p->profile != 0:
-     per X^2 step kernel that did work, in launch order (one per iteration), its duration
-     and its algorithmic bytes as counted in x2_bytes */
+  double x2_seconds;       /* p->profile != 0: summed duration of the X^2 step kernels that did
+                              work (hipEvents around each launch); else 0 */
+  int64_t x2_bytes;        /* algorithmic bytes of the X^2 products: every stored entry of X read
+                              once and of the pruned X^2 written once, value + index, plus nnz arrays */
+  int32_t x2_launches;     /* p->profile != 0: number of those kernels; else 0 */
+  /* caller-owned host arrays of length max_iter, or NULL: per iteration, the duration of its
+     X^2 step kernel (p->profile != 0 only) and its algorithmic bytes as counted in x2_bytes */
   double *hist_x2_seconds;
   int64_t *hist_x2_bytes;
 } sp2_report_t;

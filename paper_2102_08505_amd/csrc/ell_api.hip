@@ -1171,6 +1171,14 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     if (r->hist_prec) r->hist_prec[q] = pr[q];
     if (r->hist_maxw) r->hist_maxw[q] = mw[q];
   }
+  int64_t bytes = 0;
+  for (int q = 0; q < n; ++q) {
+    const int64_t sv = pr[q] ? 4 : 8;
+    const int64_t bq = nx[q] * (sv + 4) + 4LL * N + ny[q] * (sv + 4) + 4LL * N;
+    if (r->hist_x2_bytes) r->hist_x2_bytes[q] = bq;
+    bytes += bq;
+  }
+  r->x2_bytes = bytes;
   if (S.profile) {
     double sec = 0.0;
     int launches = 0;
@@ -1182,15 +1190,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       if (r->hist_x2_seconds && launches < p->max_iter) r->hist_x2_seconds[launches] = t * 1e-3;
       ++launches;
     }
-    int64_t bytes = 0;
-    for (int q = 0; q < n; ++q) {
-      const int64_t sv = pr[q] ? 4 : 8;
-      const int64_t bq = nx[q] * (sv + 4) + 4LL * N + ny[q] * (sv + 4) + 4LL * N;
-      if (r->hist_x2_bytes) r->hist_x2_bytes[q] = bq;
-      bytes += bq;
-    }
     r->x2_seconds = sec;
-    r->x2_bytes = bytes;
     r->x2_launches = launches;
   }
   return final_status;
