@@ -698,13 +698,16 @@ struct Solver {
   StepMem step;
   DevMem state, hist_trx, hist_trx2, hist_eta2, hist_up, hist_prec, hist_maxw, hist_nnzx, hist_nnzy;
   DevMem glo, ghi, gout, flags, wmax, total;
-  SP2State *host_state = nullptr;
+  SP2State *host_state = nullptr;  // host working copy (pinned): [0], and the two poll slots [1], [2]
+  hipEvent_t polled[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // step-kernel launches when profiling
   bool profile = false;
   ~Solver()
   {
     if (host_state) (void)hipHostFree(host_state);
+    for (hipEvent_t e : polled)
+      if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
   SP2Hist hist() const
@@ -858,7 +861,8 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   HIP_TRY(S.flags.alloc(sizeof(int32_t)));
   HIP_TRY(S.wmax.alloc(sizeof(int32_t)));
   HIP_TRY(S.total.alloc(sizeof(unsigned long long)));
-  HIP_TRY(hipHostMalloc((void **)&S.host_state, sizeof(SP2State), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&S.host_state, 3 * sizeof(SP2State), hipHostMallocDefault));
+  for (hipEvent_t &e : S.polled) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   hipEvent_t t0, t1;
   HIP_TRY(S.mark(&t0));
@@ -976,33 +980,64 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     return ELL_OK;
   };
 
+  // A batch is `poll` iterations followed by a copy of the device state into a
+  // pinned slot.  The next batch is queued before the host waits for the
+  // current one, so the device never idles while the host reads the state; if
+  // the current batch stopped, every kernel of the next one returns at once.
+  SP2State *slot = S.host_state + 1;
+  struct Queued {
+    size_t m0 = 0, m1 = 0;  // its step-kernel marks (profiling)
+    int k = 0;              // its poll slot
+  };
+  auto enqueue = [&](int k, Queued &b) -> int {
+    b.k = k;
+    b.m0 = S.marks.size();
+    for (int q = 0; q < poll; ++q) {
+      const int e = hs.phase32 ? launch_iteration<float>(S, pipe, S32, W32, (float)p->tau_fp32, cfg)
+                               : launch_iteration<double>(S, pipe, S64, W64, p->tau, cfg);
+      if (e) return e;
+    }
+    b.m1 = S.marks.size();
+    HIP_TRY(hipMemcpyAsync(&slot[k], S.state.p, sizeof(SP2State), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(S.polled[k], st));
+    return ELL_OK;
+  };
+
   int status = ST_RUNNING;
   // every batch advances the iteration count or changes capacity, precision or
   // pipeline (each a bounded number of times), so this bounds the loop even if
   // the device control misbehaved
   const int64_t max_batches = (int64_t)p->max_iter + 64;
+  bool fresh = true;
+  Queued cur, nxt;
   for (int64_t batch = 0;; ++batch) {
     if (batch > max_batches) {
       g_last_error = "sp2_solve: device control block did not reach a stop";
       return ELL_EDEVICE;
     }
-    const int iter_before = hs.iter;
-    const size_t mark0 = S.marks.size();
-    for (int q = 0; q < poll; ++q) {
-      rc = hs.phase32 ? launch_iteration<float>(S, pipe, S32, W32, (float)p->tau_fp32, cfg)
-                      : launch_iteration<double>(S, pipe, S64, W64, p->tau, cfg);
-      if (rc) return rc;
+    if (fresh) {
+      if ((rc = enqueue(0, cur))) return rc;
+      fresh = false;
     }
-    HIP_TRY(hipMemcpyAsync(&hs, S.state.p, sizeof(hs), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    const int iter_before = hs.iter;
+    if ((rc = enqueue(1 - cur.k, nxt))) return rc;
+    HIP_TRY(hipEventSynchronize(S.polled[cur.k]));
+    hs = slot[cur.k];
     if (S.profile) {
       // step kernels launched after the stop returned at once: drop them
       const bool redo = hs.stop && (hs.status == ELL_EOVERFLOW || hs.status == ST_FALLBACK);
       const int worked = hs.iter - iter_before + (redo ? 1 : 0);
-      for (size_t q = mark0; q < S.marks.size(); ++q)
-        if ((int)(q - mark0) >= worked) S.marks[q].first = nullptr;
+      for (size_t q = cur.m0; q < cur.m1; ++q)
+        if ((int)(q - cur.m0) >= worked) S.marks[q].first = nullptr;
     }
-    if (!hs.stop) continue;
+    if (!hs.stop) {
+      cur = nxt;
+      continue;
+    }
+    // the batch queued behind it saw the stop flag: let it drain
+    HIP_TRY(hipStreamSynchronize(st));
+    for (size_t q = nxt.m0; q < nxt.m1; ++q) S.marks[q].first = nullptr;
+    fresh = true;
     if (hs.status == ELL_EOVERFLOW) {
       const int32_t need = hs.need_width;
       if (pipe == PIPE_SPAN) {

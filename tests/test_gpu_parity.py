@@ -286,3 +286,45 @@ def test_sp2_long_range_coupling_falls_back_to_ellpack():
     Dd = E.DeviceEll(N, 64, E.ELL_F64)
     rc_g, rep_g = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-7, 1e-6, max_iter=120))
     assert_same_trajectory(o, (rc_g, Dd, rep_g))
+
+
+def test_sp2_solves_on_alternating_streams_reuse_scratch_safely():
+    """Solves on two streams in turn, with no synchronisation between them on
+    the caller's side: scratch blocks released by one stream's solve are taken
+    by the other's (after the releasing stream's event), and every result
+    equals the solve on the default stream."""
+    import torch
+    N, b = 600, 12
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=5)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    p = E.sp2_params(N // 4, 1e-8, 1e-7)
+    Dref = E.DeviceEll(N, 64, E.ELL_F64)
+    rc_ref, rep_ref = E.sp2_solve(Hd.h, Dref.h, p)
+    ref = Dref.download()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for q in range(6):
+        D = E.DeviceEll(N, 64, E.ELL_F64, stream=streams[q % 2])
+        rc, rep = E.sp2_solve(Hd.h, D.h, p)
+        outs.append((rc, rep, D))
+    torch.cuda.synchronize()
+    for rc, rep, D in outs:
+        assert rc == rc_ref and rep["iterations"] == rep_ref["iterations"]
+        assert np.array_equal(rep["eta2"].view(np.uint64), rep_ref["eta2"].view(np.uint64))
+        got = D.download()
+        assert all(np.array_equal(a, c) for a, c in zip(got[2:], ref[2:]))
+
+
+def test_sp2_report_per_iteration_bytes_and_times():
+    N, b = 300, 8
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=6)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    Dd = E.DeviceEll(N, 64, E.ELL_F64)
+    rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-8, 1e-7))
+    assert rc == E.ELL_OK and rep["x2_launches"] == 0 and rep["x2_seconds"] == 0.0
+    assert rep["x2_bytes"] == int(rep["x2_bytes_each"].sum()) > 0
+    rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-8, 1e-7, profile=1))
+    assert rc == E.ELL_OK and rep["x2_launches"] == rep["iterations"]
+    each = rep["x2_seconds_each"]
+    assert len(each) == rep["x2_launches"] and (each > 0).all()
+    assert abs(each.sum() - rep["x2_seconds"]) <= 1e-9 * rep["x2_launches"] + 1e-12
