@@ -81,6 +81,8 @@ def lib():
                                  i32p, i32p, f32p, f64p, f64p, i32p]
         L.orc_trace_f64.restype = C.c_double
         L.orc_trace_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p]
+        L.orc_trace_product_f64.restype = C.c_double
+        L.orc_trace_product_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p, f64p]
         L.orc_norm2_f64.restype = C.c_double
         L.orc_norm2_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p,
                                     f64p, f64p]
@@ -193,6 +195,13 @@ def x2(A, tau, M2=None):
 
 def trace(A):
     return lib().orc_trace_f64(A.N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p), _p(_f64(A.val), f64p))
+
+
+def trace_product(A, B):
+    """Tr(AB) = sum_ij A_ij B_ji (FP32 values widened to double)."""
+    assert A.N == B.N
+    return lib().orc_trace_product_f64(A.N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p), _p(_f64(A.val), f64p),
+                                       B.M, _p(B.nnz, i32p), _p(B.idx, i32p), _p(_f64(B.val), f64p))
 
 
 def norm2(X, Y):

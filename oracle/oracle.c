@@ -195,6 +195,33 @@ double orc_trace_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *id
   return t;
 }
 
+/* Tr(AB) = sum_i sum_j A_ij B_ji (the energy Tr(DH) of the ExaSP2 output, in
+ * the paper's "ExaSP2 Application" section).  Row term t_i: fused
+ * multiply-adds t = fma(A_ij, B_ji, t) over the stored entries of row i of A
+ * in ascending column j, B_ji taken from row j of B (skipped where B stores no
+ * (j, i) entry); Tr(AB) = pairwise tree of the t_i. */
+double orc_trace_product_f64(int32_t N, int32_t MA, const int32_t *nnzA, const int32_t *idxA, const double *valA,
+                             int32_t MB, const int32_t *nnzB, const int32_t *idxB, const double *valB)
+{
+  double *t = (double *)malloc((size_t)N * sizeof(double));
+  if (!t) return NAN;
+  for (int32_t i = 0; i < N; ++i) {
+    double acc = 0.0;
+    for (int32_t s = 0; s < nnzA[i]; ++s) {
+      const int32_t j = idxA[(int64_t)i * MA + s];
+      for (int32_t u = 0; u < nnzB[j]; ++u)
+        if (idxB[(int64_t)j * MB + u] == i) {
+          acc = fma(valA[(int64_t)i * MA + s], valB[(int64_t)j * MB + u], acc);
+          break;
+        }
+    }
+    t[i] = acc;
+  }
+  const double r = orc_pairwise(N, t);
+  free(t);
+  return r;
+}
+
 /* Row term e_i: the pairwise tree over the row's N column positions of
  * q_j = d*d with d = X2_ij - X_ij (absent entries are 0, so q_j = +0 wherever
  * neither matrix stores column j); eta^2 = pairwise tree of the e_i.  The tree

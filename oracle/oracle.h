@@ -70,6 +70,11 @@ int orc_x2_f32(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, con
 
 /* Trace (pairwise tree over the diagonal). */
 double orc_trace_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val);
+/* Tr(AB) = sum_i sum_j A_ij B_ji: per row of A an ascending-j fma chain of
+ * A_ij * B_ji over the stored (j, i) entries of B, then the pairwise tree over
+ * rows.  FP64 values (FP32 inputs are widened exactly by the caller). */
+double orc_trace_product_f64(int32_t N, int32_t MA, const int32_t *nnzA, const int32_t *idxA, const double *valA,
+                             int32_t MB, const int32_t *nnzB, const int32_t *idxB, const double *valB);
 
 /* eta^2 = ||X2 - X||_F^2; e (length N, may be NULL) receives the row terms. */
 double orc_norm2_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *idxX, const double *valX,

@@ -511,3 +511,52 @@ def test_norm_equals_pairwise_over_dense_rows():
         eta2, e = oracle.norm2(X, Y)
         for i in range(N):
             assert e[i] == exact.pairwise_recursive((Dy[i] - Dx[i]) ** 2), (N, i)
+
+
+# ---- Tr(AB) --------------------------------------------------------------------------
+
+def _trace_product_exact(DA, DB):
+    """Per row i, the exact-arithmetic fma chain over ascending j of A_ij B_ji
+    (only where both are nonzero), each step rounded once; then the pairwise
+    tree of the row terms by its recursive definition."""
+    N = DA.shape[0]
+    t = []
+    for i in range(N):
+        acc = 0.0
+        for j in range(N):
+            if DA[i, j] != 0 and DB[j, i] != 0:
+                acc = exact.fma64(DA[i, j], DB[j, i], acc)
+        t.append(acc)
+    return exact.pairwise_recursive(t)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_trace_product_bit_exact_against_brute_force(f32):
+    rng = np.random.default_rng(31 + f32)
+    dt = np.float32 if f32 else np.float64
+    DA, A = random_sparse(13, 0.4, rng, dtype=dt, extra=[("empty", 2), ("full", 4)])
+    DB, B = random_sparse(13, 0.4, rng, dtype=dt, extra=[("single", 7), ("diag", 1)])
+    got = oracle.trace_product(A, B)
+    ref = _trace_product_exact(DA.astype(np.float64), DB.astype(np.float64))
+    assert got == ref
+    # Tr(AB) = Tr(BA) in exact arithmetic; numpy's product agrees to rounding
+    assert abs(got - np.trace(DA.astype(np.float64) @ DB.astype(np.float64))) <= 1e-12 * np.abs(DA).sum() * np.abs(DB).max()
+    assert abs(got - oracle.trace_product(B, A)) <= 1e-12 * np.abs(DA).sum() * np.abs(DB).max()
+
+
+def test_trace_product_of_x_with_itself_is_the_unpruned_trace_of_x2():
+    """Tr(XX) runs the chain of the diagonal of X^2: the same bits as the trace
+    of the unpruned diagonal that the product reports."""
+    nnz, idx, val, M = synth.banded_hamiltonian(200, 6, seed=11)
+    X = oracle.Ell(200, M, nnz, idx, val)
+    rc, _, _, d2, _ = oracle.x2(X, 1e-3)
+    assert rc == 0
+    assert oracle.trace_product(X, X) == oracle.pairwise(d2)
+
+
+def test_trace_product_diagonal_closed_form():
+    a = np.array([0.5, -0.25, 2.0, 0.0, 1.5])
+    b = np.array([4.0, 8.0, -0.5, 3.0, 0.0])
+    A = oracle.Ell(5, 1, (a != 0).astype(np.int32), np.where(a != 0, np.arange(5), -1).astype(np.int32), a.copy())
+    B = oracle.Ell(5, 1, (b != 0).astype(np.int32), np.where(b != 0, np.arange(5), -1).astype(np.int32), b.copy())
+    assert oracle.trace_product(A, B) == float((a * b).sum())  # dyadic: every sum is exact
