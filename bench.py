@@ -38,6 +38,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector and matrix peak
 N, B, M_CAP = 32768, 64, 256
 TAU, TARGET = 1e-8, 1e-6
 # mixed: FP32 phase at 1e-7, FP64 tail at a tighter 1e-9 (the FP32 phase leaves
@@ -185,7 +186,7 @@ def accuracy_leg(E, synth, torch, n=131072, b=64):
         keep = (np.arange(M)[None, :] < dn[:, None]).reshape(-1)
         return sp.csr_matrix((dv[keep], (rows, di[keep])), shape=(N, N))
 
-    mats = {}
+    mats, energy = {}, {}
     for name, prec, tau in (("f64", E.SP2_F64, TAU_MIXED64), ("mixed", E.SP2_MIXED, TAU_MIXED64)):
         D = E.DeviceEll(n, M_CAP)
         p = E.sp2_params(n / 4, tau, TARGET, max_iter=200, precision=prec, tau_fp32=TAU_FP32,
@@ -198,13 +199,13 @@ def accuracy_leg(E, synth, torch, n=131072, b=64):
         out[name] = {"status": int(rc), "solve_ms": (time.perf_counter() - t0) * 1e3,
                      "iterations": rep["iterations"], "fp32_iterations": rep["fp32_iterations"], "eta": rep["eta"]}
         mats[name] = csr(D)
-    rows = np.repeat(np.arange(n), nnz)
-    keep = (np.arange(m)[None, :] < nnz[:, None]).reshape(-1)
-    Hc = sp.csr_matrix((val[keep], (rows, idx[keep])), shape=(n, n))
+        rc_e, energy[name] = E.ellpack_trace_product(D.h, H.h)  # Tr(XH) on the device
+        if rc_e != E.ELL_OK:
+            raise RuntimeError(E.ellpack_strerror(rc_e))
     X64, X32 = mats["f64"], mats["mixed"]
     dX = X32 - X64
     tr64, tr32 = X64.diagonal().sum(), X32.diagonal().sum()
-    txh64, txh32 = X64.multiply(Hc.T).sum(), X32.multiply(Hc.T).sum()
+    txh64, txh32 = energy["f64"], energy["mixed"]
     out["err_vs_f64"] = {"fro_dX": float(np.sqrt(dX.multiply(dX).sum())),
                          "fro_dX_rel": float(np.sqrt(dX.multiply(dX).sum() / X64.multiply(X64).sum())),
                          "max_abs_dX": float(abs(dX).max()) if dX.nnz else 0.0,
@@ -285,11 +286,11 @@ def main():
     H = E.DeviceEll.from_host(N, M, nnz, idx, val, stream=stream)
     D = E.DeviceEll(N, M_CAP, stream=stream)
 
-    def solve(precision, profile=0):
+    def solve(precision, profile=0, history=False):
         tau = TAU if precision == E.SP2_F64 else TAU_MIXED64
         p = E.sp2_params(N / 4, tau, TARGET, max_iter=200, precision=precision, tau_fp32=TAU_FP32,
                          switch_eta=SWITCH_ETA, profile=profile)
-        rc, rep = E.sp2_solve(H.h, D.h, p, history=False)
+        rc, rep = E.sp2_solve(H.h, D.h, p, history=history)
         return rc, rep
 
     for _ in range(args.warmup):
@@ -309,10 +310,21 @@ def main():
     value = x2_bytes / wall / 1e9
     # the step kernel's own rate: one more solve, outside the timed region, with
     # hipEvents around every X^2 launch on the solve's stream
-    _, prof = solve(E.SP2_F64, profile=1)
+    _, prof = solve(E.SP2_F64, profile=1, history=True)
     launches = prof["x2_launches"]
     x2_sec = prof["x2_seconds"]
     achieved = (prof["x2_bytes"] / launches) / (x2_sec / launches) / 1e9
+    # arithmetic roofline of the last product: D is the iterate whose X^2 it computed;
+    # its multiply-adds F = sum_i sum_{k in row i} nnz(row k), counted on the host
+    _, dM, dn, di, _ = D.download()
+    di = di.reshape(-1, dM)
+    keep = np.arange(dM)[None, :] < dn[:, None]
+    F = int(dn.astype(np.int64)[di[keep]].sum())
+    t_last = float(prof["x2_seconds_each"][-1])
+    b_last = int(prof["x2_bytes_each"][-1])
+    alu = {"flops_last_launch": 2 * F, "seconds_last_launch": t_last, "achieved_tflops": 2 * F / t_last / 1e12,
+           "peak_tflops": FP64_PEAK_TFLOPS, "frac": 2 * F / t_last / 1e12 / FP64_PEAK_TFLOPS,
+           "intensity_flop_per_byte": 2 * F / b_last, "ridge_flop_per_byte": FP64_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS}
 
     mixed = None
     if not args.no_mixed:
@@ -355,7 +367,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_x2_band16 (fused X^2 on FP64 matrix cores, prune, traces, norm, "
                                "2X - X^2 on the span form)",
-                     "bytes_per_launch": prof["x2_bytes"] / launches},
+                     "bytes_per_launch": prof["x2_bytes"] / launches,
+                     "alu": alu},
     }
     if not args.no_x2_single:
         line["x2_single_tau1e-5"] = x2_single_leg(E, H)

@@ -135,6 +135,17 @@ int ellpack_x2_step(const ellpack_t *X, ellpack_t *X2, ellpack_t *U, double tau,
 /* Tr A by the pairwise tree. */
 int ellpack_trace(const ellpack_t *A, double *trace_out);
 
+/* Tr(AB) = sum_i sum_j A_ij B_ji of two validated N x N handles of either
+ * precision: the energy Tr(DH) of a density matrix D and its Hamiltonian H
+ * (the output of the paper's "ExaSP2 Application").  Row term t_i: fused
+ * multiply-adds over the stored entries of row i of A in ascending column j,
+ * t = fma(A_ij, B_ji, t), with B_ji from row j of B (skipped where B stores no
+ * (j, i) entry) and FP32 values widened exactly to double; Tr(AB) = pairwise
+ * tree of the t_i.  trace_out: host double.  Runs on A's stream after
+ * synchronising B's.  Errors: ELL_EINVAL (NULL, different N, malformed
+ * matrix), ELL_ENONFINITE, ELL_EDEVICE. */
+int ellpack_trace_product(const ellpack_t *A, const ellpack_t *B, double *trace_out);
+
 typedef struct {
   double n_occ;            /* target occupation Tr P, in (0, N) */
   double tau;              /* FP64 drop tolerance, >= 0 */

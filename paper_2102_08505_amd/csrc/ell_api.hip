@@ -635,6 +635,38 @@ extern "C" int ellpack_trace(const ellpack_t *A, double *trace_out)
   return ELL_OK;
 }
 
+extern "C" int ellpack_trace_product(const ellpack_t *A, const ellpack_t *B, double *trace_out)
+{
+  if (!A || !B || !trace_out || A->N != B->N) return ELL_EINVAL;
+  int rc = ensure_valid(A);
+  if (rc) return rc;
+  rc = ensure_valid(B);
+  if (rc) return rc;
+  if (B->stream != A->stream) HIP_TRY(hipStreamSynchronize(B->stream));
+  AllocScope scope(A->stream);
+  DevMem d, part, out;
+  HIP_TRY(d.alloc(sizeof(double) * A->N));
+  HIP_TRY(part.alloc(sizeof(double) * ((A->N + kRedBlock - 1) / kRedBlock)));
+  HIP_TRY(out.alloc(sizeof(double)));
+  const bool a64 = A->prec == ELL_F64, b64 = B->prec == ELL_F64;
+  if (a64 && b64)
+    HIP_TRY((launch_trace_product_rows<double, double>(A->N, view<double>(A), view<double>(B), d.as<double>(),
+                                                        A->stream)));
+  else if (a64)
+    HIP_TRY((launch_trace_product_rows<double, float>(A->N, view<double>(A), view<float>(B), d.as<double>(),
+                                                       A->stream)));
+  else if (b64)
+    HIP_TRY((launch_trace_product_rows<float, double>(A->N, view<float>(A), view<double>(B), d.as<double>(),
+                                                       A->stream)));
+  else
+    HIP_TRY((launch_trace_product_rows<float, float>(A->N, view<float>(A), view<float>(B), d.as<double>(),
+                                                      A->stream)));
+  HIP_TRY(launch_tree_sum(A->N, d.as<double>(), part.as<double>(), out.as<double>(), A->stream));
+  HIP_TRY(hipMemcpyAsync(trace_out, out.p, sizeof(double), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(hipStreamSynchronize(A->stream));
+  return ELL_OK;
+}
+
 // ===========================================================================
 // SP2
 // ===========================================================================

@@ -131,6 +131,9 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
 hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hipStream_t stream);
+// row terms of Tr(AB): d[i] = ascending-j fma chain of A_ij * B_ji
+template <typename TA, typename TB>
+hipError_t launch_trace_product_rows(int N, EllView<TA> A, EllView<TB> B, double *d, hipStream_t stream);
 
 // ---- span pipeline (ell_band.hip) ------------------------------------------------------
 template <typename T>

@@ -758,6 +758,33 @@ __global__ __launch_bounds__(256) void k_trace_rows(int N, EllView<T> A, double 
   d[i] = v;
 }
 
+// One thread per row i of A: t = fma(A_ij, B_ji, t) over row i in ascending j,
+// B_ji found by a binary search of row j of B (columns ascending).
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_trace_product_rows(int N, EllView<TA> A, EllView<TB> B, double *d)
+{
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double t = 0.0;
+  const int n = A.nnz[i];
+  for (int q = 0; q < n; ++q) {
+    const int j = A.idx[(size_t)i * A.M + q];
+    const int32_t *cj = B.idx + (size_t)j * B.M;
+    int lo = 0, hi = B.nnz[j] - 1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int c = cj[mid];
+      if (c == i) {
+        t = __builtin_fma((double)A.val[(size_t)i * A.M + q], (double)B.val[(size_t)j * B.M + mid], t);
+        break;
+      }
+      if (c < i) lo = mid + 1;
+      else hi = mid - 1;
+    }
+  }
+  d[i] = t;
+}
+
 __global__ __launch_bounds__(256) void k_tree_partial(int n, const double *d, double *part)
 {
   __shared__ double ws[4];
@@ -875,6 +902,21 @@ hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream)
 }
 template hipError_t launch_trace_rows<double>(int, EllView<double>, double *, hipStream_t);
 template hipError_t launch_trace_rows<float>(int, EllView<float>, double *, hipStream_t);
+
+template <typename TA, typename TB>
+hipError_t launch_trace_product_rows(int N, EllView<TA> A, EllView<TB> B, double *d, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_trace_product_rows<TA, TB>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, B, d);
+  return hipGetLastError();
+}
+template hipError_t launch_trace_product_rows<double, double>(int, EllView<double>, EllView<double>, double *,
+                                                              hipStream_t);
+template hipError_t launch_trace_product_rows<double, float>(int, EllView<double>, EllView<float>, double *,
+                                                             hipStream_t);
+template hipError_t launch_trace_product_rows<float, double>(int, EllView<float>, EllView<double>, double *,
+                                                             hipStream_t);
+template hipError_t launch_trace_product_rows<float, float>(int, EllView<float>, EllView<float>, double *,
+                                                            hipStream_t);
 
 // Pairwise tree over n doubles: 1024-element blocks, then one more level over
 // the block sums (n <= 1024 * 1024).  `part` holds ceil(n/1024) doubles.

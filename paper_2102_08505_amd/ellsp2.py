@@ -72,6 +72,7 @@ def load():
     L.ellpack_x2_threshold.argtypes = [vp, vp, C.c_double, f64p, i32p]
     L.ellpack_x2_step.argtypes = [vp, vp, vp, C.c_double, f64p, i32p]
     L.ellpack_trace.argtypes = [vp, f64p]
+    L.ellpack_trace_product.argtypes = [vp, vp, f64p]
     L.sp2_solve.argtypes = [vp, vp, C.POINTER(SP2Params), C.POINTER(SP2Report)]
     L.sp2_solve_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(SP2Params),
                                     C.POINTER(SP2Report)]
@@ -196,6 +197,13 @@ def ellpack_x2_step(X, X2, U, tau):
 def ellpack_trace(h):
     t = C.c_double(0)
     rc = load().ellpack_trace(h, C.byref(t))
+    return rc, t.value
+
+
+def ellpack_trace_product(a, b):
+    """Tr(AB) = sum_ij A_ij B_ji."""
+    t = C.c_double(0)
+    rc = load().ellpack_trace_product(a, b, C.byref(t))
     return rc, t.value
 
 

@@ -328,3 +328,29 @@ def test_sp2_report_per_iteration_bytes_and_times():
     each = rep["x2_seconds_each"]
     assert len(each) == rep["x2_launches"] and (each > 0).all()
     assert abs(each.sum() - rep["x2_seconds"]) <= 1e-9 * rep["x2_launches"] + 1e-12
+
+
+@pytest.mark.parametrize("pa,pb", [(False, False), (True, False), (False, True), (True, True)])
+def test_trace_product_bitwise(pa, pb):
+    A = random_ell(300, 0.05, seed=61, f32=pa, full_rows=(7,), empty_rows=(3,))
+    B = random_ell(300, 0.05, seed=62, f32=pb, empty_rows=(11,))
+    Ad = dev_from_oracle(A, E.ELL_F32 if pa else E.ELL_F64)
+    Bd = dev_from_oracle(B, E.ELL_F32 if pb else E.ELL_F64)
+    rc, t = E.ellpack_trace_product(Ad.h, Bd.h)
+    assert rc == E.ELL_OK
+    assert same_float(t, oracle.trace_product(A, B))
+    rc, _ = E.ellpack_trace_product(Ad.h, dev_from_oracle(random_ell(20, 0.2, seed=1), E.ELL_F64).h)
+    assert rc == E.ELL_EINVAL
+
+
+def test_energy_of_the_sp2_density_matrix():
+    N, b = 512, 16
+    nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=0)
+    Hd = E.DeviceEll.from_host(N, Mh, nnz, idx, val)
+    Dd = E.DeviceEll(N, 128, E.ELL_F64)
+    rc, _ = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-9, 1e-8))
+    assert rc == E.ELL_OK
+    rc, energy = E.ellpack_trace_product(Dd.h, Hd.h)
+    assert rc == E.ELL_OK
+    D = oracle_from_dev(Dd)
+    assert same_float(energy, oracle.trace_product(D, oracle.Ell(N, Mh, nnz, idx, val)))
