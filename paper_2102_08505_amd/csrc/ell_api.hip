@@ -886,7 +886,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   HIP_TRY(S.hist_maxw.alloc(sizeof(int32_t) * mi));
   HIP_TRY(S.hist_nnzx.alloc(sizeof(int64_t) * mi));
   HIP_TRY(S.hist_nnzy.alloc(sizeof(int64_t) * mi));
-  const int gb = (N + 255) / 256;
+  const int gb = init_blocks(N);  // Gershgorin partials, one per workgroup
   HIP_TRY(S.glo.alloc(sizeof(double) * gb));
   HIP_TRY(S.ghi.alloc(sizeof(double) * gb));
   HIP_TRY(S.gout.alloc(sizeof(double) * 2));
@@ -1485,8 +1485,8 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   int maxN = 0;
   for (int32_t q = 0; q < n; ++q) maxN = std::max(maxN, H[q]->N);
   DevMem glo, ghi, gout, gflags;
-  HIP_TRY(glo.alloc(sizeof(double) * ((maxN + 255) / 256)));
-  HIP_TRY(ghi.alloc(sizeof(double) * ((maxN + 255) / 256)));
+  HIP_TRY(glo.alloc(sizeof(double) * init_blocks(maxN)));
+  HIP_TRY(ghi.alloc(sizeof(double) * init_blocks(maxN)));
   HIP_TRY(gout.alloc(sizeof(double) * 2 * n));
   HIP_TRY(gflags.alloc(sizeof(int32_t) * n));
   HIP_TRY(hipMemsetAsync(gflags.p, 0, sizeof(int32_t) * n, st));

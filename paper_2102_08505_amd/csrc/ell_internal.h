@@ -119,6 +119,12 @@ hipError_t launch_reduce_batch(int nblocks, const int32_t *blk_inst, const int32
 hipError_t launch_decide_batch(int n, SP2State *states, const SP2Cfg *cfgs, const SP2Hist *hists,
                                const StepScratch *ss, hipStream_t stream);
 
+// Workgroups of the initialisation kernels (one wavefront per row, 4 per
+// workgroup, rows strided over at most kInitBlocks workgroups).
+constexpr int kInitBlocks = 1024;
+inline int init_blocks(int N) { return N < 4 * kInitBlocks ? (N + 3) / 4 : kInitBlocks; }
+// Gershgorin bounds of H into emin_emax[0..1] (rowlo, rowhi: init_blocks(N)
+// doubles of per-workgroup partials); flags |= 2 if H holds a non-finite value
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi,
                              double *emin_emax, int32_t *flags, hipStream_t stream);
 template <typename T>

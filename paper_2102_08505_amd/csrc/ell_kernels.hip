@@ -610,40 +610,54 @@ __global__ __launch_bounds__(256) void k_step_final_batch(SP2State *states, cons
 // --------------------------------------------------------------------------
 // initialisation: Gershgorin bounds and X0
 // --------------------------------------------------------------------------
+// value v of lane u (u the same for the whole wavefront)
+__device__ __forceinline__ double lane_value(double v, int u)
+{
+  const long long b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), u);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One wavefront per row, rows strided over a grid of at most kInitBlocks
+// workgroups: the row's entries are loaded 64 at a time, coalesced, and passed
+// in ascending j to one running sum r = r + |H_ij| (j != i; the diagonal adds
+// +0, which leaves r unchanged since r >= +0); each workgroup writes the min /
+// max of its rows' H_ii - r_i and H_ii + r_i.
 __global__ __launch_bounds__(256) void k_gersh_rows(int N, EllView<double> H, double *plo, double *phi,
                                                     int32_t *flags)
 {
-  __shared__ double slo[256], shi[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double slo[kWavesPerBlock], shi[kWavesPerBlock];
+  const int w = threadIdx.x >> 6, lane = lane_id();
   double lo = INFINITY, hi = -INFINITY;
-  if (i < N) {
+  bool bad = false;
+  for (int i = uniform_i(blockIdx.x * kWavesPerBlock + w); i < N; i += gridDim.x * kWavesPerBlock) {
+    const int n = uniform_i(H.nnz[i]);
     double r = 0.0, hii = 0.0;
-    bool bad = false;
-    const int n = H.nnz[i];
-    for (int q = 0; q < n; ++q) {
-      const int j = H.idx[(size_t)i * H.M + q];
-      const double h = H.val[(size_t)i * H.M + q];
-      if (!isfinite(h)) bad = true;
-      if (j == i) hii = h;
-      else r = r + fabs(h);
+    for (int q0 = 0; q0 < n; q0 += kWave) {
+      const int q = q0 + lane;
+      const bool in = q < n;
+      const int j = in ? H.idx[(size_t)i * H.M + q] : -1;
+      const double h = in ? H.val[(size_t)i * H.M + q] : 0.0;
+      bad = bad || (in && !isfinite(h));
+      const uint64_t dm = __ballot(j == i);
+      if (dm) hii = lane_value(h, __builtin_ctzll(dm));
+      const double a = (in && j != i) ? fabs(h) : 0.0;
+      const int cnt = min(kWave, n - q0);
+      for (int u = 0; u < cnt; ++u) r = r + lane_value(a, u);
     }
-    if (bad) atomicOr(flags, 2);
-    lo = hii - r;
-    hi = hii + r;
+    lo = fmin(lo, hii - r);
+    hi = fmax(hi, hii + r);
   }
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
+  if (__ballot(bad) && lane == 0) atomicOr(flags, 2);
+  if (lane == 0) {
+    slo[w] = lo;
+    shi[w] = hi;
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
-      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    plo[blockIdx.x] = slo[0];
-    phi[blockIdx.x] = shi[0];
+    plo[blockIdx.x] = fmin(fmin(slo[0], slo[1]), fmin(slo[2], slo[3]));
+    phi[blockIdx.x] = fmax(fmax(shi[0], shi[1]), fmax(shi[2], shi[3]));
   }
 }
 
@@ -671,42 +685,77 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
   }
 }
 
+// X0 = (emax I - H) inv, pruned, one wavefront per row (rows strided over at
+// most kInitBlocks workgroups): the entries of row i in ascending column order,
+// with the diagonal entry (emax - 0) inv put in its place when H stores none;
+// kept values are compacted in order by ballot prefix counts.  One atomic max
+// and one atomic add per workgroup report the widest row and the total count.
 template <typename T>
 __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv,
                                             T tau, int32_t *wmax, unsigned long long *total)
 {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const int n = H.nnz[i];
-  const int32_t *ci = H.idx + (size_t)i * H.M;
-  const double *vi = H.val + (size_t)i * H.M;
-  int c = 0, q = 0;
-  bool diag_done = false;
-  while (q < n || !diag_done) {
-    int j;
-    double h;
-    if (q < n && (diag_done || ci[q] <= i)) {
-      j = ci[q];
-      h = vi[q];
-      ++q;
-    } else {
-      j = i;
-      h = 0.0;
+  __shared__ int smax[kWavesPerBlock];
+  __shared__ unsigned long long ssum[kWavesPerBlock];
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  int cmax = 0;
+  unsigned long long csum = 0;
+  for (int i = uniform_i(blockIdx.x * kWavesPerBlock + w); i < N; i += gridDim.x * kWavesPerBlock) {
+    const int n = uniform_i(H.nnz[i]);
+    const int32_t *ci = H.idx + (size_t)i * H.M;
+    const double *vi = H.val + (size_t)i * H.M;
+    // entries before the diagonal, and whether H stores it
+    int nlt = 0;
+    bool has_diag = false;
+    for (int q0 = 0; q0 < n; q0 += kWave) {
+      const int q = q0 + lane;
+      const int j = q < n ? ci[q] : INT_MAX;
+      nlt += __popcll(__ballot(j < i));
+      has_diag = has_diag || __ballot(j == i) != 0;
     }
-    if (j == i) diag_done = true;
-    const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
-    const T xt = (T)x;
-    if (absv(xt) > tau) {
-      if (c < X.M) {
-        X.idx[(size_t)i * X.M + c] = j;
-        X.val[(size_t)i * X.M + c] = xt;
+    int c = 0;
+    auto emit = [&](int qa, int qb) {  // entries qa .. qb - 1, ascending
+      for (int q0 = qa; q0 < qb; q0 += kWave) {
+        const int q = q0 + lane;
+        const bool in = q < qb;
+        const int j = in ? ci[q] : 0;
+        const double h = in ? vi[q] : 0.0;
+        const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
+        const T xt = (T)x;
+        const bool keep = in && absv(xt) > tau;
+        const uint64_t m = __ballot(keep);
+        const int pos = c + lanes_below(m);
+        if (keep && pos < X.M) {
+          X.idx[(size_t)i * X.M + pos] = j;
+          X.val[(size_t)i * X.M + pos] = xt;
+        }
+        c += __popcll(m);
       }
-      ++c;
+    };
+    emit(0, nlt);
+    if (!has_diag) {  // the diagonal H lacks: (emax - 0) inv
+      const T xt = (T)((emax - 0.0) * inv);
+      if (absv(xt) > tau) {
+        if (lane == 0 && c < X.M) {
+          X.idx[(size_t)i * X.M + c] = i;
+          X.val[(size_t)i * X.M + c] = xt;
+        }
+        ++c;
+      }
     }
+    emit(nlt, n);
+    if (lane == 0) X.nnz[i] = min(c, X.M);
+    cmax = max(cmax, c);
+    csum += (unsigned long long)c;
   }
-  X.nnz[i] = min(c, X.M);
-  atomicMax(wmax, c);
-  atomicAdd(total, (unsigned long long)c);
+  if (lane == 0) {
+    smax[w] = cmax;
+    ssum[w] = csum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(wmax, max(max(smax[0], smax[1]), max(smax[2], smax[3])));
+    atomicAdd(total, ssum[0] + ssum[1] + ssum[2] + ssum[3]);
+  }
 }
 
 // Row copy between capacities and precisions (widening float -> double is exact).
@@ -855,7 +904,7 @@ hipError_t launch_final_only(const StepScratch &s, hipStream_t stream)
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi, double *emin_emax,
                              int32_t *flags, hipStream_t stream)
 {
-  const int nb = (N + 255) / 256;
+  const int nb = init_blocks(N);
   hipLaunchKernelGGL(k_gersh_rows, dim3(nb), dim3(256), 0, stream, N, H, rowlo, rowhi, flags);
   hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(256), 0, stream, nb, rowlo, rowhi, emin_emax);
   return hipGetLastError();
@@ -865,7 +914,7 @@ template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau, int32_t *wmax,
                      unsigned long long *total, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_x0<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, H, X, emax, inv, tau, wmax,
+  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, emax, inv, tau, wmax,
                      total);
   return hipGetLastError();
 }
