@@ -365,8 +365,8 @@ def main():
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_x2_band16 (fused X^2 on FP64 matrix cores, prune, traces, norm, "
-                               "2X - X^2 on the span form)",
+                     "kernel": "k_x2_band16_part (fused X^2 on FP64 matrix cores, prune, traces, norm, "
+                               "2X - X^2 on the span form, 64-row partial sums)",
                      "bytes_per_launch": prof["x2_bytes"] / launches,
                      "alu": alu},
     }

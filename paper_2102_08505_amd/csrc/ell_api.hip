@@ -4,9 +4,10 @@
 // check runs on the host before the first HIP call, so malformed arguments
 // are reported without a GPU.  sp2_solve keeps the whole purification loop on
 // the device: the per-iteration decision (trace branch, stop, stall, overflow,
-// precision switch) is taken by a one-thread kernel that writes a device
-// control block, every kernel of the loop returns at once when that block
-// says "stop", and the host reads the block only every poll_every iterations.
+// precision switch) is taken on the device by one thread and written to a
+// device control block; every kernel of the loop returns at once when that
+// block says "stop", and the host reads the block only every poll_every
+// iterations.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -186,6 +187,69 @@ void swap_mem(DevMem &a, DevMem &b)
   std::swap(a.dev, b.dev);
 }
 
+// Pinned, device-mapped, coherent host blocks (the SP2 loop's state slots, its
+// initialisation results, its history) come from a small process-wide pool,
+// so a solve does not pay for hipHostMalloc every time.  A block returns to
+// the pool only after its stream has drained (no kernel still writes it).
+struct PinnedBlock {
+  void *p;
+  void *d;  // the device's address of it
+  size_t bytes;
+};
+constexpr size_t kPinnedPoolBlocks = 16;
+std::mutex g_pin_mu;
+std::vector<PinnedBlock> g_pin_pool;
+
+struct PinnedMem {
+  PinnedBlock b{nullptr, nullptr, 0};
+  PinnedMem() = default;
+  PinnedMem(const PinnedMem &) = delete;
+  PinnedMem &operator=(const PinnedMem &) = delete;
+  ~PinnedMem() { release(); }
+  void release()
+  {
+    if (!b.p) return;
+    {
+      std::lock_guard<std::mutex> lock(g_pin_mu);
+      if (g_pin_pool.size() < kPinnedPoolBlocks) {
+        g_pin_pool.push_back(b);
+        b = PinnedBlock{nullptr, nullptr, 0};
+        return;
+      }
+    }
+    (void)hipHostFree(b.p);
+    b = PinnedBlock{nullptr, nullptr, 0};
+  }
+  hipError_t alloc(size_t want)
+  {
+    release();
+    const size_t bytes = size_class(want);
+    {
+      std::lock_guard<std::mutex> lock(g_pin_mu);
+      for (size_t i = g_pin_pool.size(); i-- > 0;)
+        if (g_pin_pool[i].bytes == bytes) {
+          b = g_pin_pool[i];
+          g_pin_pool.erase(g_pin_pool.begin() + (ptrdiff_t)i);
+          return hipSuccess;
+        }
+    }
+    void *h = nullptr, *d = nullptr;
+    hipError_t e = hipHostMalloc(&h, bytes, hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable);
+    if (e != hipSuccess) return e;
+    e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+      (void)hipHostFree(h);
+      return e;
+    }
+    b = PinnedBlock{h, d, bytes};
+    return hipSuccess;
+  }
+  template <typename T>
+  T *host(size_t off) const { return reinterpret_cast<T *>(static_cast<char *>(b.p) + off); }
+  template <typename T>
+  T *dev(size_t off) const { return reinterpret_cast<T *>(static_cast<char *>(b.d) + off); }
+};
+
 int have_device()
 {
   int n = 0;
@@ -234,12 +298,13 @@ struct StepMem {
   hipError_t alloc(int N)
   {
     const int nb = (N + kRedBlock - 1) / kRedBlock;
+    const int nq = (N + 63) / 64;  // 64-row partials of the matrix-core span iteration; nq >= nb
     hipError_t err;
     if ((err = d1.alloc(sizeof(double) * N)) || (err = d2.alloc(sizeof(double) * N)) ||
         (err = e.alloc(sizeof(double) * N)) || (err = wy.alloc(sizeof(int32_t) * N)) ||
         (err = wu.alloc(sizeof(int32_t) * N)) || (err = ly.alloc(sizeof(int32_t) * N)) ||
-        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nb)) ||
-        (err = partw.alloc(sizeof(int32_t) * 4 * nb)) || (err = partn.alloc(sizeof(int64_t) * 2 * nb)) ||
+        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nq)) ||
+        (err = partw.alloc(sizeof(int32_t) * 4 * nq)) || (err = partn.alloc(sizeof(int64_t) * 2 * nq)) ||
         (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
         (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))))
       return err;
@@ -259,6 +324,7 @@ struct StepMem {
     s.outw = outw.as<int32_t>();
     s.outn = outn.as<int64_t>();
     s.nb = nb;
+    s.nq = nq;
     return hipSuccess;
   }
 };
@@ -316,7 +382,7 @@ int ell_extent(const ellpack *A, DevMem &lens, int32_t *maxlen, bool *zeros)
   HIP_TRY(lens.alloc(sizeof(int32_t) * A->N));
   HIP_TRY(fl.alloc(sizeof(int32_t)));
   HIP_TRY(hipMemsetAsync(fl.p, 0, sizeof(int32_t), A->stream));
-  HIP_TRY(launch_ell_extent<T>(A->N, view<T>(A), lens.as<int32_t>(), fl.as<int32_t>(), A->stream));
+  HIP_TRY(launch_ell_extent<T>(A->N, view<T>(A), lens.as<int32_t>(), fl.as<int32_t>(), nullptr, A->stream));
   std::vector<int32_t> h(A->N);
   int32_t f = 0;
   HIP_TRY(hipMemcpyAsync(h.data(), lens.p, sizeof(int32_t) * A->N, hipMemcpyDeviceToHost, A->stream));
@@ -724,30 +790,58 @@ struct SpanSet {
   SpanRot3<T> rot() const { return SpanRot3<T>{{v(0), v(1), v(2)}}; }
 };
 
+// Results of the initialisation kernels, read by the host with one copy and
+// one synchronisation.
+struct InitBlock {
+  double emin, emax;          // Gershgorin bounds
+  int32_t flags;              // bit 1: H holds a non-finite value
+  int32_t wmax;               // widest row of X0
+  unsigned long long total;   // entries of X0
+  int32_t maxlen;             // longest row interval of X0
+  int32_t xflags;             // bit 2: X0 stores an exact zero
+};
+
+// Per-iteration history, one block of arrays of max_iter entries each (device,
+// and its pinned mirror): trx, trx2, eta2 (double), nnzx, nnzy (int64), maxw
+// (int32), up, prec (int8).
+constexpr size_t kHistBytesPerIter = 3 * 8 + 2 * 8 + 4 + 1 + 1;
+constexpr size_t kHistMirrorMax = (size_t)1 << 20;  // larger histories are copied array by array
+
 struct Solver {
   int N = 0;
   hipStream_t stream = nullptr;
   StepMem step;
-  DevMem state, hist_trx, hist_trx2, hist_eta2, hist_up, hist_prec, hist_maxw, hist_nnzx, hist_nnzy;
-  DevMem glo, ghi, gout, flags, wmax, total;
-  SP2State *host_state = nullptr;  // host working copy (pinned): [0], and the two poll slots [1], [2]
+  DevMem state, hist, init;
+  size_t mi = 0;  // entries per history array
+  DevMem glo, ghi, wmax;
+  // pinned: [0] host working copy of the state, [1], [2] the poll slots; the
+  // init block; the history mirror when it fits kHistMirrorMax
+  PinnedMem pin;
+  size_t pin_init = 0, pin_hist = 0;
   hipEvent_t polled[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // step-kernel launches when profiling
   bool profile = false;
   ~Solver()
   {
-    if (host_state) (void)hipHostFree(host_state);
+    if (pin.b.p) (void)hipStreamSynchronize(stream);  // nothing queued still writes the pinned block
+    pin.release();
     for (hipEvent_t e : polled)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
-  SP2Hist hist() const
+  SP2State *host_state() const { return pin.host<SP2State>(0); }
+  SP2State *host_state_dev() const { return pin.dev<SP2State>(0); }
+  InitBlock *init_host() const { return pin.host<InitBlock>(pin_init); }
+  InitBlock *init_dev() const { return init.as<InitBlock>(); }
+  static SP2Hist hist_view(char *b, size_t mi)
   {
-    return SP2Hist{hist_trx.as<double>(),  hist_trx2.as<double>(), hist_eta2.as<double>(),
-                   hist_up.as<int8_t>(),   hist_prec.as<int8_t>(), hist_maxw.as<int32_t>(),
-                   hist_nnzx.as<int64_t>(), hist_nnzy.as<int64_t>()};
+    return SP2Hist{reinterpret_cast<double *>(b),           reinterpret_cast<double *>(b + 8 * mi),
+                   reinterpret_cast<double *>(b + 16 * mi), reinterpret_cast<int8_t *>(b + 44 * mi),
+                   reinterpret_cast<int8_t *>(b + 45 * mi), reinterpret_cast<int32_t *>(b + 40 * mi),
+                   reinterpret_cast<int64_t *>(b + 24 * mi), reinterpret_cast<int64_t *>(b + 32 * mi)};
   }
+  SP2Hist hist_dev() const { return hist_view(hist.as<char>(), mi); }
   hipError_t mark(hipEvent_t *e)
   {
     hipError_t r = hipEventCreate(e);
@@ -761,12 +855,26 @@ struct Solver {
 enum Pipe { PIPE_SPAN = 0, PIPE_ELL = 1 };
 
 template <typename T>
-int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T> &W, T tau, SP2Cfg cfg)
+int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T> &W, T tau, SP2Cfg cfg,
+                     SP2State *publish, bool *published)
 {
   hipEvent_t a = nullptr, b = nullptr;
   if (S.profile) HIP_TRY(S.mark(&a));
   SP2State *st = S.state.as<SP2State>();
   StepScratch sc = S.step.s;
+  *published = false;
+  if (pipe == PIPE_SPAN && x2_band16_fits(S.N, Sp.SW, (int)sizeof(T))) {
+    // product with 64-row partials, then the rest of the reduction and the decision
+    cfg.span = 1;
+    HIP_TRY(launch_x2_band16_part<T>(S.N, Sp.rot(), st, tau, sc, S.stream));
+    if (S.profile) {
+      HIP_TRY(S.mark(&b));
+      S.marks.emplace_back(a, b);
+    }
+    HIP_TRY(launch_step_final64(st, cfg, S.hist_dev(), sc, publish, S.stream));
+    *published = publish != nullptr;
+    return ELL_OK;
+  }
   if (pipe == PIPE_SPAN) {
     cfg.span = 1;
     HIP_TRY(launch_x2_band<T>(S.N, Sp.rot(), W.rot(), st, true, false, tau, sc, sc.flags, S.stream));
@@ -780,7 +888,7 @@ int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T
     S.marks.emplace_back(a, b);
   }
   HIP_TRY(launch_reduce(S.N, st, sc, S.stream));
-  HIP_TRY(launch_decide(st, cfg, S.hist(), sc, S.stream));
+  HIP_TRY(launch_decide(st, cfg, S.hist_dev(), sc, S.stream));
   return ELL_OK;
 }
 
@@ -877,48 +985,26 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   hipStream_t st = S.stream;
   HIP_TRY(S.step.alloc(N));
   HIP_TRY(S.state.alloc(sizeof(SP2State)));
-  const size_t mi = (size_t)p->max_iter;
-  HIP_TRY(S.hist_trx.alloc(sizeof(double) * mi));
-  HIP_TRY(S.hist_trx2.alloc(sizeof(double) * mi));
-  HIP_TRY(S.hist_eta2.alloc(sizeof(double) * mi));
-  HIP_TRY(S.hist_up.alloc(mi));
-  HIP_TRY(S.hist_prec.alloc(mi));
-  HIP_TRY(S.hist_maxw.alloc(sizeof(int32_t) * mi));
-  HIP_TRY(S.hist_nnzx.alloc(sizeof(int64_t) * mi));
-  HIP_TRY(S.hist_nnzy.alloc(sizeof(int64_t) * mi));
+  S.mi = (size_t)p->max_iter;
+  HIP_TRY(S.hist.alloc(kHistBytesPerIter * S.mi));
+  HIP_TRY(S.init.alloc(sizeof(InitBlock)));
   const int gb = init_blocks(N);  // Gershgorin partials, one per workgroup
   HIP_TRY(S.glo.alloc(sizeof(double) * gb));
   HIP_TRY(S.ghi.alloc(sizeof(double) * gb));
-  HIP_TRY(S.gout.alloc(sizeof(double) * 2));
-  HIP_TRY(S.flags.alloc(sizeof(int32_t)));
   HIP_TRY(S.wmax.alloc(sizeof(int32_t)));
-  HIP_TRY(S.total.alloc(sizeof(unsigned long long)));
-  HIP_TRY(hipHostMalloc((void **)&S.host_state, 3 * sizeof(SP2State), hipHostMallocDefault));
+  const size_t hist_bytes = kHistBytesPerIter * S.mi;
+  S.pin_init = 3 * sizeof(SP2State);
+  S.pin_hist = (S.pin_init + sizeof(InitBlock) + 63) / 64 * 64;
+  HIP_TRY(S.pin.alloc(S.pin_hist + (hist_bytes <= kHistMirrorMax ? hist_bytes : 0)));
   for (hipEvent_t &e : S.polled) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   hipEvent_t t0, t1;
   HIP_TRY(S.mark(&t0));
 
-  // Init: Gershgorin bounds (one synchronisation: degenerate spectra are an error)
-  HIP_TRY(hipMemsetAsync(S.flags.p, 0, sizeof(int32_t), st));
-  HIP_TRY(launch_gershgorin(N, view<double>(H), S.glo.as<double>(), S.ghi.as<double>(), S.gout.as<double>(),
-                            S.flags.as<int32_t>(), st));
-  double ee[2];
-  int32_t fl = 0;
-  HIP_TRY(hipMemcpyAsync(ee, S.gout.p, sizeof(ee), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&fl, S.flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (fl & 2) return ELL_ENONFINITE;
-  const double emin = ee[0], emax = ee[1];
-  if (r) {
-    r->emin = emin;
-    r->emax = emax;
-  }
-  if (!(emax > emin)) return ELL_EDEGENERATE;
-  if (!(p->n_occ > 0.0 && p->n_occ < (double)N)) return ELL_EDEGENERATE;
-  const double inv = 1.0 / (emax - emin);
-
-  // X0 in ELLPACK form (capacity grows if a row is wider)
+  // Init: Gershgorin bounds, X0 (its kernel reads the bounds on the device) and
+  // X0's row intervals, then one synchronisation for all their results.
+  // Degenerate or non-finite spectra are reported after it; the kernels queued
+  // behind the bounds stay in bounds whatever values they read.
   int32_t cap = roundup32(std::min<int64_t>((int64_t)H->M + 1, N));
   cap = std::max(cap, std::min(roundup32(D->M), roundup32(N)));
   cap = std::min(std::max(cap, 32), kMaxCap);
@@ -926,52 +1012,48 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   WorkSet<double> W64;
   SpanSet<float> S32;
   SpanSet<double> S64;
-  unsigned long long nnz0 = 0;
+  InitBlock *ib = S.init_dev();
+  InitBlock &hi = *S.init_host();
+  HIP_TRY(hipMemsetAsync(ib, 0, sizeof(InitBlock), st));
+  HIP_TRY(launch_gershgorin(N, view<double>(H), S.glo.as<double>(), S.ghi.as<double>(), &ib->emin, &ib->flags, st));
+  bool first = true;
   for (;;) {
-    HIP_TRY(hipMemsetAsync(S.wmax.p, 0, sizeof(int32_t), st));
-    HIP_TRY(hipMemsetAsync(S.total.p, 0, sizeof(unsigned long long), st));
+    if (!first) {  // X0 again, wider: clear the X0 results
+      HIP_TRY(hipMemsetAsync(&ib->wmax, 0, sizeof(InitBlock) - offsetof(InitBlock, wmax), st));
+    }
     if (mixed) {
       HIP_TRY(W32.alloc(N, cap));
-      HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), emax, inv, (float)p->tau_fp32, S.wmax.as<int32_t>(),
-                               S.total.as<unsigned long long>(), st));
+      HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), &ib->emin, (float)p->tau_fp32, &ib->wmax, &ib->total,
+                               st));
+      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, st));
     } else {
       HIP_TRY(W64.alloc(N, cap));
-      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), emax, inv, p->tau, S.wmax.as<int32_t>(),
-                                S.total.as<unsigned long long>(), st));
+      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), &ib->emin, p->tau, &ib->wmax, &ib->total, st));
+      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, st));
     }
-    int32_t w0 = 0;
-    HIP_TRY(hipMemcpyAsync(&w0, S.wmax.p, sizeof(w0), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&nnz0, S.total.p, sizeof(nnz0), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hi, ib, sizeof(InitBlock), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (w0 <= cap) break;
-    cap = roundup32(w0);
+    if (first) {
+      if (hi.flags & 2) return ELL_ENONFINITE;
+      if (r) {
+        r->emin = hi.emin;
+        r->emax = hi.emax;
+      }
+      if (!(hi.emax > hi.emin)) return ELL_EDEGENERATE;
+      if (!(p->n_occ > 0.0 && p->n_occ < (double)N)) return ELL_EDEGENERATE;
+      first = false;
+    }
+    if (hi.wmax <= cap) break;
+    cap = roundup32(hi.wmax);
     if (cap > kMaxCap) return ELL_EOVERFLOW;
   }
+  const unsigned long long nnz0 = hi.total;
 
   // Span pipeline when X0's rows are intervals short enough for it.
   Pipe pipe = PIPE_ELL;
   {
-    DevMem lens;
-    int32_t maxlen = 0;
-    bool zeros = false;
-    ellpack tmp;
-    tmp.N = N;
-    tmp.stream = st;
-    if (mixed) {
-      tmp.M = W32.cap;
-      tmp.nnz = W32.nnz[0].as<int32_t>();
-      tmp.idx = W32.idx[0].as<int32_t>();
-      tmp.val = W32.val[0].p;
-      rc = ell_extent<float>(&tmp, lens, &maxlen, &zeros);
-    } else {
-      tmp.M = W64.cap;
-      tmp.nnz = W64.nnz[0].as<int32_t>();
-      tmp.idx = W64.idx[0].as<int32_t>();
-      tmp.val = W64.val[0].p;
-      rc = ell_extent<double>(&tmp, lens, &maxlen, &zeros);
-    }
-    tmp.nnz = nullptr;  // borrowed: not freed by ~ellpack (plain struct)
-    if (rc) return rc;
+    const int32_t maxlen = hi.maxlen;
+    const bool zeros = (hi.xflags & 4) != 0;
     const int32_t sw = std::min(std::max(256, roundup64(maxlen)), std::max(64, roundup64(N)));
     if (!zeros && maxlen <= kMaxCap) {
       if (mixed) {
@@ -981,12 +1063,11 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
         HIP_TRY(S64.alloc(N, sw));
         HIP_TRY(launch_ell_to_span<double>(N, W64.v(0), S64.v(0), st));
       }
-      HIP_TRY(hipStreamSynchronize(st));
       pipe = PIPE_SPAN;
     }
   }
 
-  SP2State &hs = *S.host_state;
+  SP2State &hs = *S.host_state();
   std::memset(&hs, 0, sizeof(hs));
   hs.cur = 0;
   hs.status = ST_RUNNING;
@@ -1013,10 +1094,12 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   };
 
   // A batch is `poll` iterations followed by a copy of the device state into a
-  // pinned slot.  The next batch is queued before the host waits for the
+  // pinned slot (written by the batch's last decision kernel itself when the
+  // span form runs on the matrix cores).  The next batch is queued before the host waits for the
   // current one, so the device never idles while the host reads the state; if
   // the current batch stopped, every kernel of the next one returns at once.
-  SP2State *slot = S.host_state + 1;
+  SP2State *slot = S.host_state() + 1;
+  SP2State *slot_dev = S.host_state_dev() + 1;
   struct Queued {
     size_t m0 = 0, m1 = 0;  // its step-kernel marks (profiling)
     int k = 0;              // its poll slot
@@ -1024,13 +1107,15 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   auto enqueue = [&](int k, Queued &b) -> int {
     b.k = k;
     b.m0 = S.marks.size();
+    bool published = false;
     for (int q = 0; q < poll; ++q) {
-      const int e = hs.phase32 ? launch_iteration<float>(S, pipe, S32, W32, (float)p->tau_fp32, cfg)
-                               : launch_iteration<double>(S, pipe, S64, W64, p->tau, cfg);
+      SP2State *pub = q == poll - 1 ? slot_dev + k : nullptr;
+      const int e = hs.phase32 ? launch_iteration<float>(S, pipe, S32, W32, (float)p->tau_fp32, cfg, pub, &published)
+                               : launch_iteration<double>(S, pipe, S64, W64, p->tau, cfg, pub, &published);
       if (e) return e;
     }
     b.m1 = S.marks.size();
-    HIP_TRY(hipMemcpyAsync(&slot[k], S.state.p, sizeof(SP2State), hipMemcpyDeviceToHost, st));
+    if (!published) HIP_TRY(hipMemcpyAsync(&slot[k], S.state.p, sizeof(SP2State), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(S.polled[k], st));
     return ELL_OK;
   };
@@ -1196,6 +1281,12 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   }
   HIP_TRY(S.mark(&t1));
 
+  // the history into its pinned mirror, covered by deliver's synchronisation
+  const int n = hs.iter;
+  const bool mirror = S.pin.b.bytes >= S.pin_hist + kHistBytesPerIter * S.mi;
+  if (r && n > 0 && mirror)
+    HIP_TRY(hipMemcpyAsync(S.pin.host<char>(S.pin_hist), S.hist.p, kHistBytesPerIter * S.mi, hipMemcpyDeviceToHost,
+                           st));
   int32_t width = 0;
   rc = hs.phase32 ? deliver<float>(S, pipe, S32, W32, hs.cur, D, &width)
                   : deliver<double>(S, pipe, S64, W64, hs.cur, D, &width);
@@ -1211,21 +1302,38 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
   r->seconds = ms * 1e-3;
-  const int n = hs.iter;
   std::vector<double> a(n), b(n), c(n);
   std::vector<int8_t> up(n), pr(n);
   std::vector<int32_t> mw(n);
   std::vector<int64_t> nx(n), ny(n);
   if (n > 0) {
-    HIP_TRY(hipMemcpyAsync(a.data(), S.hist_trx.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(b.data(), S.hist_trx2.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(c.data(), S.hist_eta2.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(up.data(), S.hist_up.p, n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(pr.data(), S.hist_prec.p, n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(mw.data(), S.hist_maxw.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(nx.data(), S.hist_nnzx.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(ny.data(), S.hist_nnzy.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    const SP2Hist hd = S.hist_dev();
+    SP2Hist h = hd;
+    if (mirror) {
+      HIP_TRY(hipStreamSynchronize(st));  // normally already done by deliver
+      h = Solver::hist_view(S.pin.host<char>(S.pin_hist), S.mi);
+    } else {
+      h = SP2Hist{a.data(), b.data(), c.data(), up.data(), pr.data(), mw.data(), nx.data(), ny.data()};
+      HIP_TRY(hipMemcpyAsync(a.data(), hd.trx, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(b.data(), hd.trx2, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(c.data(), hd.eta2, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(up.data(), hd.up, n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(pr.data(), hd.prec, n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(mw.data(), hd.maxw, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(nx.data(), hd.nnzx, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(ny.data(), hd.nnzy, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (mirror) {
+      std::copy(h.trx, h.trx + n, a.begin());
+      std::copy(h.trx2, h.trx2 + n, b.begin());
+      std::copy(h.eta2, h.eta2 + n, c.begin());
+      std::copy(h.up, h.up + n, up.begin());
+      std::copy(h.prec, h.prec + n, pr.begin());
+      std::copy(h.maxw, h.maxw + n, mw.begin());
+      std::copy(h.nnzx, h.nnzx + n, nx.begin());
+      std::copy(h.nnzy, h.nnzy + n, ny.begin());
+    }
   }
   int f32 = 0;
   for (int q = 0; q < n; ++q) f32 += pr[q] ? 1 : 0;
@@ -1632,13 +1740,13 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
       v.nnz += I.r0;
       v.idx += (size_t)I.r0 * cap0;
       v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, st));
+      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, st));
     } else {
       EllView<double> v = X64.v(0);
       v.nnz += I.r0;
       v.idx += (size_t)I.r0 * cap0;
       v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, st));
+      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, st));
     }
   }
   std::vector<int32_t> hl(B.NT), xf(B.n);

@@ -498,17 +498,25 @@ __global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> 
 // Interval length of every row of an ELLPACK matrix, and a flag if any stored
 // value is exactly zero (the span form cannot represent it).
 template <typename T>
-__global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags)
+__global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags,
+                                                    int32_t *maxlen)
 {
+  __shared__ int32_t wl[kWavesPerBlock];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const int n = A.nnz[i];
   int l = 0;
-  if (n > 0) l = A.idx[(size_t)i * A.M + n - 1] - A.idx[(size_t)i * A.M] + 1;
-  len[i] = l;
-  bool zero = false;
-  for (int q = 0; q < n; ++q) zero |= A.val[(size_t)i * A.M + q] == T(0);
-  if (zero) atomicOr(flags, 4);
+  if (i < N) {
+    const int n = A.nnz[i];
+    if (n > 0) l = A.idx[(size_t)i * A.M + n - 1] - A.idx[(size_t)i * A.M] + 1;
+    if (len) len[i] = l;
+    bool zero = false;
+    for (int q = 0; q < n; ++q) zero |= A.val[(size_t)i * A.M + q] == T(0);
+    if (zero) atomicOr(flags, 4);
+  }
+  if (!maxlen) return;  // the same for the whole launch
+  l = wmax(l);
+  if (lane_id() == 0) wl[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(maxlen, max(max(wl[0], wl[1]), max(wl[2], wl[3])));
 }
 
 // ELLPACK -> span form, one wave per row: positions not stored are zero.
@@ -651,13 +659,13 @@ template hipError_t launch_x2_band_batch<float>(int, SpanRot3<float>, const int3
                                                 const StepScratch *, int32_t *, hipStream_t);
 
 template <typename T>
-hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream)
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_ell_extent<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, len, flags);
+  hipLaunchKernelGGL((k_ell_extent<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, len, flags, maxlen);
   return hipGetLastError();
 }
-template hipError_t launch_ell_extent<double>(int, EllView<double>, int32_t *, int32_t *, hipStream_t);
-template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int32_t *, hipStream_t);
+template hipError_t launch_ell_extent<double>(int, EllView<double>, int32_t *, int32_t *, int32_t *, hipStream_t);
+template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int32_t *, int32_t *, hipStream_t);
 
 template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream)

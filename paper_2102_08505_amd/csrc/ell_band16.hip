@@ -29,6 +29,7 @@
 
 #include "band_common.h"
 #include "ell_internal.h"
+#include "sp2_decide.h"
 
 namespace ellsp2 {
 namespace {
@@ -527,6 +528,151 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
             fallback);
 }
 
+// ---------------------------------------------------------------------------
+// One whole SP2 iteration in one launch
+// ---------------------------------------------------------------------------
+// Perfect pairwise tree over p[a .. a + L); positions at or past n count as
+// -0.0, the exact additive identity (x + -0.0 == x for every x).
+template <int L>
+__device__ __forceinline__ double leaf_tree(const double *p, int a, int n)
+{
+  if constexpr (L == 1) {
+    return a < n ? p[a] : -0.0;
+  } else {
+    const double lo = leaf_tree<L / 2>(p, a, n);
+    return lo + leaf_tree<L / 2>(p, a + L / 2, n);
+  }
+}
+
+// Sum of p[0 .. n) (n <= 16384) by the 256 threads of a workgroup as one
+// perfect tree: thread t holds the subtree over [t L, t L + L), L the smallest
+// power of two with 256 L >= n, then the tree over the threads; valid in every
+// thread on return.
+__device__ double group_tree(const double *p, int n, double *ws)
+{
+  const int t = threadIdx.x;
+  double v;
+  if (n <= 256) v = leaf_tree<1>(p, t, n);
+  else if (n <= 512) v = leaf_tree<2>(p, 2 * t, n);
+  else if (n <= 1024) v = leaf_tree<4>(p, 4 * t, n);
+  else if (n <= 2048) v = leaf_tree<8>(p, 8 * t, n);
+  else if (n <= 4096) v = leaf_tree<16>(p, 16 * t, n);
+  else if (n <= 8192) v = leaf_tree<32>(p, 32 * t, n);
+  else v = leaf_tree<64>(p, 64 * t, n);
+  v = wave_tree(v);
+  if (lane_id() == 0) ws[t >> 6] = v;
+  __syncthreads();
+  const double r = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ long long wsum(long long v)
+{
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// The SP2 iteration's product on the span form with its first reduction
+// level: every workgroup computes its 64 rows as k_x2_band16 does, then
+// reduces them -- the traces and the norm's row sums to one node of the
+// perfect pairwise tree over all rows (the tree the separate reduction kernels
+// form, so the sums keep their bits), the widths and counts to their maxima and
+// totals -- and writes partial xb of nq = ceil(N / 64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T tau,
+                                                        StepScratch s)
+{
+  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double sq_s[kWpb][kR * kWave];
+  __shared__ int2 meta_s[kWpb][kMeta];
+  if (st->stop) return;  // the same in every workgroup
+  const int cur = st->cur;
+  const int w = uni(threadIdx.x >> 6), lane = lane_id();
+  const int xb = xcd_block(blockIdx.x, gridDim.x);
+  const int i0 = (xb * kWpb + w) * kR;
+  if (i0 < N) {
+    const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
+    rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], sq_s[w],
+              meta_s[w], s.flags);
+  }
+  __syncthreads();  // the row outputs of all four wavefronts are written
+  if (w != 0) return;
+  const int nq = s.nq;
+  const int r = xb * (kWpb * kR) + lane;
+  const bool in = r < N;
+  const double a0 = wave_tree(in ? s.d1[r] : -0.0);
+  const double a1 = wave_tree(in ? s.d2[r] : -0.0);
+  const double a2 = wave_tree(in ? s.e[r] : -0.0);
+  const int wy = in ? s.wy[r] : 0, wu = in ? s.wu[r] : 0;
+  const int ly = in && s.ly ? s.ly[r] : 0, lu = in && s.lu ? s.lu[r] : 0;
+  const int m0 = wmax(wy), m1 = wmax(wu), m2 = wmax(ly), m3 = wmax(lu);
+  const long long ny = wsum(wy), nu = wsum(wu);
+  if (lane == 0) {
+    s.part[xb] = a0;
+    s.part[nq + xb] = a1;
+    s.part[2 * nq + xb] = a2;
+    s.partw[xb] = m0;
+    s.partw[nq + xb] = m1;
+    s.partw[2 * nq + xb] = m2;
+    s.partw[3 * nq + xb] = m3;
+    s.partn[xb] = ny;
+    s.partn[nq + xb] = nu;
+  }
+}
+
+// Upper levels of the tree over the nq partials, then the SP2 decision, by one
+// workgroup.  With `publish` (mapped pinned host memory, or null) the state
+// after the decision is also written there -- or the unchanged state, when the
+// solve had stopped before this launch.
+__global__ __launch_bounds__(256) void k_step_final64(SP2State *st, SP2Cfg cfg, SP2Hist h, StepScratch s,
+                                                      SP2State *publish)
+{
+  __shared__ double ws[kWpb];
+  __shared__ int32_t wsi[4][kWpb];
+  __shared__ long long wsl[2][kWpb];
+  if (st->stop) {
+    if (publish && threadIdx.x == 0) {
+      *publish = *st;
+      __threadfence_system();
+    }
+    return;
+  }
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int nq = s.nq;
+  double t3[3];
+  for (int c = 0; c < 3; ++c) t3[c] = group_tree(s.part + (size_t)c * nq, nq, ws);
+  int32_t mx[4] = {0, 0, 0, 0};
+  long long sy = 0, su = 0;
+  for (int b = threadIdx.x; b < nq; b += 256) {
+    for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], s.partw[c * nq + b]);
+    sy += s.partn[b];
+    su += s.partn[nq + b];
+  }
+  for (int c = 0; c < 4; ++c) mx[c] = wmax(mx[c]);
+  sy = wsum(sy);
+  su = wsum(su);
+  if (lane == 0) {
+    for (int c = 0; c < 4; ++c) wsi[c][w] = mx[c];
+    wsl[0][w] = sy;
+    wsl[1][w] = su;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 3; ++c) s.out[c] = t3[c];
+    for (int c = 0; c < 4; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
+    s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
+    s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
+    SP2State x = *st;
+    sp2dev::decide(&x, cfg, h, s);
+    *st = x;
+    if (publish) {
+      *publish = x;
+      __threadfence_system();
+    }
+  }
+}
+
 // Batched form: the instances' rows are stacked in one span matrix, instance m
 // from row r0[m] (a multiple of 16), with its own local column numbers.  Group
 // grp (16 rows) belongs to the instance of its first 8-row group; the wave
@@ -584,6 +730,29 @@ template hipError_t launch_x2_band16<double>(int, SpanRot3<double>, const SP2Sta
                                              int32_t *, hipStream_t);
 template hipError_t launch_x2_band16<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
                                             int32_t *, hipStream_t);
+
+template <typename T>
+hipError_t launch_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
+                                 hipStream_t stream)
+{
+  const int groups = (N + kR - 1) / kR;
+  const int blocks = (groups + kWpb - 1) / kWpb;
+  if (blocks != s.nq || s.nq > 16384) return hipErrorInvalidValue;  // partials sized for N rows
+  hipLaunchKernelGGL(k_x2_band16_part<T>, dim3(blocks), dim3(kWpb * kWave), 0, stream, N, spans, st, tau, s);
+  return hipGetLastError();
+}
+template hipError_t launch_x2_band16_part<double>(int, SpanRot3<double>, const SP2State *, double,
+                                                  const StepScratch &, hipStream_t);
+template hipError_t launch_x2_band16_part<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
+                                                 hipStream_t);
+
+hipError_t launch_step_final64(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
+                               SP2State *publish, hipStream_t stream)
+{
+  if (s.nq > 16384) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_step_final64, dim3(1), dim3(kWpb * kWave), 0, stream, st, cfg, h, s, publish);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,

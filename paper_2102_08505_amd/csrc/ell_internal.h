@@ -92,6 +92,7 @@ struct StepScratch {
   int64_t *outn;            // 2: nnz(X2), nnz(U)
   int32_t *flags;           // bit 0: a row group needs the ELLPACK pipeline
   int32_t nb;               // number of 1024-row reduction blocks
+  int32_t nq;               // number of 64-row partials (span iteration on the matrix cores; part* hold 3 / 4 / 2 * nq)
 };
 
 constexpr int kRedBlock = 1024;  // rows per partial-reduction block
@@ -130,6 +131,11 @@ hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *ro
 template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau,
                      int32_t *wmax, unsigned long long *total, hipStream_t stream);
+// the same with the bounds read on the device (emin_emax[0..1], as written by
+// launch_gershgorin); inv = 1 / (emax - emin) is formed there
+template <typename T>
+hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, const double *emin_emax, T tau, int32_t *wmax,
+                     unsigned long long *total, hipStream_t stream);
 template <typename TS, typename TD>
 hipError_t launch_copy(int N, EllView<TS> src, EllView<TD> dst, hipStream_t stream);
 template <typename T>
@@ -151,12 +157,22 @@ bool x2_band16_fits(int N, int SW, int elem_bytes);
 template <typename T>
 hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
                             int32_t *fallback, hipStream_t stream);
+// The SP2 iteration on the span form in two launches (ell_band16.hip): X^2,
+// the row outputs and 64-row partial sums (needs x2_band16_fits and s sized for
+// N rows: s.nq == ceil(N / 64) <= 16384); then the upper reduction levels and
+// the decision in one workgroup, `publish` (mapped pinned host memory or null)
+// receiving the state afterwards.
+template <typename T>
+hipError_t launch_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
+                                 hipStream_t stream);
+hipError_t launch_step_final64(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
+                               SP2State *publish, hipStream_t stream);
 template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                   const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
                                   const StepScratch *ss, int32_t *flags, hipStream_t stream);
 template <typename T>
-hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, hipStream_t stream);
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen, hipStream_t stream);
 template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
 template <typename TS, typename TD>

@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "ell_internal.h"
+#include "sp2_decide.h"
 #include "../../include/ellsp2.h"
 
 namespace ellsp2 {
@@ -507,92 +508,13 @@ __device__ void final_reduce(const StepScratch &s, double *ws)
   }
 }
 
-__device__ bool stalled(const double *h, int n)
-{
-  if (n < 3) return false;
-  if (!(h[n - 3] < 1e-4)) return false;
-  const double now = h[n] < h[n - 1] ? h[n] : h[n - 1];
-  const double before = h[n - 2] < h[n - 3] ? h[n - 2] : h[n - 3];
-  return now >= before;
-}
-
-// One decision of the SP2 loop, taken on the device by a single thread.
-__device__ void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s)
-{
-  const int n = st->iter;
-  if (s.flags && (*s.flags & 1)) {  // some row group was not computed: redo on the ELLPACK pipeline
-    st->status = ST_FALLBACK;
-    st->stop = 1;
-    return;
-  }
-  const double trx = s.out[0], trx2 = s.out[1], eta2 = s.out[2];
-  st->trx = trx;
-  st->trx2 = trx2;
-  st->eta2 = eta2;
-  st->wy_max = s.outw[0];
-  st->wu_max = s.outw[1];
-  h.trx[n] = trx;
-  h.trx2[n] = trx2;
-  h.eta2[n] = eta2;
-  h.maxw[n] = s.outw[0];
-  h.prec[n] = (int8_t)st->phase32;
-  h.up[n] = -1;
-  h.nnzx[n] = st->nnz_cur;
-  h.nnzy[n] = s.outn[0];
-  const bool stall = cfg.stall && stalled(h.eta2 + st->phase_start, n - st->phase_start);
-  if (st->phase32) {
-    if (eta2 < cfg.switch2 || stall) {
-      st->phase_start = n + 1;
-      st->iter = n + 1;
-      st->stop = 1;
-      st->status = (n + 1 == cfg.max_iter) ? ELL_ENOCONV : ST_SWITCH;
-      return;
-    }
-  } else {
-    if (eta2 < cfg.target2 && st->fp64_updates >= (cfg.mixed ? cfg.tail : 0)) {
-      st->status = ELL_OK;
-      st->stop = 1;
-      st->iter = n + 1;
-      return;
-    }
-    if (stall) {
-      st->status = ELL_ENOCONV;
-      st->stop = 1;
-      st->iter = n + 1;
-      return;
-    }
-  }
-  if (n + 1 == cfg.max_iter) {
-    st->status = ELL_ENOCONV;
-    st->stop = 1;
-    st->iter = n + 1;
-    return;
-  }
-  const double a = fabs(2.0 * trx - trx2 - cfg.n_occ);
-  const double b = fabs(trx2 - cfg.n_occ);
-  const bool up = a < b;
-  const int need = cfg.span ? (up ? s.outw[3] : s.outw[2]) : (up ? s.outw[1] : s.outw[0]);
-  if (need > (cfg.span ? st->sw : st->cap)) {
-    st->status = ELL_EOVERFLOW;
-    st->need_width = need;
-    st->stop = 1;
-    return;
-  }
-  h.up[n] = up ? 1 : 0;
-  const int c = st->cur;
-  st->cur = up ? (c == 0 ? 2 : c - 1) : (c == 2 ? 0 : c + 1);
-  if (!st->phase32) st->fp64_updates += 1;
-  st->nnz_cur = up ? s.outn[1] : s.outn[0];
-  st->iter = n + 1;
-}
-
 __global__ __launch_bounds__(256) void k_step_final(SP2State *st, SP2Cfg cfg, SP2Hist h, StepScratch s)
 {
   __shared__ double ws[4];
   if (st && st->stop) return;
   final_reduce(s, ws);
   __syncthreads();
-  if (st && threadIdx.x == 0) decide(st, cfg, h, s);
+  if (st && threadIdx.x == 0) sp2dev::decide(st, cfg, h, s);
 }
 
 // Batched form: block m finishes the reductions of instance m and takes its decision.
@@ -604,7 +526,7 @@ __global__ __launch_bounds__(256) void k_step_final_batch(SP2State *states, cons
   if (states[m].stop) return;
   final_reduce(ss[m], ws);
   __syncthreads();
-  if (threadIdx.x == 0) decide(&states[m], cfgs[m], hists[m], ss[m]);
+  if (threadIdx.x == 0) sp2dev::decide(&states[m], cfgs[m], hists[m], ss[m]);
 }
 
 // --------------------------------------------------------------------------
@@ -691,9 +613,13 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
 // kept values are compacted in order by ballot prefix counts.  One atomic max
 // and one atomic add per workgroup report the widest row and the total count.
 template <typename T>
-__global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv,
-                                            T tau, int32_t *wmax, unsigned long long *total)
+__global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, const double *ee, double emax,
+                                            double inv, T tau, int32_t *wmax, unsigned long long *total)
 {
+  if (ee) {  // the bounds from the Gershgorin kernel: inv = 1 / (emax - emin), correctly rounded as on the host
+    emax = ee[1];
+    inv = 1.0 / (ee[1] - ee[0]);
+  }
   __shared__ int smax[kWavesPerBlock];
   __shared__ unsigned long long ssum[kWavesPerBlock];
   const int w = threadIdx.x >> 6, lane = lane_id();
@@ -914,13 +840,25 @@ template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau, int32_t *wmax,
                      unsigned long long *total, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, emax, inv, tau, wmax,
+  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, (const double *)nullptr, emax,
+                     inv, tau, wmax, total);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, const double *emin_emax, T tau, int32_t *wmax,
+                     unsigned long long *total, hipStream_t stream)
+{
+  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, emin_emax, 0.0, 0.0, tau, wmax,
                      total);
   return hipGetLastError();
 }
 template hipError_t launch_x0<double>(int, EllView<double>, EllView<double>, double, double, double,
                                       int32_t *, unsigned long long *, hipStream_t);
 template hipError_t launch_x0<float>(int, EllView<double>, EllView<float>, double, double, float, int32_t *,
+                                     unsigned long long *, hipStream_t);
+template hipError_t launch_x0<double>(int, EllView<double>, EllView<double>, const double *, double, int32_t *,
+                                      unsigned long long *, hipStream_t);
+template hipError_t launch_x0<float>(int, EllView<double>, EllView<float>, const double *, float, int32_t *,
                                      unsigned long long *, hipStream_t);
 
 template <typename TS, typename TD>

@@ -1,0 +1,96 @@
+// The SP2 loop's decision after each X^2 product, taken on the device by one
+// thread: record the iteration's traces and norm, stop on convergence,
+// stagnation, the iteration limit, a phase switch (mixed precision) or an
+// overflow, else choose the branch and rotate the buffers.  Shared by the
+// separate decision kernel and the fused span-form iteration.  Device-only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ell_internal.h"
+#include "../../include/ellsp2.h"
+
+namespace ellsp2 {
+namespace sp2dev {
+
+__device__ inline bool stalled(const double *h, int n)
+{
+  if (n < 3) return false;
+  if (!(h[n - 3] < 1e-4)) return false;
+  const double now = h[n] < h[n - 1] ? h[n] : h[n - 1];
+  const double before = h[n - 2] < h[n - 3] ? h[n - 2] : h[n - 3];
+  return now >= before;
+}
+
+// One decision of the SP2 loop, taken on the device by a single thread.
+__device__ inline void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s)
+{
+  const int n = st->iter;
+  if (s.flags && (*s.flags & 1)) {  // some row group was not computed: redo on the ELLPACK pipeline
+    st->status = ST_FALLBACK;
+    st->stop = 1;
+    return;
+  }
+  const double trx = s.out[0], trx2 = s.out[1], eta2 = s.out[2];
+  st->trx = trx;
+  st->trx2 = trx2;
+  st->eta2 = eta2;
+  st->wy_max = s.outw[0];
+  st->wu_max = s.outw[1];
+  h.trx[n] = trx;
+  h.trx2[n] = trx2;
+  h.eta2[n] = eta2;
+  h.maxw[n] = s.outw[0];
+  h.prec[n] = (int8_t)st->phase32;
+  h.up[n] = -1;
+  h.nnzx[n] = st->nnz_cur;
+  h.nnzy[n] = s.outn[0];
+  const bool stall = cfg.stall && stalled(h.eta2 + st->phase_start, n - st->phase_start);
+  if (st->phase32) {
+    if (eta2 < cfg.switch2 || stall) {
+      st->phase_start = n + 1;
+      st->iter = n + 1;
+      st->stop = 1;
+      st->status = (n + 1 == cfg.max_iter) ? ELL_ENOCONV : ST_SWITCH;
+      return;
+    }
+  } else {
+    if (eta2 < cfg.target2 && st->fp64_updates >= (cfg.mixed ? cfg.tail : 0)) {
+      st->status = ELL_OK;
+      st->stop = 1;
+      st->iter = n + 1;
+      return;
+    }
+    if (stall) {
+      st->status = ELL_ENOCONV;
+      st->stop = 1;
+      st->iter = n + 1;
+      return;
+    }
+  }
+  if (n + 1 == cfg.max_iter) {
+    st->status = ELL_ENOCONV;
+    st->stop = 1;
+    st->iter = n + 1;
+    return;
+  }
+  const double a = fabs(2.0 * trx - trx2 - cfg.n_occ);
+  const double b = fabs(trx2 - cfg.n_occ);
+  const bool up = a < b;
+  const int need = cfg.span ? (up ? s.outw[3] : s.outw[2]) : (up ? s.outw[1] : s.outw[0]);
+  if (need > (cfg.span ? st->sw : st->cap)) {
+    st->status = ELL_EOVERFLOW;
+    st->need_width = need;
+    st->stop = 1;
+    return;
+  }
+  h.up[n] = up ? 1 : 0;
+  const int c = st->cur;
+  st->cur = up ? (c == 0 ? 2 : c - 1) : (c == 2 ? 0 : c + 1);
+  if (!st->phase32) st->fp64_updates += 1;
+  st->nnz_cur = up ? s.outn[1] : s.outn[0];
+  st->iter = n + 1;
+}
+
+}  // namespace sp2dev
+}  // namespace ellsp2
