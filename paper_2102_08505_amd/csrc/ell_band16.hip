@@ -544,27 +544,15 @@ __device__ __forceinline__ double leaf_tree(const double *p, int a, int n)
   }
 }
 
-// Sum of p[0 .. n) (n <= 16384) by the 256 threads of a workgroup as one
-// perfect tree: thread t holds the subtree over [t L, t L + L), L the smallest
-// power of two with 256 L >= n, then the tree over the threads; valid in every
-// thread on return.
-__device__ double group_tree(const double *p, int n, double *ws)
+// The leaves of thread t for the three sums p[c nq .. c nq + nq), c = 0..2,
+// as subtrees of one perfect tree per sum: thread t holds [a, a + L), a = t L,
+// L the smallest power of two with 256 L >= nq (nq <= 16384); the trees over
+// the threads follow.
+template <int L>
+__device__ __forceinline__ void leaf_tree3(const double *p, int nq, int a, double (&v)[3])
 {
-  const int t = threadIdx.x;
-  double v;
-  if (n <= 256) v = leaf_tree<1>(p, t, n);
-  else if (n <= 512) v = leaf_tree<2>(p, 2 * t, n);
-  else if (n <= 1024) v = leaf_tree<4>(p, 4 * t, n);
-  else if (n <= 2048) v = leaf_tree<8>(p, 8 * t, n);
-  else if (n <= 4096) v = leaf_tree<16>(p, 16 * t, n);
-  else if (n <= 8192) v = leaf_tree<32>(p, 32 * t, n);
-  else v = leaf_tree<64>(p, 64 * t, n);
-  v = wave_tree(v);
-  if (lane_id() == 0) ws[t >> 6] = v;
-  __syncthreads();
-  const double r = (ws[0] + ws[1]) + (ws[2] + ws[3]);
-  __syncthreads();
-  return r;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = leaf_tree<L>(p + (size_t)c * nq, a, nq);
 }
 
 __device__ __forceinline__ long long wsum(long long v)
@@ -628,42 +616,53 @@ __global__ __launch_bounds__(256) void k_x2_band16_part(int N, SpanRot3<T> spans
 __global__ __launch_bounds__(256) void k_step_final64(SP2State *st, SP2Cfg cfg, SP2Hist h, StepScratch s,
                                                       SP2State *publish)
 {
-  __shared__ double ws[kWpb];
+  __shared__ double ws[3][kWpb];
   __shared__ int32_t wsi[4][kWpb];
   __shared__ long long wsl[2][kWpb];
-  if (st->stop) {
-    if (publish && threadIdx.x == 0) {
-      *publish = *st;
-      __threadfence_system();
-    }
-    return;
-  }
-  const int w = threadIdx.x >> 6, lane = lane_id();
+  const int t = threadIdx.x, w = t >> 6, lane = lane_id();
   const int nq = s.nq;
-  double t3[3];
-  for (int c = 0; c < 3; ++c) t3[c] = group_tree(s.part + (size_t)c * nq, nq, ws);
+  // every load is issued first (the partials are read whatever the state
+  // says: they are in bounds, and unused when the solve has stopped)
+  double v[3];
+  if (nq <= 256) leaf_tree3<1>(s.part, nq, t, v);
+  else if (nq <= 512) leaf_tree3<2>(s.part, nq, 2 * t, v);
+  else if (nq <= 1024) leaf_tree3<4>(s.part, nq, 4 * t, v);
+  else if (nq <= 2048) leaf_tree3<8>(s.part, nq, 8 * t, v);
+  else if (nq <= 4096) leaf_tree3<16>(s.part, nq, 16 * t, v);
+  else if (nq <= 8192) leaf_tree3<32>(s.part, nq, 32 * t, v);
+  else leaf_tree3<64>(s.part, nq, 64 * t, v);
   int32_t mx[4] = {0, 0, 0, 0};
   long long sy = 0, su = 0;
-  for (int b = threadIdx.x; b < nq; b += 256) {
+  for (int b = t; b < nq; b += 256) {
     for (int c = 0; c < 4; ++c) mx[c] = max(mx[c], s.partw[c * nq + b]);
     sy += s.partn[b];
     su += s.partn[nq + b];
   }
+  SP2State x;
+  if (t == 0) x = *st;
+  if (st->stop) {
+    if (publish && t == 0) {
+      *publish = x;
+      __threadfence_system();
+    }
+    return;
+  }
+  for (int c = 0; c < 3; ++c) v[c] = wave_tree(v[c]);
   for (int c = 0; c < 4; ++c) mx[c] = wmax(mx[c]);
   sy = wsum(sy);
   su = wsum(su);
   if (lane == 0) {
+    for (int c = 0; c < 3; ++c) ws[c][w] = v[c];
     for (int c = 0; c < 4; ++c) wsi[c][w] = mx[c];
     wsl[0][w] = sy;
     wsl[1][w] = su;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < 3; ++c) s.out[c] = t3[c];
+  if (t == 0) {
+    for (int c = 0; c < 3; ++c) s.out[c] = (ws[c][0] + ws[c][1]) + (ws[c][2] + ws[c][3]);
     for (int c = 0; c < 4; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
     s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
     s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
-    SP2State x = *st;
     sp2dev::decide(&x, cfg, h, s);
     *st = x;
     if (publish) {
