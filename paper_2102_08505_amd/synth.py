@@ -12,9 +12,10 @@ function of (seed, stream, i, j, tag):
 * a 53-bit uniform in [0, 1) is the top 53 bits of the hash times 2^-53;
 * normals use the Box-Muller transform of two such uniforms.
 
-Workload (the paper measures model Hamiltonians from an external library that
-is not available, section "On the Generation of Model Hamiltonian System
-Matrices"; these banded matrices stand in for them):
+Workloads: the paper's own model Hamiltonians (model_hamiltonian: metals,
+semiconductors and soft matter, section "On the Generation of Model
+Hamiltonian System Matrices", rebuilt from the text since the generator it used
+is not available), and the banded matrices the benchmark and most tests use:
 
 * H_ii ~ N(0, 1);
 * H_ij = H_ji = exp(-0.5 |i - j|) * U(-1, 1) for 0 < |i - j| <= b;
@@ -37,6 +38,8 @@ TAG_DIAG_U1 = 1
 TAG_DIAG_U2 = 2
 TAG_OFFDIAG = 3
 TAG_INSTANCE = 4
+TAG_MODEL_ONSITE = 5
+TAG_MODEL_COUPLING = 6
 
 
 def splitmix64(x):
@@ -126,6 +129,112 @@ def batched_instances(count=256, seed=0, n_min=64, n_max=2048):
     n = (h % span).astype(np.int64) + n_min
     b = np.maximum(4, n // 32)
     return [(int(n[k]), int(b[k])) for k in range(count)]
+
+
+# ---- the paper's model Hamiltonians -----------------------------------------------
+#
+# Section "On the Generation of Model Hamiltonian System Matrices": a chain of
+# two-level systems, each with an A and a B orbital (onsite energies eps_A,
+# eps_B); orbitals of the same type couple with delta_AA or delta_BB, of
+# different types with delta_AB; every coupling is damped by exp(k |j - i|) for
+# orbital positions i, j; a noise parameter r turns each onsite energy and
+# coupling `param` into param * (1 + r * RAND), RAND uniform in [-1, 1].  The
+# section's three parameter sets follow; parameters it does not name are 0.
+#
+# Readings where the text leaves a choice: orbital i is of type A for even i and
+# B for odd i (site i // 2), positions are orbital indices; RAND is drawn once
+# per orbital (onsite) and once per unordered pair (coupling), so H is
+# symmetric; an entry is stored when its magnitude exceeds the drop threshold
+# `thr` (the coupling decays but never vanishes, and the printed sparsities do
+# not fix a cut-off), default 1e-5.
+MODEL_PARAMS = {
+    "metal": dict(eps_a=0.0, eps_b=0.0, d_aa=-1.0, d_bb=-1.0, d_ab=0.0, k=-0.01, r=0.0),
+    "semiconductor": dict(eps_a=0.0, eps_b=0.0, d_aa=0.0, d_bb=-1.0, d_ab=-2.0, k=-0.01, r=0.0),
+    "soft_matter": dict(eps_a=-10.0, eps_b=0.0, d_aa=0.0, d_bb=-1.0, d_ab=-1.0, k=-0.1, r=1.0),
+}
+
+
+def model_reach(kind, thr=1e-5):
+    """Largest |j - i| at which a coupling of `kind` can exceed thr."""
+    p = MODEL_PARAMS[kind]
+    top = max(abs(p["d_aa"]), abs(p["d_bb"]), abs(p["d_ab"])) * (1.0 + p["r"])
+    if top <= thr:
+        return 0
+    return int(np.floor(np.log(top / thr) / -p["k"]))
+
+
+def _model_rows(kind, N, r0, r1, seed, stream, reach):
+    """Dense candidate block of rows r0 .. r1 - 1 over columns i - reach .. i + reach."""
+    p = MODEL_PARAMS[kind]
+    rows = np.arange(r0, r1, dtype=np.int64)
+    offs = np.arange(-reach, reach + 1, dtype=np.int64)
+    cols = rows[:, None] + offs[None, :]
+    valid = (cols >= 0) & (cols < N)
+    cc = np.where(valid, cols, 0)
+    lo = np.minimum(rows[:, None], cc)
+    hi = np.maximum(rows[:, None], cc)
+    ti = (rows[:, None] & 1).astype(bool)  # True: B
+    tj = (cc & 1).astype(bool)
+    delta = np.where(ti == tj, np.where(ti, p["d_bb"], p["d_aa"]), p["d_ab"])
+    val = delta * np.exp(p["k"] * np.abs(offs[None, :]).astype(np.float64))
+    onsite = np.where((rows & 1).astype(bool), p["eps_b"], p["eps_a"]).astype(np.float64)
+    if p["r"] != 0.0:  # noise: param * (1 + r RAND)
+        rnd = 2.0 * uniform01(counter_hash(seed, stream, lo, hi, TAG_MODEL_COUPLING)) - 1.0
+        val = val * (1.0 + p["r"] * rnd)
+        ron = 2.0 * uniform01(counter_hash(seed, stream, rows, rows, TAG_MODEL_ONSITE)) - 1.0
+        onsite = onsite * (1.0 + p["r"] * ron)
+    val = np.where(offs[None, :] == 0, onsite[:, None], val)
+    return cols, valid, val
+
+
+def model_hamiltonian(kind, N, seed=0, stream=0, thr=1e-5, M=None, chunk=1024):
+    """One of the paper's model Hamiltonians ("metal", "semiconductor",
+    "soft_matter") of N orbitals in row-major ELLPACK form.
+
+    Returns (nnz, index, value, M) like banded_hamiltonian; M defaults to the
+    widest row.  Rows are built `chunk` at a time over the columns within
+    model_reach(kind, thr) of the diagonal.
+    """
+    if kind not in MODEL_PARAMS:
+        raise ValueError(f"unknown model Hamiltonian {kind!r}")
+    N = int(N)
+    if N <= 0:
+        raise ValueError("N must be positive")
+    reach = min(model_reach(kind, thr), N - 1)
+    counts, flat_cols, flat_vals = [], [], []
+    for r0 in range(0, N, chunk):
+        r1 = min(N, r0 + chunk)
+        cols, valid, val = _model_rows(kind, N, r0, r1, seed, stream, reach)
+        keep = valid & (np.abs(val) > thr)
+        counts.append(keep.sum(axis=1).astype(np.int32))
+        flat_cols.append(cols[keep])  # row by row, ascending columns
+        flat_vals.append(val[keep])
+    nnz = np.concatenate(counts)
+    wmax = int(nnz.max())
+    if M is None:
+        M = max(1, wmax)
+    if M < wmax:
+        raise ValueError(f"M={M} is smaller than the widest row {wmax}")
+    cols = np.concatenate(flat_cols)
+    vals = np.concatenate(flat_vals)
+    row = np.repeat(np.arange(N, dtype=np.int64), nnz)
+    start = np.concatenate(([0], np.cumsum(nnz, dtype=np.int64)[:-1]))
+    slot = np.arange(cols.size, dtype=np.int64) - start[row]
+    index = np.full(N * M, -1, dtype=np.int32)
+    value = np.zeros(N * M, dtype=np.float64)
+    index[row * M + slot] = cols.astype(np.int32)
+    value[row * M + slot] = vals
+    return nnz, index, value, int(M)
+
+
+def fermi_occupation(nnz, idx, val, M, mu=0.0):
+    """Number of eigenvalues of the (symmetric) ELLPACK matrix below the Fermi
+    level mu -- the occupation N_occ that SP2 is given.  The section on the model
+    Hamiltonians sets the Fermi level at 0 eV.  Dense eigenvalues: for the sizes
+    the tests and the benchmark run (N up to a few thousand)."""
+    N = len(nnz)
+    w = np.linalg.eigvalsh(ell_to_dense(N, M, nnz, idx, val))
+    return int((w < mu).sum()), w
 
 
 # ---- storage moves (no arithmetic) -------------------------------------------------
