@@ -215,6 +215,67 @@ def accuracy_leg(E, synth, torch, n=131072, b=64):
     return out
 
 
+def model_leg(E, synth, torch, reps=5):
+    """The paper's model Hamiltonians (metals, semiconductors, soft matter,
+    section "On the Generation of Model Hamiltonian System Matrices"): one FP64
+    X^2 of H itself at tau = 1e-5 on each system, at 32000 orbitals where the
+    product's rows fit the library's 4096-entry capacity (metals, soft matter)
+    and at 4096 for semiconductors (at 32000 their X^2 rows reach about 4900
+    entries); then SP2, FP64 and mixed, on the two gapped systems at 4096
+    orbitals, N_occ = the eigenvalues below the 0 eV Fermi level."""
+    import numpy as np
+    out = {"workload": "model Hamiltonians (A/B two-level chains, drop threshold 1e-5): X^2 of H at tau 1e-5; "
+                       f"SP2 at N=4096, FP64 tau {TAU_MIXED64:g}, mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}, to "
+                       f"||X^2-X||_F<{TARGET:g}"}
+    x2 = {}
+    for kind, n in (("metal", 32000), ("semiconductor", 4096), ("soft_matter", 32000)):
+        nnz, idx, val, m = synth.model_hamiltonian(kind, n)
+        X = E.DeviceEll.from_host(n, m, nnz, idx, val)
+        Y = E.DeviceEll(n, min(4096, n))
+        rc, tr, w = E.ellpack_x2_threshold(X.h, Y.h, 1e-5)  # warm-up; the product's width
+        if rc != E.ELL_OK:
+            x2[kind] = {"N": n, "status": int(rc), "width": int(w)}
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E.ellpack_x2_threshold(X.h, Y.h, 1e-5)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        ynnz = Y.download()[2]
+        byts = (int(nnz.sum()) * 12 + 4 * n) + (int(ynnz.sum()) * 12 + 4 * n)
+        x2[kind] = {"N": n, "status": int(rc), "H_width": int(m), "H_sparsity": 1.0 - float(nnz.sum()) / n / n,
+                    "x2_width": int(w), "ms": sec * 1e3, "bytes": byts, "GBs": byts / sec / 1e9,
+                    "fma": int(nnz.astype(np.int64)[idx.reshape(n, m)[np.arange(m)[None, :] < nnz[:, None]]].sum())}
+        x2[kind]["tflops"] = 2 * x2[kind]["fma"] / sec / 1e12
+        del X, Y
+    out["x2"] = x2
+    sp2 = {}
+    n = 4096
+    for kind in ("semiconductor", "soft_matter"):
+        nnz, idx, val, m = synth.model_hamiltonian(kind, n)
+        n_occ, w = synth.fermi_occupation(nnz, idx, val, m)
+        H = E.DeviceEll.from_host(n, m, nnz, idx, val)
+        res = {"N": n, "n_occ": n_occ, "gap_at_fermi": float(w[n_occ] - w[n_occ - 1]),
+               "spectrum": [float(w[0]), float(w[-1])]}
+        # tau = 1e-8 leaves FP64 above eta = 1e-6 on these spectra: both solves use the mixed run's FP64 tau
+        for name, prec, tau in (("f64", E.SP2_F64, TAU_MIXED64), ("mixed", E.SP2_MIXED, TAU_MIXED64)):
+            D = E.DeviceEll(n, 256)
+            p = E.sp2_params(n_occ, tau, TARGET, max_iter=200, precision=prec, tau_fp32=TAU_FP32,
+                             switch_eta=SWITCH_ETA)
+            E.sp2_solve(H.h, D.h, p, history=False)  # warm-up (and capacity growth)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, rep = E.sp2_solve(H.h, D.h, p, history=False)
+            torch.cuda.synchronize()
+            res[name] = {"status": int(rc), "solve_ms": (time.perf_counter() - t0) * 1e3,
+                         "iterations": rep["iterations"], "fp32_iterations": rep["fp32_iterations"],
+                         "eta": rep["eta"], "trace": rep["trace_x"], "final_M": rep["final_M"]}
+        sp2[kind] = res
+    out["sp2"] = sp2
+    return out
+
+
 def dense_leg(E, synth, torch, n=8192, b=512):
     """Dense-block variant: N = 8192 dense H (half-bandwidth 512), SP2 to
     ||X^2-X||_F < 1e-6 with BF16x3 products (then FP64 steps) and in plain FP64."""
@@ -257,6 +318,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the N = 131072 mixed-vs-FP64 comparison")
     ap.add_argument("--no-x2-single", action="store_true", help="skip the tau = 1e-5 single X^2 timings")
+    ap.add_argument("--no-model", action="store_true", help="skip the paper's model Hamiltonians")
     ap.add_argument("--main-only", action="store_true",
                     help="only the FP64 solves of the headline line (for profiling the step kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -264,7 +326,7 @@ def main():
     args = ap.parse_args()
     if args.main_only:
         args.no_cpu = args.no_mixed = args.no_batched = args.no_dense = True
-        args.no_accuracy = args.no_x2_single = True
+        args.no_accuracy = args.no_x2_single = args.no_model = True
     if args.copy_calibration:
         copy_calibration()
         return
@@ -378,6 +440,8 @@ def main():
         line["dense"] = dense_leg(E, synth, torch)
     if not args.no_accuracy:
         line["mixed_accuracy"] = accuracy_leg(E, synth, torch)
+    if not args.no_model:
+        line["model_hamiltonians"] = model_leg(E, synth, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(nnz, idx, val, M)
     print(json.dumps(line), flush=True)

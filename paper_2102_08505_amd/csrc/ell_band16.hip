@@ -45,7 +45,7 @@ constexpr int kP = 4;                   // 16-column tiles per 64-column block
 constexpr int kWpb = 4;                 // waves per workgroup
 constexpr int kKQ = 4;                  // rows k whose intervals are held in registers: 64 kKQ
 constexpr int kMeta = kKQ * kWave;      // entries of the wave's LDS table of row intervals
-constexpr int kWin = 64;                // widest output window, in aligned 64-column blocks
+constexpr int kLev = 16;                // levels of the norm's block tree (2^16 aligned 64-column blocks)
 constexpr uint32_t kOob = 0x80000000u;  // byte offset past every buffer: loads give 0, stores are dropped
 
 // Loads and stores through raw buffers.  The whole offset stays in the VGPR
@@ -235,8 +235,8 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
 template <typename T>
 __device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
-                       const SpanView<T> SU, const T tau, const StepScratch &s, double *bsum, double *sq,
-                       int2 *meta, int32_t *fallback)
+                       const SpanView<T> SU, const T tau, const StepScratch &s, double *stk, double *sq,
+                       int2 *meta, [[maybe_unused]] int32_t *fallback)
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -307,10 +307,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   wlo = wmin(wlo) & ~63;
   whi = wmax(whi);
   const int nblk = (whi - wlo + kWave) / kWave;
-  if (nblk > kWin) {
-    if (lane == 0) atomicOr(fallback, 1);
-    return;
-  }
+  const int b_first = wlo >> 6;  // the window's first aligned block
   if (kfit) {
 #pragma unroll
     for (int j = 0; j < kKQ; ++j) meta[j * kWave + lane] = make_int2(kbq[j], klq[j]);
@@ -328,6 +325,10 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   }
   const int arow = (i0 + r) * SW - bA;
   RowRun ry[4], ru[4];
+  // the norm's pending subtrees of row lane / 4 (lanes 4 g): bit l set when
+  // stk[g][l] holds a completed left subtree of 2^l blocks awaiting its right
+  // sibling
+  uint32_t pend = 0;
 
   for (int pc = 0; pc < nblk; ++pc) {
     const int p0 = wlo + pc * kWave;
@@ -456,33 +457,40 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
       double tb = v[0];
       tb = tb + dpp<0xb1>(tb);
       tb = tb + dpp<0x4e>(tb);
-      if (p == 0) bsum[g * kWin + pc] = tb;
+      if (p == 0) {
+        // block b = p0 / 64 enters row g's pairwise tree over all aligned
+        // blocks (those outside the window are +0, and x + 0 == x for the
+        // sums of squares here): as a right child it joins its left sibling
+        // -- on the stack if that subtree holds a window block, else +0 --
+        // and climbs; as a left child it waits on the stack
+        int node = p0 >> 6, lvl = 0;
+        while (node & 1) {
+          if ((node << lvl) > b_first) tb = stk[g * kLev + lvl] + tb;
+          pend &= ~(1u << lvl);
+          node >>= 1;
+          ++lvl;
+        }
+        stk[g * kLev + lvl] = tb;
+        pend |= 1u << lvl;
+      }
     }
     wave_sync();
   }
   wave_sync();
 
-  // Norm row term: the pairwise tree over the 128 aligned blocks from b0 (two
-  // 64-block subtrees; every block outside the window holds 0).  Four lanes per
-  // row, 32 leaves each, then two butterfly levels.
+  // Norm row term: the pending left subtrees, each joined to everything right
+  // of it (the lower levels; their missing right parts are +0)
   {
-    const int row = lane >> 2, j = lane & 3;
-    const int sh = (wlo >> 6) - ((wlo >> 6) & ~63);  // window's first block within the 128
-    double v[32];
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int sl = 32 * j + u - sh;
-      const bool in = (unsigned)sl < (unsigned)nblk;
-      v[u] = in ? bsum[row * kWin + (in ? sl : 0)] : 0.0;
-    }
-#pragma unroll
-    for (int w = 1; w < 32; w <<= 1)
-#pragma unroll
-      for (int u = 0; u < 32; u += 2 * w) v[u] = v[u] + v[u + w];
-    double g = v[0];
-    g = g + __shfl_xor(g, 1, kWave);
-    g = g + __shfl_xor(g, 2, kWave);
-    if (j == 0 && row < nrows) s.e[i0 + row] = g;
+    const int g = lane >> 2;
+    double e = 0.0;
+    bool any = false;
+    for (int l = 0; l < kLev; ++l)
+      if ((pend >> l) & 1u) {
+        const double v = stk[g * kLev + l];
+        e = any ? v + e : v;
+        any = true;
+      }
+    if ((lane & 3) == 0 && g < nrows) s.e[i0 + g] = e;
   }
   if (r == 0) {
 #pragma unroll
@@ -511,7 +519,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, StepScratch s,
                                                    int32_t *fallback)
 {
-  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double stk_s[kWpb][kR * kLev];
   __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   int cur = 0;
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
   const int i0 = grp * kR;
   if (i0 >= N) return;
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], sq_s[w], meta_s[w],
+  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, stk_s[w], sq_s[w], meta_s[w],
             fallback);
 }
 
@@ -549,10 +557,27 @@ __device__ __forceinline__ double leaf_tree(const double *p, int a, int n)
 // L the smallest power of two with 256 L >= nq (nq <= 16384); the trees over
 // the threads follow.
 template <int L>
+__device__ __forceinline__ double leaf_tree_lean(const double *p, int a, int n)
+{
+  if constexpr (L <= 8) {
+    return leaf_tree<L>(p, a, n);
+  } else {  // halves one after the other: at most 8 leaves live at a time
+    const double lo = leaf_tree_lean<L / 2>(p, a, n);
+    asm volatile("" ::: "memory");
+    return lo + leaf_tree_lean<L / 2>(p, a + L / 2, n);
+  }
+}
+
+template <int L>
 __device__ __forceinline__ void leaf_tree3(const double *p, int nq, int a, double (&v)[3])
 {
+  if constexpr (L <= 8) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) v[c] = leaf_tree<L>(p + (size_t)c * nq, a, nq);
+    for (int c = 0; c < 3; ++c) v[c] = leaf_tree<L>(p + (size_t)c * nq, a, nq);
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) v[c] = leaf_tree_lean<L>(p + (size_t)c * nq, a, nq);
+  }
 }
 
 __device__ __forceinline__ long long wsum(long long v)
@@ -571,7 +596,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T tau,
                                                         StepScratch s)
 {
-  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double stk_s[kWpb][kR * kLev];
   __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   if (st->stop) return;  // the same in every workgroup
@@ -581,7 +606,7 @@ __global__ __launch_bounds__(256) void k_x2_band16_part(int N, SpanRot3<T> spans
   const int i0 = (xb * kWpb + w) * kR;
   if (i0 < N) {
     const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-    rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, bsum_s[w], sq_s[w],
+    rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, stk_s[w], sq_s[w],
               meta_s[w], s.flags);
   }
   __syncthreads();  // the row outputs of all four wavefronts are written
@@ -694,7 +719,7 @@ __global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T
                                                          const SP2State *states, int32_t phase32, const T *taus,
                                                          const StepScratch *ss, int32_t *flags)
 {
-  __shared__ double bsum_s[kWpb][kR * kWin];
+  __shared__ double stk_s[kWpb][kR * kLev];
   __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   const int w = uni(threadIdx.x >> 6);
@@ -709,7 +734,7 @@ __global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T
   const int i0 = grp * kR - r0;
   if (i0 >= n) return;  // alignment rows after the instance's last row
   rows16<T>(n, i0, min(kR, n - i0), rows_from(spans.b[cur], r0), rows_from(spans.b[cy], r0),
-            rows_from(spans.b[cu], r0), taus[m], ss[m], bsum_s[w], sq_s[w], meta_s[w], flags + m);
+            rows_from(spans.b[cu], r0), taus[m], ss[m], stk_s[w], sq_s[w], meta_s[w], flags + m);
 }
 
 }  // namespace
