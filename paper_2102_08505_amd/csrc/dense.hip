@@ -130,32 +130,54 @@ __global__ __launch_bounds__(256) void k_transpose64(int N, DSel<double> sel, do
 }
 
 // ---- BF16x3 GEMM: C = hi.hi + hi.lo + lo.hi, 128 x 128 tile per block ----------------
-// LDS holds 32 k-values per row (A tiles) and per column (B tiles, read from the
-// transposed copies).  Wave (wm, wn) computes rows 64 wm .. +63 and columns
+// LDS holds 64 k-values per row (A tiles) and per column (B tiles, read from the
+// transposed copies); the next 64-value slice is loaded into registers while
+// the current one's products issue.  Wave (wm, wn) computes rows 64 wm .. +63 and columns
 // 64 wn .. +63 as 2 x 2 MFMA 32 x 32 blocks.  v_mfma_f32_32x32x16_bf16 operand
 // layout: lane l feeds A[l % 32][8 (l / 32) .. +7] and B[8 (l / 32) .. +7][l % 32]
 // and holds C[8 g + 4 (l / 32) + t][l % 32] in accumulator 4 g + t.
-constexpr int kBM = 128, kBK = 32;
-constexpr int kLdsK = kBK + 8;  // padded LDS row: 40 bf16 (80 bytes)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBM = 128, kBK = 64;
+constexpr int kLdsK = kBK + 8;               // padded LDS row: 72 bf16 (144 bytes)
+constexpr int kPieces = kBM * kBK / 8 / 256;  // 16-byte pieces of one tile per thread (4)
 
+// One 16-byte piece (8 bf16 along k) of row `gr`, from k = gk; zeros past N.
+// With VEC (N % 8 == 0) a raw buffer load over the N x N matrix, whose
+// out-of-range offset reads zeros, so no branch separates the load from its use.
 template <bool VEC>
-__device__ __forceinline__ void stage_tile(int N, const uint16_t *__restrict__ src, int row0, int k0,
-                                           uint16_t (*dst)[kLdsK])
+__device__ __forceinline__ uint4 fetch_piece(int N, const uint16_t *__restrict__ src, __amdgpu_buffer_rsrc_t rs,
+                                             int gr, int gk)
 {
-  // 128 rows x 32 k = 512 pieces of 8 values, two per thread
-  for (int p = threadIdx.x; p < kBM * kBK / 8; p += 256) {
-    const int r = p >> 2, kc = (p & 3) * 8;
-    const int gr = row0 + r, gk = k0 + kc;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (VEC && gr < N && gk + 8 <= N) {
-      v = *(const uint4 *)(src + (size_t)gr * N + gk);  // 16-byte aligned: N % 8 == 0, gk % 8 == 0
-    } else if (gr < N) {
-      uint16_t tmp[8];
-      for (int e = 0; e < 8; ++e) tmp[e] = gk + e < N ? src[(size_t)gr * N + gk + e] : 0;
-      memcpy(&v, tmp, 16);
-    }
-    memcpy(&dst[r][kc], &v, 16);
+  if (VEC) {
+    uint32_t off = gr < N && gk < N ? ((uint32_t)gr * (uint32_t)N + (uint32_t)gk) * 2u : 0xffffffffu;
+    asm("" : "+v"(off));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
   }
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (gr < N) {
+    uint16_t tmp[8];
+    for (int e = 0; e < 8; ++e) tmp[e] = gk + e < N ? src[(size_t)gr * N + gk + e] : 0;
+    memcpy(&v, tmp, 16);
+  }
+  return v;
+}
+
+// The four operand tiles (A hi, A lo from rows row0.., B hi, B lo from the
+// transposed copies' rows col0..) of the k-slice k0 .. k0 + kBK - 1: thread t
+// holds pieces t + 256 j, piece p = row p / 8, k-offset 8 (p % 8).
+template <bool VEC>
+__device__ __forceinline__ void fetch_tiles(int N, const uint16_t *const (&src)[4],
+                                            const __amdgpu_buffer_rsrc_t (&rs)[4], int row0, int col0, int k0,
+                                            uint4 (&pre)[4][kPieces])
+{
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int j = 0; j < kPieces; ++j) {
+      const int p = threadIdx.x + 256 * j;
+      pre[t][j] = fetch_piece<VEC>(N, src[t], rs[t], (t < 2 ? row0 : col0) + (p >> 3), k0 + (p & 7) * 8);
+    }
 }
 
 template <bool VEC>
@@ -164,35 +186,53 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
                                                      const uint16_t *__restrict__ hiT,
                                                      const uint16_t *__restrict__ loT, DSel<float> sel)
 {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[kBM][kLdsK], Al[kBM][kLdsK], Bh[kBM][kLdsK], Bl[kBM][kLdsK];
+  __shared__ __attribute__((aligned(16))) uint16_t T4[4][kBM][kLdsK];  // A hi, A lo, B hi, B lo
   const float *unused;
   float *C;
   if (!resolve(sel, unused, C)) return;
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int row0 = blockIdx.y * kBM, col0 = blockIdx.x * kBM;
+  const uint16_t *const src[4] = {hi, lo, hiT, loT};
+  const uint32_t bytes = (uint32_t)((size_t)N * N * 2 > 0xfffffff0u ? 0xfffffff0u : (size_t)N * N * 2);
+  const __amdgpu_buffer_rsrc_t rs[4] = {
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(hi), (short)0, (int)bytes, 0x00020000),
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(lo), (short)0, (int)bytes, 0x00020000),
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(hiT), (short)0, (int)bytes, 0x00020000),
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(loT), (short)0, (int)bytes, 0x00020000)};
   f32x16 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
+  uint4 pre[4][kPieces];
+  auto stage = [&]() {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < kPieces; ++j) {
+        const int p = threadIdx.x + 256 * j;
+        memcpy(&T4[t][p >> 3][(p & 7) * 8], &pre[t][j], 16);
+      }
+  };
+  fetch_tiles<VEC>(N, src, rs, row0, col0, 0, pre);
+  stage();
+  __syncthreads();
+  // the next slice's global loads are in flight while this slice's products issue
   for (int k0 = 0; k0 < N; k0 += kBK) {
-    stage_tile<VEC>(N, hi, row0, k0, Ah);
-    stage_tile<VEC>(N, lo, row0, k0, Al);
-    stage_tile<VEC>(N, hiT, col0, k0, Bh);
-    stage_tile<VEC>(N, loT, col0, k0, Bl);
-    __syncthreads();
+    const bool more = k0 + kBK < N;
+    if (more) fetch_tiles<VEC>(N, src, rs, row0, col0, k0 + kBK, pre);
     for (int ks = 0; ks < kBK; ks += 16) {
       const int kk = ks + 8 * (lane >> 5);
       bf16x8 ah[2], al[2], bh[2], bl[2];
       for (int a = 0; a < 2; ++a) {
         const int r = wm * 64 + a * 32 + (lane & 31);
-        memcpy(&ah[a], &Ah[r][kk], 16);
-        memcpy(&al[a], &Al[r][kk], 16);
+        memcpy(&ah[a], &T4[0][r][kk], 16);
+        memcpy(&al[a], &T4[1][r][kk], 16);
       }
       for (int b = 0; b < 2; ++b) {
         const int c = wn * 64 + b * 32 + (lane & 31);
-        memcpy(&bh[b], &Bh[c][kk], 16);
-        memcpy(&bl[b], &Bl[c][kk], 16);
+        memcpy(&bh[b], &T4[2][c][kk], 16);
+        memcpy(&bl[b], &T4[3][c][kk], 16);
       }
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
@@ -202,6 +242,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
         }
     }
     __syncthreads();
+    if (more) {
+      stage();
+      __syncthreads();
+    }
   }
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
