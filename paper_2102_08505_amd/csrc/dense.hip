@@ -256,15 +256,36 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
       }
 }
 
-// ---- FP64 GEMM: C = A.A, 64 x 64 tile per block -------------------------------------
+// ---- FP64 GEMM: C = A.A, 128 x 128 tile per block -----------------------------------
 // v_mfma_f64_16x16x4_f64: lane l feeds A[l % 16][l / 16] and B[l / 16][l % 16]
 // and holds C[l / 16 + 4 t][l % 16] in accumulator t.  Each output is updated by
 // a chain of four fused multiply-adds in ascending k (checked on gfx950 against
 // exactly rounded fma on random operands), so with k0 ascending the whole
 // product is the same fma chain as the textbook loop, bit for bit.  Wave
-// (wm, wn) owns rows 32 wm .. +31 and columns 32 wn .. +31 (2 x 2 MFMA blocks).
-constexpr int kDM = 64, kDK = 16;
+// (wm, wn) owns rows 64 wm .. +63 and columns 64 wn .. +63 (4 x 4 MFMA blocks).
+constexpr int kDM = 128, kDK = 16;
+constexpr int kDPieces = kDM * kDK / 2 / 256;  // 16-byte pieces (two doubles) of one tile per thread (4)
 
+// Piece p of the k-slice k0 .. k0 + kDK - 1 of rows row0..: row p / 8, k-offset
+// 2 (p % 8).  With VEC (N even) one raw buffer load whose out-of-range offset
+// reads zeros; else element by element.
+template <bool VEC>
+__device__ __forceinline__ void fetch_pair(int N, const double *__restrict__ src, __amdgpu_buffer_rsrc_t rs,
+                                           int gr, int gk, double &v0, double &v1)
+{
+  if (VEC) {
+    uint32_t off = gr < N && gk < N ? ((uint32_t)gr * (uint32_t)N + (uint32_t)gk) * 8u : 0xffffffffu;
+    asm("" : "+v"(off));
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    v0 = __builtin_bit_cast(double, (unsigned long long)v.y << 32 | v.x);
+    v1 = __builtin_bit_cast(double, (unsigned long long)v.w << 32 | v.z);
+    return;
+  }
+  v0 = gr < N && gk < N ? src[(size_t)gr * N + gk] : 0.0;
+  v1 = gr < N && gk + 1 < N ? src[(size_t)gr * N + gk + 1] : 0.0;
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restrict__ AT, DSel<double> sel)
 {
   __shared__ double As[kDM][kDK + 1], Bs[kDM][kDK + 1];
@@ -274,34 +295,63 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restric
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int row0 = blockIdx.y * kDM, col0 = blockIdx.x * kDM;
-  f64x4 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+  const size_t nbytes = (size_t)N * N * 8;
+  const uint32_t bytes = (uint32_t)(nbytes > 0xfffffff0u ? 0xfffffff0u : nbytes);
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A), (short)0, (int)bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(AT), (short)0, (int)bytes, 0x00020000);
+  f64x4 acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
       for (int e = 0; e < 4; ++e) acc[a][b][e] = 0.0;
-  for (int k0 = 0; k0 < N; k0 += kDK) {
-    for (int p = threadIdx.x; p < kDM * kDK; p += 256) {
-      const int r = p / kDK, k = p % kDK;
-      const int gk = k0 + k;
-      As[r][k] = (row0 + r < N && gk < N) ? A[(size_t)(row0 + r) * N + gk] : 0.0;
-      Bs[r][k] = (col0 + r < N && gk < N) ? AT[(size_t)(col0 + r) * N + gk] : 0.0;
+  double pa[kDPieces][2], pb[kDPieces][2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < kDPieces; ++j) {
+      const int p = threadIdx.x + 256 * j;
+      fetch_pair<VEC>(N, A, ra, row0 + (p >> 3), k0 + 2 * (p & 7), pa[j][0], pa[j][1]);
+      fetch_pair<VEC>(N, AT, rb, col0 + (p >> 3), k0 + 2 * (p & 7), pb[j][0], pb[j][1]);
     }
-    __syncthreads();
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int j = 0; j < kDPieces; ++j) {
+      const int p = threadIdx.x + 256 * j;
+      const int r = p >> 3, k = 2 * (p & 7);
+      As[r][k] = pa[j][0];
+      As[r][k + 1] = pa[j][1];
+      Bs[r][k] = pb[j][0];
+      Bs[r][k + 1] = pb[j][1];
+    }
+  };
+  fetch(0);
+  stage();
+  __syncthreads();
+  // the next slice's loads are in flight while this slice's products issue
+  for (int k0 = 0; k0 < N; k0 += kDK) {
+    const bool more = k0 + kDK < N;
+    if (more) fetch(k0 + kDK);
     for (int ks = 0; ks < kDK; ks += 4) {
       const int kk = ks + (lane >> 4);
-      double av[2], bv[2];
-      for (int a = 0; a < 2; ++a) av[a] = As[wm * 32 + a * 16 + (lane & 15)][kk];
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[wn * 32 + b * 16 + (lane & 15)][kk];
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+      double av[4], bv[4];
+      for (int a = 0; a < 4; ++a) av[a] = As[wm * 64 + a * 16 + (lane & 15)][kk];
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[wn * 64 + b * 16 + (lane & 15)][kk];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
+    if (more) {
+      stage();
+      __syncthreads();
+    }
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
       for (int e = 0; e < 4; ++e) {
-        const int r = row0 + wm * 32 + a * 16 + (lane >> 4) + 4 * e;
-        const int c = col0 + wn * 32 + b * 16 + (lane & 15);
+        const int r = row0 + wm * 64 + a * 16 + (lane >> 4) + 4 * e;
+        const int c = col0 + wn * 64 + b * 16 + (lane & 15);
         if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
       }
 }
@@ -418,7 +468,10 @@ hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s)
   const dim3 tb((N + 31) / 32, (N + 31) / 32);
   hipLaunchKernelGGL(k_transpose64, tb, dim3(256), 0, s, N, sel, XT);
   const dim3 gb((N + kDM - 1) / kDM, (N + kDM - 1) / kDM);
-  hipLaunchKernelGGL(k_gemm_f64, gb, dim3(256), 0, s, N, XT, sel);
+  if (N % 2 == 0)
+    hipLaunchKernelGGL(k_gemm_f64<true>, gb, dim3(256), 0, s, N, XT, sel);
+  else
+    hipLaunchKernelGGL(k_gemm_f64<false>, gb, dim3(256), 0, s, N, XT, sel);
   return hipGetLastError();
 }
 
