@@ -22,8 +22,9 @@ same target; single X^2 steps at tau = 1e-5 on X0, the midpoint and the final
 iterate; the mixed solve at N = 131072 against the FP64 solve (differences of
 X, Tr X and Tr(XH)); the batched workload (256 instances of uneven size in one
 call, against solving them one by one); the dense-block variant at N = 8192
-(BF16x3 against FP64 MFMA products); and the oracle on the host cores as
-cpu_baseline.
+(BF16x3 against FP64 MFMA products); the paper's model Hamiltonians (one X^2
+of H for metals, semiconductors and soft matter, SP2 on the two gapped
+systems); and the oracle on the host cores as cpu_baseline.
 """
 from __future__ import annotations
 
