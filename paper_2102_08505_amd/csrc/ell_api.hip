@@ -455,8 +455,9 @@ int run_step_band16(const ellpack *X, ellpack *Y, ellpack *U, double tau, int32_
 
 // One fused step on ELLPACK handles.  Matrices whose rows are short intervals
 // go through a band kernel after an exact conversion to span form (the
-// matrix-core kernel, else the register-tiled one); anything else, or a row
-// group whose window is too wide, through the LDS-window kernel.
+// matrix-core kernel when the span matrices fit its 2^31-byte buffer range,
+// else the register-tiled one, which hands row groups with too wide a window
+// on); anything else through the LDS-window kernel.
 template <typename T>
 int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
 {

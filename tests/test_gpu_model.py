@@ -36,10 +36,10 @@ def test_x2_of_model_hamiltonians_bitwise(kind, N):
     x2_both(kind, N)
 
 
-def test_x2_of_a_metal_wider_than_the_matrix_core_window():
-    """N = 4608: rows of X^2 span up to 4605 columns, more than the 64 aligned
-    64-column blocks one wavefront of the matrix-core kernel holds, so the
-    product runs on the ELLPACK path."""
+def test_x2_of_a_metal_with_output_windows_of_73_blocks():
+    """N = 4608: a wavefront's output window spans up to 4605 columns (73
+    aligned blocks of 64), so the norm's per-row tree climbs past 64 blocks
+    and starts from blocks at odd positions."""
     x2_both("metal", 4608)
 
 
