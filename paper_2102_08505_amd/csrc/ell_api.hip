@@ -374,24 +374,27 @@ struct SpanMem {
   }
 };
 
-// Longest row interval of an ELLPACK matrix and whether it stores exact zeros.
+// Longest row interval of an ELLPACK matrix, whether it stores exact zeros,
+// and whether its rows fill their intervals densely enough for span form.
 template <typename T>
-int ell_extent(const ellpack *A, DevMem &lens, int32_t *maxlen, bool *zeros)
+int ell_extent(const ellpack *A, DevMem &lens, int32_t *maxlen, bool *zeros, bool *dense = nullptr)
 {
-  DevMem fl;
+  struct Ext {
+    int32_t flags, maxlen;
+    unsigned long long sums[2];
+  };
+  DevMem ex;
   HIP_TRY(lens.alloc(sizeof(int32_t) * A->N));
-  HIP_TRY(fl.alloc(sizeof(int32_t)));
-  HIP_TRY(hipMemsetAsync(fl.p, 0, sizeof(int32_t), A->stream));
-  HIP_TRY(launch_ell_extent<T>(A->N, view<T>(A), lens.as<int32_t>(), fl.as<int32_t>(), nullptr, A->stream));
-  std::vector<int32_t> h(A->N);
-  int32_t f = 0;
-  HIP_TRY(hipMemcpyAsync(h.data(), lens.p, sizeof(int32_t) * A->N, hipMemcpyDeviceToHost, A->stream));
-  HIP_TRY(hipMemcpyAsync(&f, fl.p, sizeof(f), hipMemcpyDeviceToHost, A->stream));
+  HIP_TRY(ex.alloc(sizeof(Ext)));
+  HIP_TRY(hipMemsetAsync(ex.p, 0, sizeof(Ext), A->stream));
+  Ext *e = ex.as<Ext>();
+  HIP_TRY(launch_ell_extent<T>(A->N, view<T>(A), lens.as<int32_t>(), &e->flags, &e->maxlen, e->sums, A->stream));
+  Ext h{};
+  HIP_TRY(hipMemcpyAsync(&h, ex.p, sizeof(Ext), hipMemcpyDeviceToHost, A->stream));
   HIP_TRY(hipStreamSynchronize(A->stream));
-  int32_t m = 0;
-  for (int32_t v : h) m = std::max(m, v);
-  *maxlen = m;
-  *zeros = (f & 4) != 0;
+  *maxlen = h.maxlen;
+  *zeros = (h.flags & 4) != 0;
+  if (dense) *dense = (unsigned long long)kMinSpanFillInv * h.sums[0] >= h.sums[1];
   return ELL_OK;
 }
 
@@ -468,10 +471,10 @@ int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3]
   Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
   DevMem lens;
   int32_t maxlen = 0;
-  bool zeros = false;
-  int rc = ell_extent<T>(X, lens, &maxlen, &zeros);
+  bool zeros = false, dense = false;
+  int rc = ell_extent<T>(X, lens, &maxlen, &zeros, &dense);
   if (rc) return rc;
-  if (!zeros && maxlen <= kMaxCap) {
+  if (!zeros && dense && maxlen <= kMaxCap) {
     rc = run_step_band16<T>(X, Y, U, tau, maxlen, m, out, widths);
     if (rc != kNotTaken) return rc;
     SpanMem<T> sx;
@@ -1026,11 +1029,11 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       HIP_TRY(W32.alloc(N, cap));
       HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), &ib->emin, (float)p->tau_fp32, &ib->wmax, &ib->total,
                                st));
-      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, st));
+      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, nullptr, st));
     } else {
       HIP_TRY(W64.alloc(N, cap));
       HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), &ib->emin, p->tau, &ib->wmax, &ib->total, st));
-      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, st));
+      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, nullptr, st));
     }
     HIP_TRY(hipMemcpyAsync(&hi, ib, sizeof(InitBlock), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1056,6 +1059,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     const int32_t maxlen = hi.maxlen;
     const bool zeros = (hi.xflags & 4) != 0;
     const int32_t sw = std::min(std::max(256, roundup64(maxlen)), std::max(64, roundup64(N)));
+    // (X0's fill of its intervals does not decide here: the iterates fill them)
     if (!zeros && maxlen <= kMaxCap) {
       if (mixed) {
         HIP_TRY(S32.alloc(N, sw));
@@ -1741,13 +1745,13 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
       v.nnz += I.r0;
       v.idx += (size_t)I.r0 * cap0;
       v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, st));
+      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, nullptr, st));
     } else {
       EllView<double> v = X64.v(0);
       v.nnz += I.r0;
       v.idx += (size_t)I.r0 * cap0;
       v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, st));
+      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, nullptr, st));
     }
   }
   std::vector<int32_t> hl(B.NT), xf(B.n);

@@ -499,13 +499,14 @@ __global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> 
 // value is exactly zero (the span form cannot represent it).
 template <typename T>
 __global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags,
-                                                    int32_t *maxlen)
+                                                    int32_t *maxlen, unsigned long long *sums)
 {
   __shared__ int32_t wl[kWavesPerBlock];
+  __shared__ unsigned long long ws[2][kWavesPerBlock];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  int l = 0;
+  int l = 0, n = 0;
   if (i < N) {
-    const int n = A.nnz[i];
+    n = A.nnz[i];
     if (n > 0) l = A.idx[(size_t)i * A.M + n - 1] - A.idx[(size_t)i * A.M] + 1;
     if (len) len[i] = l;
     bool zero = false;
@@ -513,10 +514,25 @@ __global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t
     if (zero) atomicOr(flags, 4);
   }
   if (!maxlen) return;  // the same for the whole launch
+  unsigned long long sn = (unsigned long long)n, sl = (unsigned long long)l;
+  for (int o = 32; o > 0; o >>= 1) {
+    sn += __shfl_xor(sn, o, kWave);
+    sl += __shfl_xor(sl, o, kWave);
+  }
   l = wmax(l);
-  if (lane_id() == 0) wl[threadIdx.x >> 6] = l;
+  if (lane_id() == 0) {
+    wl[threadIdx.x >> 6] = l;
+    ws[0][threadIdx.x >> 6] = sn;
+    ws[1][threadIdx.x >> 6] = sl;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) atomicMax(maxlen, max(max(wl[0], wl[1]), max(wl[2], wl[3])));
+  if (threadIdx.x == 0) {
+    atomicMax(maxlen, max(max(wl[0], wl[1]), max(wl[2], wl[3])));
+    if (sums) {
+      atomicAdd(&sums[0], ws[0][0] + ws[0][1] + ws[0][2] + ws[0][3]);
+      atomicAdd(&sums[1], ws[1][0] + ws[1][1] + ws[1][2] + ws[1][3]);
+    }
+  }
 }
 
 // ELLPACK -> span form, one wave per row: positions not stored are zero.
@@ -659,13 +675,16 @@ template hipError_t launch_x2_band_batch<float>(int, SpanRot3<float>, const int3
                                                 const StepScratch *, int32_t *, hipStream_t);
 
 template <typename T>
-hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen, hipStream_t stream)
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen,
+                             unsigned long long *sums, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_ell_extent<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, len, flags, maxlen);
+  hipLaunchKernelGGL((k_ell_extent<T>), dim3((N + 255) / 256), dim3(256), 0, stream, N, A, len, flags, maxlen, sums);
   return hipGetLastError();
 }
-template hipError_t launch_ell_extent<double>(int, EllView<double>, int32_t *, int32_t *, int32_t *, hipStream_t);
-template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int32_t *, int32_t *, hipStream_t);
+template hipError_t launch_ell_extent<double>(int, EllView<double>, int32_t *, int32_t *, int32_t *,
+                                              unsigned long long *, hipStream_t);
+template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int32_t *, int32_t *,
+                                             unsigned long long *, hipStream_t);
 
 template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream)

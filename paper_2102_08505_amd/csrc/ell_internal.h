@@ -171,8 +171,17 @@ template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                   const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
                                   const StepScratch *ss, int32_t *flags, hipStream_t stream);
+// Row intervals of an ELLPACK matrix: len[i] (or null), flags |= 4 when a value
+// is an exact zero; with maxlen: the longest interval, and with sums:
+// sums[0] += stored entries, sums[1] += interval lengths.
 template <typename T>
-hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen, hipStream_t stream);
+hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen,
+                             unsigned long long *sums, hipStream_t stream);
+// Span form pays for every position of a row's interval; a standalone product
+// whose operand fills less than this share of its intervals (stored entries /
+// interval positions) goes to the ELLPACK kernels.  (Not so in SP2, whose
+// iterates fill their intervals.)
+constexpr int kMinSpanFillInv = 64;
 template <typename T>
 hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
 template <typename TS, typename TD>

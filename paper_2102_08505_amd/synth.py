@@ -227,6 +227,54 @@ def model_hamiltonian(kind, N, seed=0, stream=0, thr=1e-5, M=None, chunk=1024):
     return nnz, index, value, int(M)
 
 
+def grid3d_hamiltonian(n, delta=1.0, t=1.0, r=0.1, seed=0, stream=0, M=None):
+    """A non-banded pattern: the nearest-neighbour Hamiltonian of an n x n x n
+    cubic lattice in lexicographic order (site i = x + n y + n^2 z), onsite
+    +delta on sites with x + y + z even and -delta on the others, hopping
+    -t (1 + r RAND) to the six neighbours (open boundaries), RAND uniform in
+    [-1, 1] once per bond.  Row i holds columns i, i +- 1, i +- n, i +- n^2:
+    seven entries spread over 2 n^2 + 1 positions.  For even n the spectrum has
+    no eigenvalue in (-delta, delta) and N_occ = n^3 / 2 at the Fermi level 0."""
+    n = int(n)
+    if n <= 0:
+        raise ValueError("n must be positive")
+    N = n ** 3
+    i = np.arange(N, dtype=np.int64)
+    x, y, z = i % n, (i // n) % n, i // (n * n)
+    onsite = np.where((x + y + z) % 2 == 0, delta, -delta).astype(np.float64)
+    cols = [i]
+    vals = [onsite]
+    valid = [np.ones(N, dtype=bool)]
+    for step, coord in ((1, x), (n, y), (n * n, z)):
+        for sgn in (-1, 1):
+            j = i + sgn * step
+            ok = (coord + sgn >= 0) & (coord + sgn < n)
+            jc = np.where(ok, j, 0)
+            lo, hi = np.minimum(i, jc), np.maximum(i, jc)
+            rnd = 2.0 * uniform01(counter_hash(seed, stream, lo, hi, TAG_MODEL_COUPLING)) - 1.0
+            cols.append(jc)
+            vals.append(-t * (1.0 + r * rnd))
+            valid.append(ok)
+    cols = np.stack(cols, axis=1)
+    vals = np.stack(vals, axis=1)
+    valid = np.stack(valid, axis=1) & (vals != 0.0)
+    cols = np.where(valid, cols, np.iinfo(np.int64).max)
+    order = np.argsort(cols, axis=1, kind="stable")
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(vals, order, axis=1)
+    valid = np.take_along_axis(valid, order, axis=1)
+    nnz = valid.sum(axis=1).astype(np.int32)
+    if M is None:
+        M = 7
+    if M < 7:
+        raise ValueError("M must hold the seven stencil slots")
+    index = np.full((N, M), -1, dtype=np.int32)
+    value = np.zeros((N, M), dtype=np.float64)
+    index[:, :7] = np.where(valid, cols, -1).astype(np.int32)
+    value[:, :7] = np.where(valid, vals, 0.0)
+    return nnz, index.reshape(-1), value.reshape(-1), int(M)
+
+
 def fermi_occupation(nnz, idx, val, M, mu=0.0):
     """Number of eigenvalues of the (symmetric) ELLPACK matrix below the Fermi
     level mu -- the occupation N_occ that SP2 is given.  The section on the model

@@ -1,7 +1,8 @@
 """The GPU path on the paper's model Hamiltonians (section "On the Generation of
 Model Hamiltonian System Matrices"), against the oracle, bit for bit: the X^2
 product on all three systems, SP2 on the two the paper solves (semiconductors
-and soft matter, gapped at the 0 eV Fermi level)."""
+and soft matter, gapped at the 0 eV Fermi level); and a non-banded pattern, a
+3D lattice, through both the span form and the ELLPACK kernels."""
 import pytest
 
 import oracle
@@ -71,3 +72,37 @@ def test_sp2_mixed_on_soft_matter_bitwise():
     assert o[0] == 0
     assert_same_trajectory(o, g)
     assert 0 < g[2]["fp32_iterations"] < g[2]["iterations"]
+
+
+# ------------------------------------------ a non-banded pattern: the 3D lattice
+def grid(n):
+    nnz, idx, val, M = synth.grid3d_hamiltonian(n)
+    return oracle.Ell(n ** 3, M, nnz, idx, val), (nnz, idx, val, M)
+
+
+@pytest.mark.parametrize("n", [10, 16])
+def test_x2_of_the_3d_lattice_bitwise(n):
+    """n = 10: rows fill 7 of 201 interval positions (span form); n = 16: 7 of
+    513, below 1/64 (ELLPACK kernels)."""
+    H, (nnz, idx, val, M) = grid(n)
+    N = n ** 3
+    rc, Y, d1, d2, wy = oracle.x2(H, 1e-5)
+    X = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    Yd = E.DeviceEll(N, wy, E.ELL_F64)
+    rc_g, tr, w = E.ellpack_x2_threshold(X.h, Yd.h, 1e-5)
+    assert rc_g == E.ELL_OK and w == wy
+    assert_same_rows(oracle_from_dev(Yd), Y, f"3D lattice n={n} X^2")
+    assert same_float(tr[0], oracle.pairwise(d1)) and same_float(tr[1], oracle.pairwise(d2))
+
+
+def test_sp2_on_the_3d_lattice_bitwise():
+    n = 6
+    H, (nnz, idx, val, M) = grid(n)
+    N = n ** 3
+    po = oracle.make_params(N // 2, 1e-8, 1e-6, max_iter=200)
+    rc_o, Do, ro = oracle.sp2(H, po, Mo=N)
+    Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    Dd = E.DeviceEll(N, 32, E.ELL_F64)
+    rc_g, rg = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 2, 1e-8, 1e-6, max_iter=200))
+    assert rc_o == 0
+    assert_same_trajectory((rc_o, Do, ro), (rc_g, Dd, rg))

@@ -38,7 +38,8 @@ CASES = [
     (64, 0.1, True, (), (5, 6)),
     (257, 0.03, False, (100,), (0, 256)),
     (1000, 0.004, True, (17,), (3,)),       # a full row: span 1000 > one 512-wide window
-    (1500, 0.002, False, (700, 701), ()),
+    (1500, 0.002, False, (700, 701), ()),   # fill below 1/64 of the intervals: ELLPACK kernels
+    (1000, 0.03, False, (), (9,)),          # span form, row groups whose rows k exceed the register table
 ]
 
 

@@ -2,7 +2,8 @@
 Hamiltonian System Matrices"): the generator's structure against the section's
 definition, the one sparsity figure it prints that the reading reproduces, and
 oracle pins on these inputs (X^2 against a dense product, SP2 against the
-spectral projector at the 0 eV Fermi level).  CPU only."""
+spectral projector at the 0 eV Fermi level); and the same for a non-banded
+pattern, a 3D lattice in lexicographic order.  CPU only."""
 import numpy as np
 import pytest
 
@@ -146,3 +147,40 @@ def test_oracle_sp2_reaches_the_projector_below_the_fermi_level(kind):
     assert rc == 0
     assert np.linalg.norm(X.dense() - P) <= 1e-8
     assert abs(rep["trace_x"] - n_occ) <= 1e-8
+
+
+# ------------------------------------------ a non-banded pattern: the 3D lattice
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_grid3d_structure(n):
+    nnz, idx, val, M = synth.grid3d_hamiltonian(n, delta=1.5, t=1.0, r=0.1)
+    N = n ** 3
+    D = synth.ell_to_dense(N, M, nnz, idx, val)
+    assert np.array_equal(D, D.T)
+    for i, (c, v) in enumerate(synth.ell_rows(N, M, nnz, idx, val)):
+        x, y, z = i % n, (i // n) % n, i // (n * n)
+        want = sorted([i] + [i + s * d for d, co in ((1, x), (n, y), (n * n, z)) for s in (-1, 1)
+                             if 0 <= co + s < n])
+        assert list(c) == want
+        assert D[i, i] == (1.5 if (x + y + z) % 2 == 0 else -1.5)
+        off = v[c != i]
+        assert np.all(off <= -0.9 + 1e-15) and np.all(off >= -1.1 - 1e-15)
+
+
+def test_grid3d_gap_and_occupation():
+    nnz, idx, val, M = synth.grid3d_hamiltonian(6)
+    n_occ, w = synth.fermi_occupation(nnz, idx, val, M)
+    assert n_occ == 6 ** 3 // 2
+    assert w[n_occ - 1] <= -1.0 + 1e-12 and w[n_occ] >= 1.0 - 1e-12  # nothing inside (-delta, delta)
+
+
+def test_oracle_sp2_on_the_3d_lattice_reaches_the_projector():
+    n = 4
+    nnz, idx, val, M = synth.grid3d_hamiltonian(n)
+    N = n ** 3
+    D = synth.ell_to_dense(N, M, nnz, idx, val)
+    w, V = np.linalg.eigh(D)
+    P = V[:, : N // 2] @ V[:, : N // 2].T
+    p = oracle.make_params(N // 2, 0.0, 1e-10, max_iter=200)
+    rc, X, rep = oracle.sp2(oracle.Ell(N, M, nnz, idx, val), p)
+    assert rc == 0
+    assert np.linalg.norm(X.dense() - P) <= 1e-8
