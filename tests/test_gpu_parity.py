@@ -146,6 +146,36 @@ def test_x2_banded_full_size_bitwise(tau):
     assert same_float(out[2], eta2)
 
 
+@pytest.mark.parametrize("k", [30, 60])
+def test_sp2_full_size_step_bitwise(k):
+    """The benchmark's solve (N = 32768, half-bandwidth 64, FP64, tau = 1e-8) at
+    full size, by induction: the GPU's iterate X_k (the solve cut at k
+    products) and the GPU's X_{k+1} against one oracle step -- X_k^2, the
+    traces, the branch and 2X - X^2 -- applied to that X_k.  With X_0 checked
+    against the oracle above, every step being exact makes the trajectory
+    exact (the solve stops after 69 products)."""
+    N, b, tau = 32768, 64, 1e-8
+    nnz, idx, val, M = synth.banded_hamiltonian(N, b)
+    Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
+    outs = []
+    for it in (k, k + 1):
+        D = E.DeviceEll(N, 256, E.ELL_F64)
+        rc, rep = E.sp2_solve(Hd.h, D.h, E.sp2_params(N // 4, tau, 1e-6, max_iter=it), history=False)
+        assert rc == E.ELL_ENOCONV and rep["iterations"] == it
+        outs.append(oracle_from_dev(D))
+    Xk, Xk1 = outs
+    rc, Y, d1, d2, wy = oracle.x2(Xk, tau, M2=512)
+    assert rc == 0
+    trx, trx2 = oracle.pairwise(d1), oracle.pairwise(d2)
+    up = abs(2.0 * trx - trx2 - N // 4) < abs(trx2 - N // 4)
+    if up:
+        rc, want, _ = oracle.update(Xk, Y, tau, Mo=512)
+        assert rc == 0
+    else:
+        want = Y
+    assert_same_rows(Xk1, want, f"X_{k + 1} ({'2X - X^2' if up else 'X^2'})")
+
+
 # ---------------------------------------------------------------------------------- SP2
 def sp2_both(N, b, tau, target, M=32, max_iter=100, mixed=False, seed=0, tau32=1e-7, switch_eta=1e-3):
     nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=seed)
