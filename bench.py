@@ -289,10 +289,13 @@ def dense_leg(E, synth, torch, n=8192, b=512):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, rep = E.dense_sp2_solve(dH.data_ptr(), n, dD.data_ptr(), mode, p, torch.cuda.current_stream(),
-                                    history=False)
+                                    history=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        per = rep["x2_seconds"] / max(rep["x2_launches"], 1)
+        # per product of the mode's own precision (a BF16x3 solve ends with a few FP64 products)
+        secs, prec = rep["x2_seconds_each"], rep["prec"][:len(rep["x2_seconds_each"])]
+        own = secs[prec == (1 if mode == E.DENSE_BF16X3 else 0)]
+        per = float(own.mean()) if len(own) else rep["x2_seconds"] / max(rep["x2_launches"], 1)
         flops = 2.0 * n ** 3
         out[name] = {"status": int(rc), "solve_ms": wall * 1e3, "iterations": rep["iterations"],
                      "fp32_iterations": rep["fp32_iterations"], "eta": rep["eta"],

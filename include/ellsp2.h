@@ -179,7 +179,8 @@ typedef struct {
                               once and of the pruned X^2 written once, value + index, plus nnz arrays */
   int32_t x2_launches;     /* p->profile != 0: number of those kernels; else 0 */
   /* caller-owned host arrays of length max_iter, or NULL: per iteration, the duration of its
-     X^2 step kernel (p->profile != 0 only) and its algorithmic bytes as counted in x2_bytes */
+     X^2 step kernel (p->profile != 0 only) and its algorithmic bytes as counted in x2_bytes
+     (dense_sp2_solve: the duration of each product and its bytes, p->profile != 0 only) */
   double *hist_x2_seconds;
   int64_t *hist_x2_bytes;
 } sp2_report_t;

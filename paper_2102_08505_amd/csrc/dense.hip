@@ -681,6 +681,8 @@ extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_
         float ms = 0.f;
         DTRY(hipEventElapsedTime(&ms, ev[2 + 2 * q], ev[3 + 2 * q]));
         x2_sec += ms * 1e-3;
+        if (r && r->hist_x2_seconds && x2_n < p->max_iter) r->hist_x2_seconds[x2_n] = ms * 1e-3;
+        if (r && r->hist_x2_bytes && x2_n < p->max_iter) r->hist_x2_bytes[x2_n] = (int64_t)nn * (phase32 ? 8 : 16);
         ++x2_n;
         // algorithmic traffic of one product: X read once, X^2 written once
         x2_bytes += (int64_t)nn * (phase32 ? 8 : 16);
