@@ -181,3 +181,19 @@ def test_dense_sp2_max_iter_and_errors():
     p = E.sp2_params(1, 0.0, 1e-8)
     assert E.dense_sp2_solve(d.data_ptr(), 4, d.data_ptr(), E.DENSE_F64, p)[0] == E.ELL_EINVAL
     assert E.dense_sp2_solve(d.data_ptr(), 4, d.data_ptr() + 128, 5, p)[0] == E.ELL_EINVAL
+
+
+def test_dense_sp2_reports_each_product_when_profiling():
+    N, b, n_occ = 200, 6, 50
+    H = synth.dense_hamiltonian(N, b, seed=3)
+    dH = torch.from_numpy(H).cuda()
+    dD = torch.empty_like(dH)
+    p = E.sp2_params(n_occ, 0.0, 1e-8, max_iter=100, poll_every=3, profile=1, tau_fp32=1e-7, switch_eta=1e-3)
+    rc, rep = E.dense_sp2_solve(dH.data_ptr(), N, dD.data_ptr(), E.DENSE_BF16X3, p, torch.cuda.current_stream())
+    assert rc == E.ELL_OK
+    n = rep["iterations"]
+    assert rep["x2_launches"] == n and len(rep["x2_seconds_each"]) == n
+    assert np.all(rep["x2_seconds_each"] > 0)
+    assert abs(rep["x2_seconds_each"].sum() - rep["x2_seconds"]) <= 1e-9 * n
+    per = np.where(rep["prec"] == 1, N * N * 8, N * N * 16)  # X read and X^2 written, FP32 or FP64
+    assert np.array_equal(rep["x2_bytes_each"], per) and rep["x2_bytes"] == per.sum()
