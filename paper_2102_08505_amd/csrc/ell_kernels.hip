@@ -556,17 +556,29 @@ __global__ __launch_bounds__(256) void k_gersh_rows(int N, EllView<double> H, do
   for (int i = uniform_i(blockIdx.x * kWavesPerBlock + w); i < N; i += gridDim.x * kWavesPerBlock) {
     const int n = uniform_i(H.nnz[i]);
     double r = 0.0, hii = 0.0;
-    for (int q0 = 0; q0 < n; q0 += kWave) {
-      const int q = q0 + lane;
-      const bool in = q < n;
-      const int j = in ? H.idx[(size_t)i * H.M + q] : -1;
-      const double h = in ? H.val[(size_t)i * H.M + q] : 0.0;
-      bad = bad || (in && !isfinite(h));
-      const uint64_t dm = __ballot(j == i);
-      if (dm) hii = lane_value(h, __builtin_ctzll(dm));
-      const double a = (in && j != i) ? fabs(h) : 0.0;
-      const int cnt = min(kWave, n - q0);
-      for (int u = 0; u < cnt; ++u) r = r + lane_value(a, u);
+    for (int q1 = 0; q1 < n; q1 += 4 * kWave) {
+      // up to four 64-entry chunks loaded together, then summed in order
+      int j[4];
+      double h[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = q1 + c * kWave + lane;
+        const bool in = q < n;
+        j[c] = in ? H.idx[(size_t)i * H.M + q] : -1;
+        h[c] = in ? H.val[(size_t)i * H.M + q] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q0 = q1 + c * kWave;
+        if (q0 >= n) break;  // the same for the whole wavefront
+        const bool in = q0 + lane < n;
+        bad = bad || (in && !isfinite(h[c]));
+        const uint64_t dm = __ballot(j[c] == i);
+        if (dm) hii = lane_value(h[c], __builtin_ctzll(dm));
+        const double a = (in && j[c] != i) ? fabs(h[c]) : 0.0;
+        const int cnt = min(kWave, n - q0);
+        for (int u = 0; u < cnt; ++u) r = r + lane_value(a, u);
+      }
     }
     lo = fmin(lo, hii - r);
     hi = fmax(hi, hii + r);
@@ -610,7 +622,7 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
 // X0 = (emax I - H) inv, pruned, one wavefront per row (rows strided over at
 // most kInitBlocks workgroups): the entries of row i in ascending column order,
 // with the diagonal entry (emax - 0) inv put in its place when H stores none;
-// kept values are compacted in order by ballot prefix counts.  One atomic max
+// kept values are compacted in order by ballot prefix counts, in one pass.  One atomic max
 // and one atomic add per workgroup report the widest row and the total count.
 template <typename T>
 __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, const double *ee, double emax,
@@ -629,46 +641,50 @@ __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T>
     const int n = uniform_i(H.nnz[i]);
     const int32_t *ci = H.idx + (size_t)i * H.M;
     const double *vi = H.val + (size_t)i * H.M;
-    // entries before the diagonal, and whether H stores it
-    int nlt = 0;
-    bool has_diag = false;
+    // One pass in ascending column order.  The diagonal H lacks, (emax - 0)
+    // inv, belongs between the entries with j < i and those with j > i; at the
+    // first entry with j >= i it is known whether H stores it (columns are
+    // sorted and unique), so the entries with j > i are placed one further when
+    // it is inserted, and the diagonal itself goes in at the end.
+    const T xd = (T)((emax - 0.0) * inv);
+    int c = 0;       // kept entries of H so far
+    int c_lt = -1;   // kept entries with j < i (once known)
+    bool ins = false;
     for (int q0 = 0; q0 < n; q0 += kWave) {
       const int q = q0 + lane;
-      const int j = q < n ? ci[q] : INT_MAX;
-      nlt += __popcll(__ballot(j < i));
-      has_diag = has_diag || __ballot(j == i) != 0;
-    }
-    int c = 0;
-    auto emit = [&](int qa, int qb) {  // entries qa .. qb - 1, ascending
-      for (int q0 = qa; q0 < qb; q0 += kWave) {
-        const int q = q0 + lane;
-        const bool in = q < qb;
-        const int j = in ? ci[q] : 0;
-        const double h = in ? vi[q] : 0.0;
-        const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
-        const T xt = (T)x;
-        const bool keep = in && absv(xt) > tau;
-        const uint64_t m = __ballot(keep);
-        const int pos = c + lanes_below(m);
-        if (keep && pos < X.M) {
-          X.idx[(size_t)i * X.M + pos] = j;
-          X.val[(size_t)i * X.M + pos] = xt;
+      const bool in = q < n;
+      const int j = in ? ci[q] : INT_MAX;
+      const double h = in ? vi[q] : 0.0;
+      const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
+      const T xt = (T)x;
+      const bool keep = in && absv(xt) > tau;
+      const uint64_t m = __ballot(keep);
+      if (c_lt < 0) {
+        const uint64_t mge = __ballot(in && j >= i);
+        if (mge) {
+          const int f = __builtin_ctzll(mge);  // the first entry at or past the diagonal column
+          c_lt = c + __popcll(m & ((1ull << f) - 1ull));
+          ins = __ballot(in && j == i) == 0 && absv(xd) > tau;
         }
-        c += __popcll(m);
       }
-    };
-    emit(0, nlt);
-    if (!has_diag) {  // the diagonal H lacks: (emax - 0) inv
-      const T xt = (T)((emax - 0.0) * inv);
-      if (absv(xt) > tau) {
-        if (lane == 0 && c < X.M) {
-          X.idx[(size_t)i * X.M + c] = i;
-          X.val[(size_t)i * X.M + c] = xt;
-        }
-        ++c;
+      const int pos = c + lanes_below(m) + (ins && j > i ? 1 : 0);
+      if (keep && pos < X.M) {
+        X.idx[(size_t)i * X.M + pos] = j;
+        X.val[(size_t)i * X.M + pos] = xt;
       }
+      c += __popcll(m);
     }
-    emit(nlt, n);
+    if (c_lt < 0) {  // every entry lies before the diagonal column
+      c_lt = c;
+      ins = absv(xd) > tau;
+    }
+    if (ins) {
+      if (lane == 0 && c_lt < X.M) {
+        X.idx[(size_t)i * X.M + c_lt] = i;
+        X.val[(size_t)i * X.M + c_lt] = xd;
+      }
+      ++c;
+    }
     if (lane == 0) X.nnz[i] = min(c, X.M);
     cmax = max(cmax, c);
     csum += (unsigned long long)c;
