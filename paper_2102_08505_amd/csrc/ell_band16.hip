@@ -413,16 +413,21 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
         my[p] = __ballot(ky[p]);
         mu[p] = __ballot(ku[p]);
       }
+      // (a quad whose rows keep nothing of X^2, or of 2X - X^2, in this block
+      // leaves that output's row state as it is and writes nothing to it)
       uint32_t lo, hi;
-      int gy, gu;
-      row_bits(my, q, lo, hi);
-      const int ly = ry[t].add(lo, hi, p0, gy);
-      row_bits(mu, q, lo, hi);
-      const int lu = ru[t].add(lo, hi, p0, gu);
+      int gy = p0, gu = p0;
+      if ((my[0] | my[1] | my[2] | my[3]) != 0) {
+        row_bits(my, q, lo, hi);
+        const int ly = ry[t].add(lo, hi, p0, gy);
 #pragma unroll
-      for (int p = 0; p < kP; ++p) {
-        put<T>(yr, ry[t].first, ly, p0 + 16 * p + r, i * SW, SW, act, yk[p]);
-        put<T>(ur, ru[t].first, lu, p0 + 16 * p + r, i * SW, SW, act, uk[p]);
+        for (int p = 0; p < kP; ++p) put<T>(yr, ry[t].first, ly, p0 + 16 * p + r, i * SW, SW, act, yk[p]);
+      }
+      if ((mu[0] | mu[1] | mu[2] | mu[3]) != 0) {
+        row_bits(mu, q, lo, hi);
+        const int lu = ru[t].add(lo, hi, p0, gu);
+#pragma unroll
+        for (int p = 0; p < kP; ++p) put<T>(ur, ru[t].first, lu, p0 + 16 * p + r, i * SW, SW, act, uk[p]);
       }
       // the norm's squared differences, to the block table [row][column]
 #pragma unroll
