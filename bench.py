@@ -199,6 +199,14 @@ def accuracy_leg(E, synth, torch, n=131072, b=64):
         torch.cuda.synchronize()
         out[name] = {"status": int(rc), "solve_ms": (time.perf_counter() - t0) * 1e3,
                      "iterations": rep["iterations"], "fp32_iterations": rep["fp32_iterations"], "eta": rep["eta"]}
+        # the step kernel's own rate at a size whose three span buffers exceed the
+        # 256 MB last-level cache: one more solve with events around every launch
+        p.profile = 1
+        _, prof = E.sp2_solve(H.h, D.h, p, history=False)
+        gbs = prof["x2_bytes"] / prof["x2_seconds"] / 1e9
+        out[name]["x2_us_per_launch"] = prof["x2_seconds"] / prof["x2_launches"] * 1e6
+        out[name]["x2_GBs"] = gbs
+        out[name]["x2_hbm_frac"] = gbs / HBM_PEAK_GBS
         mats[name] = csr(D)
         rc_e, energy[name] = E.ellpack_trace_product(D.h, H.h)  # Tr(XH) on the device
         if rc_e != E.ELL_OK:
