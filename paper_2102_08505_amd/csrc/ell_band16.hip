@@ -204,12 +204,14 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
       b[p] = ld(xr, at<T>((unsigned)(col - m.x) < (unsigned)m.y, brow + col), T(0));
     }
   };
-  // tile p's products are skipped at steps outside its own k range (its B
-  // operand is all zeros there)
+  // In FP64, tile p's products are skipped at steps outside its own k range
+  // (its B operand is all zeros there).  FP32 products are cheap enough that
+  // the branches cost more than the products they skip: all four issue, adding
+  // exact zeros.
   auto mma = [&](int k0, T a, const T (&b)[kP]) {
 #pragma unroll
     for (int p = 0; p < kP; ++p)
-      if (k0 <= thi[p] && k0 + 3 >= tlo[p]) acc[p] = Mfma<T>::mma(a, b[p], acc[p]);
+      if (sizeof(T) == 4 || (k0 <= thi[p] && k0 + 3 >= tlo[p])) acc[p] = Mfma<T>::mma(a, b[p], acc[p]);
   };
   const int nsteps = (khi - klo) / 4 + 1;
   T a0, b0[kP], a1, b1[kP];
