@@ -23,9 +23,13 @@
  *           diagonal of the product before pruning.
  *   pairwise tree   while n > 1: d'[i] = d[2i] + d[2i+1], an odd last element
  *           passes through.
- *   norm    eta^2 = ||X^2 - X||_F^2 over the union of the stored patterns of
- *           the pruned X^2 and X: per row, the pairwise tree of the rounded
- *           squares in ascending column order; rows combined by pairwise tree.
+ *   norm    eta^2 = ||X^2 - X||_F^2 with the pruned X^2 and the stored X.  Row
+ *           term e_i: the pairwise tree over all N column positions j of
+ *           q_j = d*d, d = X^2_ij - X_ij (a value absent from a matrix is 0,
+ *           so q_j = +0 where neither stores column j), each square rounded
+ *           to double (FP32 values are widened exactly first); eta^2 = the
+ *           pairwise tree of the e_i.  The tree over N leaves is the perfect
+ *           tree over the next power of two with +0 leaves past N.
  *   X0      Gershgorin bounds emin, emax of H (row sums of |H_ij|, j != i, in
  *           ascending j); X0 = (emax I - H) * (1 / (emax - emin)), pruned.
  *   branch  up = |2 TrX - TrX^2 - n_occ| < |TrX^2 - n_occ| (a tie takes X^2);

@@ -10,7 +10,10 @@
 // feeds to one MFMA are contiguous along k.  After the product, one kernel per
 // row forms 2X - X^2, both diagonals and the row term of the idempotency norm
 // (pairwise tree over the N columns); the reductions and the device-side SP2
-// decision are those of the sparse path (Sec. 2, Alg. 1 of the paper).
+// decision are those of the sparse path (the SP2-Basic loop of the paper's
+// section "Performance Evaluation using an ExaSP2 Application": an X^2 product,
+// a matrix norm and the remaining update per iteration).  The paper has no
+// dense variant; this one squares dense blocks on the matrix cores.
 #include <climits>
 #include <cmath>
 #include <cstring>

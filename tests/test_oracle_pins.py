@@ -6,6 +6,7 @@ dropped term, a wrong sign, a transposed operand or a wrong summation order in
 the oracle fails here.
 """
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -192,12 +193,27 @@ def test_norm_against_numpy_on_union_pattern():
 
 
 def test_norm_f32_differences_in_double():
-    x = np.float32(1.0) + np.float32(2.0 ** -23)
-    y = np.float32(1.0)
+    # 0.3f - 1.0000001f and its square are exact in double (two binary32 values
+    # differ by a 25-bit number) but not in float, so this separates a norm
+    # formed in double from one formed in float: float gives 0.49000016.
+    x = np.float32(1.0000001)
+    y = np.float32(0.3)
     X = oracle.Ell(1, 1, [1], [0], np.array([x], np.float32))
     Y = oracle.Ell(1, 1, [1], [0], np.array([y], np.float32))
     eta2, e = oracle.norm2(X, Y)
-    assert eta2 == 2.0 ** -46
+    d = Fraction(float(y)) - Fraction(float(x))
+    assert eta2 == float(d * d)                       # one rounding, of the exact square
+    df = np.float32(y) - np.float32(x)
+    assert eta2 != float(np.float32(df * df))          # what float arithmetic would give
+    # a row of several such terms: each square rounded to double, then the tree
+    xs = np.array([1.0000001, 0.7, -0.3000001, 2.5], np.float32)
+    ys = np.array([0.3, 0.1, 0.9, 1.0000001], np.float32)
+    pad = np.zeros(12, np.float32)
+    X = oracle.Ell(4, 4, [4, 0, 0, 0], [0, 1, 2, 3] + [0] * 12, np.concatenate([xs, pad]))
+    Y = oracle.Ell(4, 4, [4, 0, 0, 0], [0, 1, 2, 3] + [0] * 12, np.concatenate([ys, pad]))
+    eta2, e = oracle.norm2(X, Y)
+    q = [float((Fraction(float(b)) - Fraction(float(a))) ** 2) for a, b in zip(xs, ys)]
+    assert eta2 == (q[0] + q[1]) + (q[2] + q[3])
 
 
 # --------------------------------------------------------------------------- update
@@ -228,6 +244,34 @@ def test_update_single_rounding():
     Y = oracle.Ell(1, 1, [1], [0], [y])
     rc, Z, w = oracle.update(X, Y, 0.0)
     assert Z.rows()[0][1][0] == exact.fma64(2.0, x, -y)
+
+
+def test_update_f32_rounds_and_thresholds_in_float():
+    # FP32 mode: 2x - y is one binary32 rounding of the exact value, and the
+    # threshold compares that float with the float tau.
+    rng = np.random.default_rng(31)
+    N = 24
+    xs = (rng.uniform(-1, 1, N) * 2.0 ** rng.integers(-12, 2, N)).astype(np.float32)
+    ys = (rng.uniform(-1, 1, N) * 2.0 ** rng.integers(-40, 2, N)).astype(np.float32)
+    # row 0: 2 * 0.5 - (-2^-30) = 1 + 2^-30 exactly; binary32 rounds it to 1.0,
+    # which is not > tau = 1.0 (in double it would be kept)
+    xs[0], ys[0] = np.float32(0.5), np.float32(-(2.0 ** -30))
+    # row 1: 2 * 1.0000001f - 2^-40 rounds back to 2 * 1.0000001f in float
+    xs[1], ys[1] = np.float32(1.0000001), np.float32(2.0 ** -40)
+    tau = np.float32(1.0)
+    X = oracle.Ell(N, 1, [1] * N, list(range(N)), xs)
+    Y = oracle.Ell(N, 1, [1] * N, list(range(N)), ys)
+    rc, Z, w = oracle.update(X, Y, 0.0)
+    assert Z.val.dtype == np.float32
+    for i, (c, v) in enumerate(Z.rows()):
+        ref = exact.to_f32(2 * Fraction(float(xs[i])) - Fraction(float(ys[i])))
+        assert list(c) == ([i] if ref != 0 else [])
+        if ref != 0:
+            assert v[0].view(np.uint32) == np.float32(ref).view(np.uint32)
+    assert Z.rows()[1][1][0] == np.float32(2) * xs[1]
+    rc, Z, w = oracle.update(X, Y, float(tau))
+    assert 0 not in Z.rows()[0][0]                      # 1 + 2^-30 -> 1.0f, not kept
+    assert list(Z.rows()[1][0]) == [1]                  # 2.0000002f > 1
 
 
 # --------------------------------------------------------------------------- Gershgorin, X0
