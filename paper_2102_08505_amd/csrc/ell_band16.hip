@@ -1,7 +1,9 @@
 // X^2 of span-form matrices on the matrix cores, FP64 and FP32: the product,
-// pruning, and per-row outputs of every SP2 iteration (the X^2 step of the
-// SP2 algorithm of the paper's SP2 section, on the thresholded sparse product
-// of its ELLPACK section).
+// pruning, and per-row outputs of every SP2 iteration (the "SP2 Loop X2",
+// "SP2 Loop Norm" and "SP2 Loop Misc" steps of the paper's section
+// "Performance Evaluation using an ExaSP2 Application", on the ELLPACK
+// matrix-matrix multiply of its section "Performance Evaluation using System
+// Matrices").
 //
 // In span form row i of X is stored densely over the columns
 // [base[i], base[i] + len[i]) at val[i*SW ...], with zeros at the pruned

@@ -32,7 +32,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kWin = 512;        // accumulator window per wave (entries)
-constexpr int kMaxBlocks = 192;  // aligned 64-column blocks of one row's window (three groups of 64)
+constexpr int kLev = 16;         // levels of a row's norm tree over aligned 64-column blocks (2^16 blocks)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -107,16 +107,37 @@ constexpr int kBatch = 8;      // rows k whose entries are loaded before their u
 
 // Running state of the ascending sweep over one output row.
 struct SweepState {
-  int cy, cu, nu;  // kept X^2 entries, kept 2X - X^2 entries, nonzero: window too wide
+  int cy, cu;     // kept X^2 entries, kept 2X - X^2 entries
+  uint32_t pend;  // lane 0: bit l set when stk[l] holds a completed left subtree of 2^l blocks
 };
+
+// The norm's row term is the perfect pairwise tree over the row's column
+// positions; every aligned 64-column block is one of its subtrees.  Blocks
+// arrive in ascending order from the window's first block b_first on; block b
+// (total t) enters the tree over all blocks, those outside the window being
+// +0 (and x + 0 == x for these sums of squares): as a right child it joins its
+// left sibling -- on the stack when that subtree holds a window block, else
+// +0 -- and climbs; as a left child it waits on the stack.
+__device__ __forceinline__ void push_block(double *stk, uint32_t &pend, const int b, const int b_first, double t)
+{
+  int node = b, lvl = 0;
+  while (node & 1) {
+    if ((node << lvl) > b_first) t = stk[lvl] + t;
+    pend &= ~(1u << lvl);
+    node >>= 1;
+    ++lvl;
+  }
+  stk[lvl] = t;
+  pend |= 1u << lvl;
+}
 
 // Sweep one accumulator window in ascending column order (the window starts
 // on a multiple of 64 columns): compact the kept entries of X^2 (and of
 // 2X - X^2), and reduce each aligned 64-column block of the norm's squared
-// differences by the lane tree into bsum[block - b0].
+// differences by the lane tree into the row's block tree (lane 0).
 template <typename T, bool WITH_U>
 __device__ __forceinline__ void sweep_window(const int i, const int wlo, const int wlen, const T tau,
-                                             const T *acc, const T *xw, const int b0, double *bsum,
+                                             const T *acc, const T *xw, const int b_first, double *stk,
                                              const EllView<T> &Y, const EllView<T> &U, SweepState &st)
 {
   const int lane = lane_id();
@@ -152,28 +173,23 @@ __device__ __forceinline__ void sweep_window(const int i, const int wlo, const i
     }
     const double dd = (double)yk - (double)x;
     const double t = wave_tree(dd * dd);
-    const int rel = ((wlo + q0) >> 6) - b0;
-    if (lane == 0) {
-      if (rel < kMaxBlocks) bsum[rel] = t;
-      else st.nu = 1;  // window wider than the block table
-    }
+    if (lane == 0) push_block(stk, st.pend, (wlo + q0) >> 6, b_first, t);
   }
 }
 
-// Norm row term from the block sums: bsum[r] is the aligned 64-column block
-// b0 + r (b0 a multiple of 64), so each 64-entry group of the table is a
-// perfect subtree; the (at most three) group totals meet in the tree over
-// absolute group positions.  Valid in every lane.
-__device__ __forceinline__ double finish_norm(const int b0, const double *bsum, const bool too_wide)
+// Norm row term (lane 0): the pending left subtrees, each joined to everything
+// right of it (the lower levels; their missing right parts are +0).
+__device__ __forceinline__ double finish_norm(const double *stk, const uint32_t pend)
 {
-  const int lane = lane_id();
-  wave_sync();
-  const double g0 = __shfl(wave_tree(bsum[lane]), 0, kWave);
-  const double g1 = __shfl(wave_tree(bsum[kWave + lane]), 0, kWave);
-  const double g2 = __shfl(wave_tree(bsum[2 * kWave + lane]), 0, kWave);
-  if (too_wide) return __builtin_nan("");
-  const int G = b0 >> 6;
-  return (G & 1) ? g0 + (g1 + g2) : (g0 + g1) + g2;
+  double e = 0.0;
+  bool any = false;
+  for (int l = 0; l < kLev; ++l)
+    if ((pend >> l) & 1u) {
+      const double v = stk[l];
+      e = any ? v + e : v;
+      any = true;
+    }
+  return e;
 }
 
 // Accumulate the products of rows k = row i's columns into the window
@@ -242,7 +258,7 @@ __device__ __forceinline__ void accumulate_window(const int wi, const int wlo, c
 template <typename T, bool WITH_U>
 __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int32_t *__restrict__ xidx,
                        const T *__restrict__ xval, const int M, EllView<T> Y, EllView<T> U, const T tau,
-                       T *acc, T *xw, double *bsum, const StepScratch &s)
+                       T *acc, T *xw, double *stk, const StepScratch &s)
 {
   const int lane = lane_id();
   const int wi = uniform_i(xnnz[i]);
@@ -310,13 +326,12 @@ __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int3
   const uint64_t dm = __ballot(has_diag);
   if (dm) d1 = __shfl(d1, __builtin_ctzll(dm), kWave);
 
-  SweepState st{0, 0, 0};
+  SweepState st{0, 0, 0u};
   double d2 = 0.0;
   // windows start on multiples of 64 columns, so every 64-wide step of the
   // sweep is one aligned block of the norm's column tree
   const int lo_al = lo == INT_MAX ? lo : (lo & ~63);
-  const int b0 = lo == INT_MAX ? 0 : ((lo_al >> 6) & ~63);
-  for (int r = lane; r < kMaxBlocks; r += kWave) bsum[r] = 0.0;
+  const int b_first = lo == INT_MAX ? 0 : (lo_al >> 6);
   for (int wlo = lo_al; wlo <= hi; wlo += kWin) {
     const int wlen = min(kWin, hi - wlo + 1);
     for (int p = lane; p < wlen; p += kWave) {
@@ -349,9 +364,9 @@ __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int3
     }
     wave_sync();
     if (i >= wlo && i < wlo + wlen) d2 = (double)acc[i - wlo];
-    sweep_window<T, WITH_U>(i, wlo, wlen, tau, acc, xw, b0, bsum, Y, U, st);
+    sweep_window<T, WITH_U>(i, wlo, wlen, tau, acc, xw, b_first, stk, Y, U, st);
   }
-  const double ev = finish_norm(b0, bsum, st.nu != 0);
+  const double ev = finish_norm(stk, st.pend);
   if (lane == 0) {
     Y.nnz[i] = min(st.cy, Y.M);
     s.wy[i] = st.cy;
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
 {
   __shared__ T acc_s[kWavesPerBlock][kWin];
   __shared__ T xw_s[kWavesPerBlock][kWin];
-  __shared__ double bsum_s[kWavesPerBlock][kMaxBlocks];
+  __shared__ double stk_s[kWavesPerBlock][kLev];
   int cur = 0;
   if (st) {
     if (st->stop) return;
@@ -396,7 +411,7 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
   const EllView<T> X = bufs.b[cur];
   const EllView<T> Y = bufs.b[cur == 2 ? 0 : cur + 1];
   const EllView<T> U = bufs.b[cur == 0 ? 2 : cur - 1];
-  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, acc_s[w], xw_s[w], bsum_s[w], s);
+  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, acc_s[w], xw_s[w], stk_s[w], s);
 }
 
 // --------------------------------------------------------------------------

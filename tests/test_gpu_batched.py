@@ -87,6 +87,27 @@ def test_batched_small_instances_match_the_oracle():
         assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
 
 
+def test_batched_mixed_instances_match_the_oracle():
+    """Mixed-precision instances (FP32 phase, then FP64 steps) of uneven size
+    in one batch, each against the oracle's mixed-mode solve."""
+    specs = [(80, 4, 14), (150, 5, 15), (231, 7, 17)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-9, 1e-8, mixed=True) for (N, *_r) in inst]
+    rc_b, reps_b, Db, singles, Hs = _run(inst, params)
+    for q, (N, Mh, nnz, idx, val) in enumerate(inst):
+        po = oracle.make_params(N // 4, 1e-9, 1e-8, max_iter=100, precision=oracle.PREC_MIXED,
+                                tau_fp32=1e-7, switch_eta=1e-3)
+        rc_o, Do, ro = oracle.sp2(oracle.Ell(N, Mh, nnz, idx, val), po, Mo=N)
+        assert reps_b[q]["status"] == rc_o == E.ELL_OK
+        assert reps_b[q]["iterations"] == ro["iterations"]
+        assert reps_b[q]["fp32_iterations"] == ro["fp32_iterations"] > 0
+        for k in ("trx", "trx2", "eta2"):
+            assert np.array_equal(reps_b[q][k].view(np.uint64), ro[k].view(np.uint64)), k
+        for k in ("up", "prec"):
+            assert np.array_equal(reps_b[q][k], ro[k]), k
+        assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
+
+
 def test_batched_mixed_and_fp64_instances_together():
     specs = [(128, 4, 21), (256, 8, 22), (512, 16, 23), (700, 21, 24), (64, 4, 25)]
     inst = _instances(specs)

@@ -73,6 +73,103 @@ def test_x2_step_bitwise(case, f32):
     assert widths[1] == wu
 
 
+def long_range_ell(N, offsets, seed):
+    """Symmetric rows i with entries at i and i +- each offset (mod N): a
+    handful of entries spread over the whole row, so X^2's row windows span
+    most of the N columns and fill far less than 1/64 of them."""
+    rng = np.random.default_rng(seed)
+    rows = [set([i]) for i in range(N)]
+    for i in range(N):
+        for o in offsets:
+            j = (i + o) % N
+            rows[i].add(j)
+            rows[j].add(i)
+    vals = {}
+    for i in range(N):
+        for j in rows[i]:
+            if (j, i) in vals:
+                vals[(i, j)] = vals[(j, i)]
+            else:
+                vals[(i, j)] = float(rng.uniform(-1, 1))
+    M = max(len(r) for r in rows)
+    nnz = np.zeros(N, np.int32)
+    idx = np.zeros(N * M, np.int32)
+    val = np.zeros(N * M)
+    for i in range(N):
+        c = sorted(rows[i])
+        nnz[i] = len(c)
+        idx[i * M:i * M + len(c)] = c
+        val[i * M:i * M + len(c)] = [vals[(i, j)] for j in c]
+    return oracle.Ell(N, M, nnz, idx, val)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_x2_step_row_windows_wider_than_12288_columns(f32):
+    """Rows of X^2 whose column windows run over more than 12288 columns (192
+    aligned blocks of 64) on the ELLPACK kernels: the norm's row term is the
+    tree over all column positions whatever the window's width."""
+    N = 20000
+    A = long_range_ell(N, (1, 6133, 13007), seed=71)
+    if f32:
+        A = oracle.Ell(N, A.M, A.nnz, A.idx, A.val.astype(np.float32))
+    tau = np.float32(1e-3) if f32 else 1e-3
+    prec = E.ELL_F32 if f32 else E.ELL_F64
+    rc, Y, d1, d2, wy = oracle.x2(A, tau, M2=64)
+    assert rc == 0
+    X = dev_from_oracle(A, prec)
+    Yd = E.DeviceEll(N, 64, prec)
+    U = E.DeviceEll(N, 64, prec)
+    rc, out, widths = E.ellpack_x2_step(X.h, Yd.h, U.h, tau)
+    assert rc == E.ELL_OK, E.ellpack_strerror(rc)
+    assert widths[0] == wy
+    cols = [c for c, _ in Y.rows()]
+    assert max(int(c[-1]) - int(c[0]) for c in cols if len(c)) > 12288
+    assert_same_rows(oracle_from_dev(Yd, f32), Y, "X^2")
+    eta2, _ = oracle.norm2(A, Y)
+    assert np.isfinite(out[2])
+    assert same_float(out[2], eta2)
+    assert same_float(out[0], oracle.pairwise(d1)) and same_float(out[1], oracle.pairwise(d2))
+    rcu, Uo, wu = oracle.update(A, Y, tau, Mo=64)
+    assert rcu == 0 and widths[1] == wu
+    assert_same_rows(oracle_from_dev(U, f32), Uo, "2X - X^2")
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("sparse_rows", [False, True])
+def test_x2_step_subnormal_operands_tau0(f32, sparse_rows):
+    """tau = 0 keeps every nonzero, so products that land in the subnormal
+    range (and subnormal entries themselves) reach the output: the matrix-core
+    span kernel (dense rows) and the ELLPACK kernel (sparse rows) must give the
+    oracle's bits there too."""
+    rng = np.random.default_rng(81 + f32 + 2 * sparse_rows)
+    N = 600 if sparse_rows else 200
+    dens = 0.004 if sparse_rows else 0.15
+    D = rng.uniform(-1, 1, (N, N)) * (rng.random((N, N)) < dens)
+    D = np.triu(D) + np.triu(D, 1).T
+    small, tiny = (2.0 ** -70, 2.0 ** -140) if f32 else (2.0 ** -530, 2.0 ** -1040)
+    pick = rng.random((N, N))
+    pick = np.triu(pick) + np.triu(pick, 1).T
+    D = np.where(pick < 0.3, D * small, D)        # products of two: subnormal or underflow
+    D = np.where(pick > 0.9, D * tiny, D)         # subnormal entries
+    if f32:
+        D = D.astype(np.float32).astype(np.float64)
+    nnz, idx, val, Mx = synth.dense_to_ell(D)
+    A = oracle.Ell(N, Mx, nnz, idx, val.astype(np.float32) if f32 else val)
+    sub = np.abs(A.val[A.val != 0]) < (np.finfo(np.float32 if f32 else np.float64).tiny)
+    assert sub.any()
+    tau = np.float32(0.0) if f32 else 0.0
+    rc, out, widths, X, Yd, U, (Y, d1, d2, wy) = x2_pair(A, tau, f32, with_u=True)
+    assert rc == E.ELL_OK, E.ellpack_strerror(rc)
+    Yv = Y.val[Y.val != 0]
+    assert (np.abs(Yv) < np.finfo(Yv.dtype).tiny).any()   # subnormal results are in the output
+    assert_same_rows(oracle_from_dev(Yd, f32), Y, "X^2")
+    assert same_float(out[1], oracle.pairwise(d2))
+    eta2, _ = oracle.norm2(A, Y)
+    assert same_float(out[2], eta2)
+    rcu, Uo, wu = oracle.update(A, Y, tau)
+    assert_same_rows(oracle_from_dev(U, f32), Uo, "2X - X^2")
+
+
 def test_x2_threshold_matches_step_and_is_deterministic():
     A = random_ell(300, 0.05, seed=5, symmetric=True)
     rc, Y, d1, d2, wy = oracle.x2(A, 1e-3)
