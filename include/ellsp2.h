@@ -136,6 +136,21 @@ int ellpack_x2_threshold(const ellpack_t *X, ellpack_t *X2, double tau, double t
 int ellpack_x2_step(const ellpack_t *X, ellpack_t *X2, ellpack_t *U, double tau, double out[3],
                     int32_t widths[2]);
 
+/* ellpack_x2_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results, errors and bits as ellpack_x2_step, computed
+ * by the ELLPACK step kernel only, with every intermediate (per-row outputs,
+ * reduction partials, the validation flag) in a fixed device array of the
+ * library, about 4 MiB per device, kept until the process ends.  Calls no
+ * hipMalloc / hipFree.  N must be <= 131072 (ELL_EINVAL beyond, with a
+ * message in ellpack_last_device_error).  The first call on a device resolves
+ * that device's copy of the array (the current device, which must be the
+ * handles' device).  Every call on one device shares that array: calls that
+ * overlap on one device (other host threads, or other streams still running
+ * an earlier call) race and give undefined results. */
+int ellpack_x2_step_noalloc(const ellpack_t *X, ellpack_t *X2, ellpack_t *U, double tau, double out[3],
+                            int32_t widths[2]);
+
 /* Tr A by the pairwise tree. */
 int ellpack_trace(const ellpack_t *A, double *trace_out);
 

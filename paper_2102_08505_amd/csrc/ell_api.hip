@@ -685,6 +685,140 @@ extern "C" int ellpack_x2_threshold(const ellpack_t *X, ellpack_t *X2, double ta
   return rc;
 }
 
+// ===========================================================================
+// the fused step without allocation
+// ===========================================================================
+namespace {
+
+// Scratch of ellpack_x2_step_noalloc: the per-row outputs and reduction
+// partials of the ELLPACK step kernel for up to kNoAllocMaxN rows, in one
+// file-scope device array (each device holds its own copy until the process
+// ends).  Layout, every part starting on a 256-byte boundary:
+//   [0, 256)           validation flag (int32), out (3 double), outw (4 int32), outn (2 int64)
+//   part   3 nb double, partw 4 nb int32, partn 2 nb int64   (nb = ceil(N / 1024) <= kNoAllocBlocks)
+//   d1, d2, e          kNoAllocMaxN double each
+//   wy, wu             kNoAllocMaxN int32 each
+constexpr int32_t kNoAllocMaxN = 131072;
+constexpr int32_t kNoAllocBlocks = (kNoAllocMaxN + kRedBlock - 1) / kRedBlock;
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kNaHead = 0;
+constexpr size_t kNaPart = 256;
+constexpr size_t kNaPartW = kNaPart + align256(sizeof(double) * 3 * kNoAllocBlocks);
+constexpr size_t kNaPartN = kNaPartW + align256(sizeof(int32_t) * 4 * kNoAllocBlocks);
+constexpr size_t kNaRows = kNaPartN + align256(sizeof(int64_t) * 2 * kNoAllocBlocks);
+constexpr size_t kNaD1 = kNaRows;
+constexpr size_t kNaD2 = kNaD1 + align256(sizeof(double) * kNoAllocMaxN);
+constexpr size_t kNaE = kNaD2 + align256(sizeof(double) * kNoAllocMaxN);
+constexpr size_t kNaWy = kNaE + align256(sizeof(double) * kNoAllocMaxN);
+constexpr size_t kNaWu = kNaWy + align256(sizeof(int32_t) * kNoAllocMaxN);
+constexpr size_t kNoAllocBytes = kNaWu + align256(sizeof(int32_t) * kNoAllocMaxN);  // about 4 MiB
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device, resolved once per device with
+// that device current.  In host code the array's name is only a host-side
+// stand-in: kernels receive these addresses.
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+int noalloc_scratch(unsigned char **out)
+{
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) {
+    set_device_error("ellpack_x2_step_noalloc: device ordinal beyond the library's table of 64");
+    return ELL_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_device_error("ellpack_x2_step_noalloc: no device address for the scratch array");
+      return ELL_EDEVICE;
+    }
+    g_noalloc_ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return ELL_OK;
+}
+
+template <typename T>
+int run_step_noalloc(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3], int32_t widths[2])
+{
+  const int N = X->N;
+  unsigned char *base = nullptr;
+  int rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  int32_t *flag = reinterpret_cast<int32_t *>(base + kNaHead);
+  StepScratch s{};
+  s.out = reinterpret_cast<double *>(base + kNaHead + 64);
+  s.outw = reinterpret_cast<int32_t *>(base + kNaHead + 128);
+  s.outn = reinterpret_cast<int64_t *>(base + kNaHead + 192);
+  s.part = reinterpret_cast<double *>(base + kNaPart);
+  s.partw = reinterpret_cast<int32_t *>(base + kNaPartW);
+  s.partn = reinterpret_cast<int64_t *>(base + kNaPartN);
+  s.d1 = reinterpret_cast<double *>(base + kNaD1);
+  s.d2 = reinterpret_cast<double *>(base + kNaD2);
+  s.e = reinterpret_cast<double *>(base + kNaE);
+  s.wy = reinterpret_cast<int32_t *>(base + kNaWy);
+  s.wu = reinterpret_cast<int32_t *>(base + kNaWu);
+  s.ly = s.lu = nullptr;
+  s.flags = nullptr;
+  s.nb = (N + kRedBlock - 1) / kRedBlock;
+  s.nq = (N + 63) / 64;
+  // a wrapped X is validated on its first use, as by ellpack_x2_step, with
+  // the flag in the scratch array (cleared first: it keeps the last call's value)
+  if (!X->validated) {
+    HIP_TRY(launch_zero_words(1, flag, X->stream));
+    HIP_TRY(launch_validate<T>(N, view<T>(X), flag, X->stream));
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, X->stream));
+    HIP_TRY(hipStreamSynchronize(X->stream));
+    if (h & 1) return ELL_EINVAL;
+    if (h & 2) return ELL_ENONFINITE;
+    const_cast<ellpack *>(X)->validated = true;
+  }
+  Rot3<T> bufs{{view<T>(X), view<T>(Y), U ? view<T>(U) : view<T>(Y)}};
+  HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, s, X->stream));
+  HIP_TRY(launch_reduce(N, nullptr, s, X->stream));
+  HIP_TRY(launch_final_only(s, X->stream));
+  double h[3];
+  int32_t w[4];
+  HIP_TRY(hipMemcpyAsync(h, s.out, sizeof(h), hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipMemcpyAsync(w, s.outw, sizeof(w), hipMemcpyDeviceToHost, X->stream));
+  HIP_TRY(hipStreamSynchronize(X->stream));
+  if (out) {
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+  }
+  if (widths) {
+    widths[0] = w[0];
+    widths[1] = U ? w[1] : 0;
+  }
+  if (w[0] > Y->M || (U && w[1] > U->M)) return ELL_EOVERFLOW;
+  Y->validated = true;
+  if (U) U->validated = true;
+  return ELL_OK;
+}
+
+}  // namespace
+
+extern "C" int ellpack_x2_step_noalloc(const ellpack_t *X, ellpack_t *X2, ellpack_t *U, double tau, double out[3],
+                                       int32_t widths[2])
+{
+  int rc = check_step_args(X, X2, U, tau);
+  if (rc) return rc;
+  if (X->N > kNoAllocMaxN) {
+    g_last_error = "ellpack_x2_step_noalloc: N exceeds the 131072 rows of its fixed scratch";
+    return ELL_EINVAL;
+  }
+  return X->prec == ELL_F64 ? run_step_noalloc<double>(X, X2, U, tau, out, widths)
+                            : run_step_noalloc<float>(X, X2, U, tau, out, widths);
+}
+
 extern "C" int ellpack_trace(const ellpack_t *A, double *trace_out)
 {
   if (!A || !trace_out) return ELL_EINVAL;

@@ -140,6 +140,7 @@ template <typename TS, typename TD>
 hipError_t launch_copy(int N, EllView<TS> src, EllView<TD> dst, hipStream_t stream);
 template <typename T>
 hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stream);
+hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream);
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
 hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hipStream_t stream);

@@ -752,6 +752,14 @@ __global__ __launch_bounds__(256) void k_validate(int N, EllView<T> A, int32_t *
   if (nonfinite) atomicOr(flags, 2);
 }
 
+// n words set to zero (a kernel rather than a memset node, so that a caller
+// may record it in a graph)
+__global__ __launch_bounds__(256) void k_zero_words(int n, int32_t *p)
+{
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_trace_rows(int N, EllView<T> A, double *d)
 {
@@ -911,6 +919,13 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 }
 template hipError_t launch_validate<double>(int, EllView<double>, int32_t *, hipStream_t);
 template hipError_t launch_validate<float>(int, EllView<float>, int32_t *, hipStream_t);
+
+hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream)
+{
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, stream, n, p);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream)

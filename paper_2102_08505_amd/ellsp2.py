@@ -71,6 +71,7 @@ def load():
     L.ellpack_download.argtypes = [vp, i32p, i32p, f64p]
     L.ellpack_x2_threshold.argtypes = [vp, vp, C.c_double, f64p, i32p]
     L.ellpack_x2_step.argtypes = [vp, vp, vp, C.c_double, f64p, i32p]
+    L.ellpack_x2_step_noalloc.argtypes = [vp, vp, vp, C.c_double, f64p, i32p]
     L.ellpack_trace.argtypes = [vp, f64p]
     L.ellpack_trace_product.argtypes = [vp, vp, f64p]
     L.sp2_solve.argtypes = [vp, vp, C.POINTER(SP2Params), C.POINTER(SP2Report)]
@@ -191,6 +192,15 @@ def ellpack_x2_step(X, X2, U, tau):
     out = np.zeros(3)
     w = np.zeros(2, np.int32)
     rc = load().ellpack_x2_step(X, X2, U, float(tau), _ptr(out, f64p), _ptr(w, i32p))
+    return rc, tuple(out), tuple(int(x) for x in w)
+
+
+def ellpack_x2_step_noalloc(X, X2, U, tau):
+    """ellpack_x2_step with its intermediates in the library's fixed device
+    scratch (no device allocation).  Returns as ellpack_x2_step."""
+    out = np.zeros(3)
+    w = np.zeros(2, np.int32)
+    rc = load().ellpack_x2_step_noalloc(X, X2, U, float(tau), _ptr(out, f64p), _ptr(w, i32p))
     return rc, tuple(out), tuple(int(x) for x in w)
 
 
