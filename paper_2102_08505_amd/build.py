@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libellsp2.so")
-SOURCES = ["ell_api.hip", "ell_kernels.hip", "ell_band.hip", "ell_band16.hip", "dense.hip"]
+SOURCES = ["ell_api.hip", "ell_kernels.hip", "ell_band.hip", "ell_band16.hip", "ell_sym16.hip", "dense.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -26,7 +26,8 @@ HIPCC_FLAGS = [
 
 # The matrix-core band kernel keeps its accumulators in VGPRs: with the
 # compiler's AGPR choice they are copied between the two files every step.
-EXTRA_FLAGS = {"ell_band16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA_FLAGS = {"ell_band16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               "ell_sym16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose=False, jobs=4):

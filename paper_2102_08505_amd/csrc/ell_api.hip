@@ -303,9 +303,9 @@ struct StepMem {
     if ((err = d1.alloc(sizeof(double) * N)) || (err = d2.alloc(sizeof(double) * N)) ||
         (err = e.alloc(sizeof(double) * N)) || (err = wy.alloc(sizeof(int32_t) * N)) ||
         (err = wu.alloc(sizeof(int32_t) * N)) || (err = ly.alloc(sizeof(int32_t) * N)) ||
-        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 3 * nq)) ||
+        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 5 * nq)) ||
         (err = partw.alloc(sizeof(int32_t) * 4 * nq)) || (err = partn.alloc(sizeof(int64_t) * 2 * nq)) ||
-        (err = out.alloc(sizeof(double) * 3)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
+        (err = out.alloc(sizeof(double) * 5)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
         (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))))
       return err;
     if ((err = flags.zero(sizeof(int32_t)))) return err;
@@ -937,6 +937,7 @@ struct InitBlock {
   unsigned long long total;   // entries of X0
   int32_t maxlen;             // longest row interval of X0
   int32_t xflags;             // bit 2: X0 stores an exact zero
+  int32_t asym;               // bit 0: H is not bitwise symmetric
 };
 
 // Per-iteration history, one block of arrays of max_iter entries each (device,
@@ -960,6 +961,7 @@ struct Solver {
   std::vector<hipEvent_t> events;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // step-kernel launches when profiling
   bool profile = false;
+  bool sym = false;  // H bitwise symmetric: the span iteration fixes each branch before its product
   ~Solver()
   {
     if (pin.b.p) (void)hipStreamSynchronize(stream);  // nothing queued still writes the pinned block
@@ -1001,6 +1003,19 @@ int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T
   SP2State *st = S.state.as<SP2State>();
   StepScratch sc = S.step.s;
   *published = false;
+  if (pipe == PIPE_SPAN && S.sym && x2_band16_fits(S.N, Sp.SW, (int)sizeof(T))) {
+    // product of the branch fixed beforehand, writing that iterate only; then
+    // the rest of the reduction, the decision and the next branch
+    cfg.span = 1;
+    HIP_TRY(launch_x2_sym_part<T>(S.N, Sp.rot(), st, tau, sc, S.stream));
+    if (S.profile) {
+      HIP_TRY(S.mark(&b));
+      S.marks.emplace_back(a, b);
+    }
+    HIP_TRY(launch_sym_final(st, cfg, S.hist_dev(), sc, publish, S.stream));
+    *published = publish != nullptr;
+    return ELL_OK;
+  }
   if (pipe == PIPE_SPAN && x2_band16_fits(S.N, Sp.SW, (int)sizeof(T))) {
     // product with 64-row partials, then the rest of the reduction and the decision
     cfg.span = 1;
@@ -1154,6 +1169,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   InitBlock &hi = *S.init_host();
   HIP_TRY(hipMemsetAsync(ib, 0, sizeof(InitBlock), st));
   HIP_TRY(launch_gershgorin(N, view<double>(H), S.glo.as<double>(), S.ghi.as<double>(), &ib->emin, &ib->flags, st));
+  HIP_TRY(launch_check_symmetric(N, view<double>(H), &ib->asym, st));
   bool first = true;
   for (;;) {
     if (!first) {  // X0 again, wider: clear the X0 results
@@ -1192,15 +1208,20 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   {
     const int32_t maxlen = hi.maxlen;
     const bool zeros = (hi.xflags & 4) != 0;
-    const int32_t sw = std::min(std::max(256, roundup64(maxlen)), std::max(64, roundup64(N)));
+    // a bitwise symmetric H gives bitwise symmetric iterates: their rows are
+    // read through the symmetry, in runs of kSymAlign columns
+    S.sym = (hi.asym & 1) == 0;
+    const int32_t pad = S.sym ? 2 * (kSymAlign - 1) : 0;
+    const int32_t sw = std::min(std::max(256, roundup64(maxlen + pad)), std::max(64, roundup64(N)));
     // (X0's fill of its intervals does not decide here: the iterates fill them)
     if (!zeros && maxlen <= kMaxCap) {
+      const int align = S.sym ? kSymAlign : 1;
       if (mixed) {
         HIP_TRY(S32.alloc(N, sw));
-        HIP_TRY(launch_ell_to_span<float>(N, W32.v(0), S32.v(0), st));
+        HIP_TRY(launch_ell_to_span<float>(N, W32.v(0), S32.v(0), st, align));
       } else {
         HIP_TRY(S64.alloc(N, sw));
-        HIP_TRY(launch_ell_to_span<double>(N, W64.v(0), S64.v(0), st));
+        HIP_TRY(launch_ell_to_span<double>(N, W64.v(0), S64.v(0), st, align));
       }
       pipe = PIPE_SPAN;
     }
@@ -1224,6 +1245,22 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   cfg.tail = p->fp64_tail_steps;
   cfg.stall = p->stall_stop ? 1 : 0;
   cfg.mixed = mixed ? 1 : 0;
+
+  // The symmetric iteration needs the branch of the first product of the
+  // current X before it: from the chains of squares of X's rows.
+  auto seed = [&]() -> int {
+    if (pipe != PIPE_SPAN || !S.sym) return ELL_OK;
+    SP2State *dst = S.state.as<SP2State>();
+    if (hs.phase32) {
+      if (x2_band16_fits(N, S32.SW, (int)sizeof(float)))
+        HIP_TRY(launch_sym_seed<float>(N, S32.rot(), dst, cfg, S.step.s, st));
+    } else {
+      if (x2_band16_fits(N, S64.SW, (int)sizeof(double)))
+        HIP_TRY(launch_sym_seed<double>(N, S64.rot(), dst, cfg, S.step.s, st));
+    }
+    return ELL_OK;
+  };
+  if ((rc = seed())) return rc;
 
   auto restart = [&]() -> int {
     hs.stop = 0;
@@ -1413,7 +1450,13 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       hs.cur = 0;
       hs.phase32 = 0;
       if ((rc = restart())) return rc;
+      if ((rc = seed())) return rc;  // the FP64 traces of the widened X fix its first branch
       continue;
+    }
+    if (hs.status == ST_MISPREDICT) {  // (the report holds the history up to that product)
+      g_last_error = "sp2_solve: the traces of an iterate differ from those its branch was chosen with";
+      status = ELL_EDEVICE;
+      break;
     }
     status = hs.status;
     break;

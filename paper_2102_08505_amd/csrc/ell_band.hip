@@ -536,8 +536,10 @@ __global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t
 }
 
 // ELLPACK -> span form, one wave per row: positions not stored are zero.
+// The interval starts on a multiple of `align` columns (a power of two) and
+// holds a multiple of `align` positions.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanView<T> S)
+__global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanView<T> S, int align)
 {
   const int w = threadIdx.x >> 6;
   const int i = blockIdx.x * kWavesPerBlock + w;
@@ -546,8 +548,8 @@ __global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanVi
   const int n = A.nnz[i];
   const int32_t *ci = A.idx + (size_t)i * A.M;
   const T *vi = A.val + (size_t)i * A.M;
-  const int b = n > 0 ? ci[0] : 0;
-  const int l = n > 0 ? ci[n - 1] - b + 1 : 0;
+  const int b = n > 0 ? ci[0] & ~(align - 1) : 0;
+  const int l = n > 0 ? ((ci[n - 1] | (align - 1)) + 1) - b : 0;
   // each lane fills its positions by a binary search in the sorted row
   for (int p = lane; p < l; p += kWave) {
     const int j = b + p;
@@ -687,14 +689,15 @@ template hipError_t launch_ell_extent<float>(int, EllView<float>, int32_t *, int
                                              unsigned long long *, hipStream_t);
 
 template <typename T>
-hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream)
+hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream, int align)
 {
+  if (align < 1 || (align & (align - 1))) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_ell_to_span<T>), dim3((N + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream, N,
-                     A, S);
+                     A, S, align);
   return hipGetLastError();
 }
-template hipError_t launch_ell_to_span<double>(int, EllView<double>, SpanView<double>, hipStream_t);
-template hipError_t launch_ell_to_span<float>(int, EllView<float>, SpanView<float>, hipStream_t);
+template hipError_t launch_ell_to_span<double>(int, EllView<double>, SpanView<double>, hipStream_t, int);
+template hipError_t launch_ell_to_span<float>(int, EllView<float>, SpanView<float>, hipStream_t, int);
 
 template <typename TS, typename TD>
 hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream)

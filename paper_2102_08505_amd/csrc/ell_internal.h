@@ -61,9 +61,15 @@ struct SP2State {
   int32_t wy_max, wu_max;
   int64_t nnz_cur;      // stored entries of the current X
   double trx, trx2, eta2;
+  // symmetric span iteration: the branch of the next product (1: 2X - X^2),
+  // fixed from the traces of the current X that the step which wrote it
+  // predicted, Tr X and the unpruned Tr X^2; the next step checks them
+  int32_t up_next, pad_;
+  double ptrx, ptrx2;
 };
 
 enum { ST_FALLBACK = 3 };  // span pipeline cannot take a row group: continue on ELLPACK
+enum { ST_MISPREDICT = 4 };  // symmetric iteration: the traces of X differ from those predicted
 
 struct SP2Cfg {
   double n_occ, target2, switch2;
@@ -87,12 +93,12 @@ struct StepScratch {
   double *part;             // 3 * nb partial sums
   int32_t *partw;           // 4 * nb partial maxima (wy, wu, ly, lu)
   int64_t *partn;           // 2 * nb partial nnz totals (X2, U)
-  double *out;              // 3: TrX, TrX2, eta2
+  double *out;              // 3: TrX, TrX2, eta2 (symmetric span iteration: 5, with Tr X', Tr X'^2)
   int32_t *outw;            // 4: widest X2 row, widest U row, longest X2 / U interval
   int64_t *outn;            // 2: nnz(X2), nnz(U)
   int32_t *flags;           // bit 0: a row group needs the ELLPACK pipeline
   int32_t nb;               // number of 1024-row reduction blocks
-  int32_t nq;               // number of 64-row partials (span iteration on the matrix cores; part* hold 3 / 4 / 2 * nq)
+  int32_t nq;               // number of 64-row partials (span iteration on the matrix cores; part* hold 5 / 4 / 2 * nq)
 };
 
 constexpr int kRedBlock = 1024;  // rows per partial-reduction block
@@ -143,6 +149,8 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream);
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
+// *flag |= 1 unless every stored H_ij has a stored H_ji with the same bits
+hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, hipStream_t stream);
 hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hipStream_t stream);
 // row terms of Tr(AB): d[i] = ascending-j fma chain of A_ij * B_ji
 template <typename TA, typename TB>
@@ -168,6 +176,21 @@ hipError_t launch_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T
                                  hipStream_t stream);
 hipError_t launch_step_final64(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
                                SP2State *publish, hipStream_t stream);
+// The symmetric span iteration on the matrix cores (ell_sym16.hip): the
+// product writes only the iterate of the branch fixed beforehand
+// (st->up_next) and leaves 64-row partials of Tr X, Tr X^2, eta^2 and of
+// Tr X', Tr X'^2 of that iterate (needs x2_band16_fits, spans whose rows
+// start on a multiple of 16 / sizeof(T) columns and hold a multiple of that,
+// X bitwise symmetric, s sized for N rows); then the decision.  The seed sets
+// the branch of the first product of the current X from its traces.
+template <typename T>
+hipError_t launch_x2_sym_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
+                              hipStream_t stream);
+hipError_t launch_sym_final(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
+                            SP2State *publish, hipStream_t stream);
+template <typename T>
+hipError_t launch_sym_seed(int N, SpanRot3<T> spans, SP2State *st, const SP2Cfg &cfg, const StepScratch &s,
+                           hipStream_t stream);
 template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                   const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
@@ -183,8 +206,12 @@ hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, 
 // interval positions) goes to the ELLPACK kernels.  (Not so in SP2, whose
 // iterates fill their intervals.)
 constexpr int kMinSpanFillInv = 64;
+// (rows start on a multiple of `align` columns and hold a multiple of `align`
+// positions, zeros filling the ends; align a power of two)
 template <typename T>
-hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream);
+hipError_t launch_ell_to_span(int N, EllView<T> A, SpanView<T> S, hipStream_t stream, int align = 1);
+// Span alignment of the symmetric iteration: 16-byte runs of either precision
+constexpr int kSymAlign = 4;
 template <typename TS, typename TD>
 hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax, hipStream_t stream);
 // batched step: ngroups groups of kGroupRows rows; group -> instance; instance m's

@@ -752,6 +752,35 @@ __global__ __launch_bounds__(256) void k_validate(int N, EllView<T> A, int32_t *
   if (nonfinite) atomicOr(flags, 2);
 }
 
+// Bitwise symmetry of an ELLPACK matrix, one thread per row: each stored
+// (i, j) is looked up in row j by bisection.
+__global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag)
+{
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int n = H.nnz[i];
+  bool bad = false;
+  for (int s = 0; s < n && !bad; ++s) {
+    const int j = H.idx[(size_t)i * H.M + s];
+    const double v = H.val[(size_t)i * H.M + s];
+    const int32_t *cj = H.idx + (size_t)j * H.M;
+    int lo = 0, hi = H.nnz[j] - 1;
+    bool found = false;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int c = cj[mid];
+      if (c == i) {
+        found = __double_as_longlong(H.val[(size_t)j * H.M + mid]) == __double_as_longlong(v);
+        break;
+      }
+      if (c < i) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    bad = !found;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // n words set to zero (a kernel rather than a memset node, so that a caller
 // may record it in a graph)
 __global__ __launch_bounds__(256) void k_zero_words(int n, int32_t *p)
@@ -919,6 +948,12 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 }
 template hipError_t launch_validate<double>(int, EllView<double>, int32_t *, hipStream_t);
 template hipError_t launch_validate<float>(int, EllView<float>, int32_t *, hipStream_t);
+
+hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, hipStream_t stream)
+{
+  hipLaunchKernelGGL(k_check_symmetric, dim3((N + 255) / 256), dim3(256), 0, stream, N, H, flag);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream)
 {

@@ -92,5 +92,110 @@ __device__ inline void decide(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h,
   st->iter = n + 1;
 }
 
+__device__ inline bool closer_up(double trx, double trx2, double n_occ)
+{
+  return fabs(2.0 * trx - trx2 - n_occ) < fabs(trx2 - n_occ);
+}
+
+__device__ inline bool same_bits(double a, double b) { return __double_as_longlong(a) == __double_as_longlong(b); }
+
+// The branch of the next product from the traces of the current X (Tr X and
+// the unpruned Tr X^2, the latter from the chains of squares of its rows).
+__device__ inline void seed_sym(SP2State *st, const SP2Cfg &cfg, double trx, double trx2)
+{
+  st->ptrx = trx;
+  st->ptrx2 = trx2;
+  st->up_next = closer_up(trx, trx2, cfg.n_occ) ? 1 : 0;
+}
+
+// decide() for the symmetric span iteration, whose product wrote only the
+// iterate of the branch st->up_next: the same record, stop, stall, switch,
+// limit and overflow rules; the branch taken is the one fixed beforehand,
+// which equals the rule's choice on this product's traces because those
+// traces equal the predicted ones (checked: a difference stops the solve
+// with ST_MISPREDICT).  s.out[3], s.out[4]: Tr X', Tr X'^2 of the written
+// iterate, which fix the next branch.  s.outw: widest pruned X^2 row, widest
+// iterate row, longest iterate interval; s.outn: entries of the pruned X^2
+// and of the iterate.
+__device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s)
+{
+  const int n = st->iter;
+  const double trx = s.out[0], trx2 = s.out[1], eta2 = s.out[2];
+  if (!same_bits(trx, st->ptrx) || !same_bits(trx2, st->ptrx2)) {
+    // the product's own traces are recorded; D keeps X_n
+    h.trx[n] = trx;
+    h.trx2[n] = trx2;
+    h.eta2[n] = eta2;
+    h.maxw[n] = s.outw[0];
+    h.prec[n] = (int8_t)st->phase32;
+    h.up[n] = -1;
+    h.nnzx[n] = st->nnz_cur;
+    h.nnzy[n] = s.outn[0];
+    st->trx = trx;
+    st->trx2 = trx2;
+    st->eta2 = eta2;
+    st->iter = n + 1;
+    st->status = ST_MISPREDICT;
+    st->stop = 1;
+    return;
+  }
+  st->trx = trx;
+  st->trx2 = trx2;
+  st->eta2 = eta2;
+  st->wy_max = s.outw[0];
+  st->wu_max = s.outw[1];
+  h.trx[n] = trx;
+  h.trx2[n] = trx2;
+  h.eta2[n] = eta2;
+  h.maxw[n] = s.outw[0];
+  h.prec[n] = (int8_t)st->phase32;
+  h.up[n] = -1;
+  h.nnzx[n] = st->nnz_cur;
+  h.nnzy[n] = s.outn[0];
+  const bool stall = cfg.stall && stalled(h.eta2 + st->phase_start, n - st->phase_start);
+  if (st->phase32) {
+    if (eta2 < cfg.switch2 || stall) {
+      st->phase_start = n + 1;
+      st->iter = n + 1;
+      st->stop = 1;
+      st->status = (n + 1 == cfg.max_iter) ? ELL_ENOCONV : ST_SWITCH;
+      return;
+    }
+  } else {
+    if (eta2 < cfg.target2 && st->fp64_updates >= (cfg.mixed ? cfg.tail : 0)) {
+      st->status = ELL_OK;
+      st->stop = 1;
+      st->iter = n + 1;
+      return;
+    }
+    if (stall) {
+      st->status = ELL_ENOCONV;
+      st->stop = 1;
+      st->iter = n + 1;
+      return;
+    }
+  }
+  if (n + 1 == cfg.max_iter) {
+    st->status = ELL_ENOCONV;
+    st->stop = 1;
+    st->iter = n + 1;
+    return;
+  }
+  const bool up = st->up_next != 0;
+  if (s.outw[2] > st->sw) {
+    st->status = ELL_EOVERFLOW;
+    st->need_width = s.outw[2];
+    st->stop = 1;
+    return;
+  }
+  h.up[n] = up ? 1 : 0;
+  const int c = st->cur;
+  st->cur = up ? (c == 0 ? 2 : c - 1) : (c == 2 ? 0 : c + 1);
+  if (!st->phase32) st->fp64_updates += 1;
+  st->nnz_cur = s.outn[1];
+  st->iter = n + 1;
+  seed_sym(st, cfg, s.out[3], s.out[4]);
+}
+
 }  // namespace sp2dev
 }  // namespace ellsp2
