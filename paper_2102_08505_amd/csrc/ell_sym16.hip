@@ -221,11 +221,11 @@ struct RowOut {
 };
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16).  X is read, the
-// iterate the branch selects (up: 2X - X^2, else X^2) is written to SO.  rw:
+// iterate the branch selects (UP: 2X - X^2, else X^2) is written to SO.  rw:
 // the wave's 16 rows in the workgroup's RowOut.
-template <typename T>
+template <typename T, bool UP>
 __device__ void rows16_sym(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SO,
-                           const bool up, const T tau, double *stk, double *sq, int2 *meta, RowOut &ro, const int rw)
+                           const T tau, double *stk, double *sq, int2 *meta, RowOut &ro, const int rw)
 {
   constexpr int G = Run<T>::G, H = Run<T>::H;
   const int lane = lane_id();
@@ -392,9 +392,14 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
           const T y = acc[kP * sb + p][t], x = xv[t][p];
           ky[p] = act && absv(y) > tau;
           const T yk = ky[p] ? y : T(0);
-          const T v = up ? T(2) * x - yk : yk;
-          kv[p] = act && absv(v) > tau;
-          vk[p] = kv[p] ? v : T(0);
+          if (UP) {
+            const T v = T(2) * x - yk;
+            kv[p] = act && absv(v) > tau;
+            vk[p] = kv[p] ? v : T(0);
+          } else {  // the iterate is the pruned X^2 itself
+            kv[p] = ky[p];
+            vk[p] = yk;
+          }
           const double d = (double)yk - (double)x;
           sq[rr * kWave + (run_col<T>(0, p / G, r) + p % G)] = d * d;
           vks[t][p] = vk[p];
@@ -555,8 +560,12 @@ __global__ __launch_bounds__(256) void k_x2_sym_part(int N, SpanRot3<T> spans, c
     // the iterate goes where the decision will find it: X^2 to slot cur + 1,
     // 2X - X^2 to slot cur + 2 (mod 3)
     const int co = up ? (cur == 0 ? 2 : cur - 1) : (cur == 2 ? 0 : cur + 1);
-    rows16_sym<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], up, tau, stk_s[w], sq_s[w], meta_s[w], ro,
-                  w * kR);
+    if (up)
+      rows16_sym<T, true>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, stk_s[w], sq_s[w], meta_s[w], ro,
+                          w * kR);
+    else
+      rows16_sym<T, false>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, stk_s[w], sq_s[w], meta_s[w], ro,
+                           w * kR);
   } else if (lane < kR) {
     for (int c = 0; c < kSums; ++c) ro.s[c][w * kR + lane] = -0.0;
     ro.wy[w * kR + lane] = 0;
