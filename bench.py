@@ -380,9 +380,15 @@ def main():
                     help="skip the FP64 solve to ||X^2-X||_F < 1e-8 (tau = 1e-10)")
     ap.add_argument("--main-only", action="store_true",
                     help="only the FP64 solves of the headline line (for profiling the step kernel)")
+    ap.add_argument("--profile-size", type=int, default=0,
+                    help="with --main-only: run the FP64 solves at this N instead (tau 1e-9 above N = 32768), "
+                         "for profiling the step kernel at a size beyond the last-level cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling the HBM counters)")
     args = ap.parse_args()
+    if args.profile_size and not args.main_only:
+        print("--profile-size goes with --main-only", file=sys.stderr)
+        sys.exit(2)
     if args.main_only:
         args.no_cpu = args.no_mixed = args.no_batched = args.no_dense = True
         args.no_accuracy = args.no_x2_single = args.no_model = args.no_fp64_target = True
@@ -403,6 +409,11 @@ def main():
     E.load()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    global N, TAU
+    if args.profile_size:
+        N = args.profile_size
+        if N > 32768:
+            TAU = TAU_MIXED64  # (tau 1e-8 leaves the FP64 solve above the target at larger N)
     nnz, idx, val, M = synth.banded_hamiltonian(N, B)
     H = E.DeviceEll.from_host(N, M, nnz, idx, val, stream=stream)
     D = E.DeviceEll(N, M_CAP, stream=stream)
@@ -476,9 +487,9 @@ def main():
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_x2_sym_part (X^2 of the bitwise symmetric span form on the FP64 matrix "
-                               "cores, pruning, traces, norm, the iterate of the branch fixed beforehand, "
-                               "64-row partial sums)",
+                     "kernel": "k_x2_sym_step (X^2 of the bitwise symmetric span form on the FP64 matrix "
+                               "cores, pruning, traces, norm, the iterate of the branch fixed beforehand; "
+                               "the last workgroup reduces the partial sums and takes the SP2 decision)",
                      "bytes_per_launch": prof["x2_bytes"] / launches,
                      "alu": alu},
     }

@@ -293,22 +293,25 @@ int ensure_valid(const ellpack *A)
 
 // Scratch of one fused step for N rows.
 struct StepMem {
-  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags;
+  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags, ticket;
   StepScratch s{};
   hipError_t alloc(int N)
   {
     const int nb = (N + kRedBlock - 1) / kRedBlock;
     const int nq = (N + 63) / 64;  // 64-row partials of the matrix-core span iteration; nq >= nb
+    int lq = 1;                    // leaves per thread of the 256-thread trees over them
+    while (256 * lq < nq) lq *= 2;
     hipError_t err;
     if ((err = d1.alloc(sizeof(double) * N)) || (err = d2.alloc(sizeof(double) * N)) ||
         (err = e.alloc(sizeof(double) * N)) || (err = wy.alloc(sizeof(int32_t) * N)) ||
         (err = wu.alloc(sizeof(int32_t) * N)) || (err = ly.alloc(sizeof(int32_t) * N)) ||
-        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * 5 * nq)) ||
+        (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * (5 * nq + 256 * lq))) ||
         (err = partw.alloc(sizeof(int32_t) * 4 * nq)) || (err = partn.alloc(sizeof(int64_t) * 2 * nq)) ||
         (err = out.alloc(sizeof(double) * 5)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
-        (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))))
+        (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))) ||
+        (err = ticket.alloc(sizeof(uint32_t))))
       return err;
-    if ((err = flags.zero(sizeof(int32_t)))) return err;
+    if ((err = flags.zero(sizeof(int32_t))) || (err = ticket.zero(sizeof(uint32_t)))) return err;
     s.d1 = d1.as<double>();
     s.d2 = d2.as<double>();
     s.e = e.as<double>();
@@ -317,6 +320,7 @@ struct StepMem {
     s.ly = ly.as<int32_t>();
     s.lu = lu.as<int32_t>();
     s.flags = flags.as<int32_t>();
+    s.ticket = ticket.as<uint32_t>();
     s.part = part.as<double>();
     s.partw = partw.as<int32_t>();
     s.partn = partn.as<int64_t>();
@@ -347,7 +351,9 @@ template <typename T>
 struct SpanMem {
   DevMem val, base, len;
   int32_t SW = 0;
-  hipError_t alloc(int N, int32_t sw)
+  // zero_values: false when only the symmetric iteration reads the matrices
+  // (its reads stay inside the row intervals, which every writer fills)
+  hipError_t alloc(int N, int32_t sw, bool zero_values = true)
   {
     SW = sw;
     hipError_t e;
@@ -359,7 +365,7 @@ struct SpanMem {
     if ((e = base.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
     if ((e = len.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
     // the guard bands are read (and masked) by the band kernel: keep them finite
-    return val.zero(sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard));
+    return zero_values ? val.zero(sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard)) : hipSuccess;
   }
   void release()
   {
@@ -910,11 +916,11 @@ template <typename T>
 struct SpanSet {
   SpanMem<T> m[3];
   int32_t SW = 0;
-  hipError_t alloc(int N, int32_t sw)
+  hipError_t alloc(int N, int32_t sw, bool zero_values = true)
   {
     SW = sw;
     for (int b = 0; b < 3; ++b) {
-      hipError_t e = m[b].alloc(N, sw);
+      hipError_t e = m[b].alloc(N, sw, zero_values);
       if (e) return e;
     }
     return hipSuccess;
@@ -1007,12 +1013,11 @@ int launch_iteration(Solver &S, Pipe pipe, const SpanSet<T> &Sp, const WorkSet<T
     // product of the branch fixed beforehand, writing that iterate only; then
     // the rest of the reduction, the decision and the next branch
     cfg.span = 1;
-    HIP_TRY(launch_x2_sym_part<T>(S.N, Sp.rot(), st, tau, sc, S.stream));
+    HIP_TRY(launch_x2_sym_step<T>(S.N, Sp.rot(), st, tau, sc, cfg, S.hist_dev(), publish, S.stream));
     if (S.profile) {
       HIP_TRY(S.mark(&b));
       S.marks.emplace_back(a, b);
     }
-    HIP_TRY(launch_sym_final(st, cfg, S.hist_dev(), sc, publish, S.stream));
     *published = publish != nullptr;
     return ELL_OK;
   }
@@ -1216,11 +1221,13 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     // (X0's fill of its intervals does not decide here: the iterates fill them)
     if (!zeros && maxlen <= kMaxCap) {
       const int align = S.sym ? kSymAlign : 1;
+      // (the symmetric iteration reads nothing outside the rows' intervals)
+      const bool zero = !(S.sym && x2_band16_fits(N, sw, mixed ? (int)sizeof(float) : (int)sizeof(double)));
       if (mixed) {
-        HIP_TRY(S32.alloc(N, sw));
+        HIP_TRY(S32.alloc(N, sw, zero));
         HIP_TRY(launch_ell_to_span<float>(N, W32.v(0), S32.v(0), st, align));
       } else {
-        HIP_TRY(S64.alloc(N, sw));
+        HIP_TRY(S64.alloc(N, sw, zero));
         HIP_TRY(launch_ell_to_span<double>(N, W64.v(0), S64.v(0), st, align));
       }
       pipe = PIPE_SPAN;
@@ -1435,7 +1442,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     }
     if (hs.status == ST_SWITCH) {
       if (pipe == PIPE_SPAN) {
-        HIP_TRY(S64.alloc(N, S32.SW));
+        HIP_TRY(S64.alloc(N, S32.SW, !(S.sym && x2_band16_fits(N, S32.SW, (int)sizeof(double)))));
         HIP_TRY((launch_span_copy<float, double>(N, S32.v(hs.cur), S64.v(0), st)));
         HIP_TRY(hipStreamSynchronize(st));
         S32.release();

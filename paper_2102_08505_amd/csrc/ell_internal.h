@@ -90,13 +90,14 @@ struct StepScratch {
   double *d1, *d2, *e;      // N
   int32_t *wy, *wu;         // N: true survivor counts (may exceed capacity)
   int32_t *ly, *lu;         // N: interval lengths of X2 and U rows (span pipeline), or NULL
-  double *part;             // 3 * nb partial sums
+  double *part;             // 3 * nb partial sums (symmetric span iteration: 5 * nq + 256 L, L >= nq / 256 a power of two)
   int32_t *partw;           // 4 * nb partial maxima (wy, wu, ly, lu)
   int64_t *partn;           // 2 * nb partial nnz totals (X2, U)
   double *out;              // 3: TrX, TrX2, eta2 (symmetric span iteration: 5, with Tr X', Tr X'^2)
   int32_t *outw;            // 4: widest X2 row, widest U row, longest X2 / U interval
   int64_t *outn;            // 2: nnz(X2), nnz(U)
   int32_t *flags;           // bit 0: a row group needs the ELLPACK pipeline
+  uint32_t *ticket;         // workgroups of the symmetric step finished so far (0 between launches)
   int32_t nb;               // number of 1024-row reduction blocks
   int32_t nq;               // number of 64-row partials (span iteration on the matrix cores; part* hold 5 / 4 / 2 * nq)
 };
@@ -176,18 +177,18 @@ hipError_t launch_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T
                                  hipStream_t stream);
 hipError_t launch_step_final64(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
                                SP2State *publish, hipStream_t stream);
-// The symmetric span iteration on the matrix cores (ell_sym16.hip): the
-// product writes only the iterate of the branch fixed beforehand
-// (st->up_next) and leaves 64-row partials of Tr X, Tr X^2, eta^2 and of
-// Tr X', Tr X'^2 of that iterate (needs x2_band16_fits, spans whose rows
-// start on a multiple of 16 / sizeof(T) columns and hold a multiple of that,
-// X bitwise symmetric, s sized for N rows); then the decision.  The seed sets
-// the branch of the first product of the current X from its traces.
+// The symmetric span iteration on the matrix cores in one launch
+// (ell_sym16.hip): the product writes only the iterate of the branch fixed
+// beforehand (st->up_next); the workgroup that finishes last reduces the
+// traces, the norm and Tr X', Tr X'^2 of that iterate and takes the decision,
+// publishing the state to `publish` (mapped pinned host memory, or null).
+// Needs x2_band16_fits, spans whose rows start on a multiple of
+// 16 / sizeof(T) columns and hold a multiple of that, X bitwise symmetric, s
+// sized for N rows with s.ticket zero.  The seed sets the branch of the first
+// product of the current X from its traces.
 template <typename T>
-hipError_t launch_x2_sym_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
-                              hipStream_t stream);
-hipError_t launch_sym_final(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
-                            SP2State *publish, hipStream_t stream);
+hipError_t launch_x2_sym_step(int N, SpanRot3<T> spans, SP2State *st, T tau, const StepScratch &s,
+                              const SP2Cfg &cfg, const SP2Hist &h, SP2State *publish, hipStream_t stream);
 template <typename T>
 hipError_t launch_sym_seed(int N, SpanRot3<T> spans, SP2State *st, const SP2Cfg &cfg, const StepScratch &s,
                            hipStream_t stream);

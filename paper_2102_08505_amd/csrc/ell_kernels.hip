@@ -752,33 +752,35 @@ __global__ __launch_bounds__(256) void k_validate(int N, EllView<T> A, int32_t *
   if (nonfinite) atomicOr(flags, 2);
 }
 
-// Bitwise symmetry of an ELLPACK matrix, one thread per row: each stored
-// (i, j) is looked up in row j by bisection.
+// Bitwise symmetry of an ELLPACK matrix: one wavefront per row, rows strided
+// over the grid; each lane takes one stored (i, j) and looks it up in row j by
+// bisection.
 __global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag)
 {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const int n = H.nnz[i];
+  const int lane = lane_id();
   bool bad = false;
-  for (int s = 0; s < n && !bad; ++s) {
-    const int j = H.idx[(size_t)i * H.M + s];
-    const double v = H.val[(size_t)i * H.M + s];
-    const int32_t *cj = H.idx + (size_t)j * H.M;
-    int lo = 0, hi = H.nnz[j] - 1;
-    bool found = false;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int c = cj[mid];
-      if (c == i) {
-        found = __double_as_longlong(H.val[(size_t)j * H.M + mid]) == __double_as_longlong(v);
-        break;
+  for (int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += gridDim.x * kWavesPerBlock) {
+    const int n = H.nnz[i];
+    for (int s = lane; s < n; s += kWave) {
+      const int j = H.idx[(size_t)i * H.M + s];
+      const double v = H.val[(size_t)i * H.M + s];
+      const int32_t *cj = H.idx + (size_t)j * H.M;
+      int lo = 0, hi = H.nnz[j] - 1;
+      bool found = false;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int c = cj[mid];
+        if (c == i) {
+          found = __double_as_longlong(H.val[(size_t)j * H.M + mid]) == __double_as_longlong(v);
+          break;
+        }
+        if (c < i) lo = mid + 1;
+        else hi = mid - 1;
       }
-      if (c < i) lo = mid + 1;
-      else hi = mid - 1;
+      bad = bad || !found;
     }
-    bad = !found;
   }
-  if (bad) atomicOr(flag, 1);
+  if (__ballot(bad) && lane == 0) atomicOr(flag, 1);
 }
 
 // n words set to zero (a kernel rather than a memset node, so that a caller
@@ -951,7 +953,7 @@ template hipError_t launch_validate<float>(int, EllView<float>, int32_t *, hipSt
 
 hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, hipStream_t stream)
 {
-  hipLaunchKernelGGL(k_check_symmetric, dim3((N + 255) / 256), dim3(256), 0, stream, N, H, flag);
+  hipLaunchKernelGGL(k_check_symmetric, dim3(init_blocks(N)), dim3(256), 0, stream, N, H, flag);
   return hipGetLastError();
 }
 

@@ -538,19 +538,109 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
   }
 }
 
-// The SP2 iteration's product: each workgroup computes 64 rows, then reduces
-// them -- the five sums to one node of the perfect pairwise tree over all rows
-// (rows past N enter as -0.0, the exact additive identity), the widths to
-// maxima, the kept counts to totals -- into partials xb of nq = ceil(N / 64).
+// Loads and stores of the partials that the last workgroup of a launch reads:
+// coherent across the chip's L2 caches (agent scope), so that no release or
+// acquire fence -- which would write back or invalidate a whole L2 -- is needed.
+template <typename V>
+__device__ __forceinline__ V cld(const V *p)
+{
+  return __hip_atomic_load(const_cast<V *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ void cst(V *p, V v)
+{
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Perfect pairwise trees over the nq partials of sums c0 .. c0 + NS - 1, by
+// one workgroup of 256: thread t holds the leaves [t L, t L + L) of each (L
+// the smallest power of two with 256 L >= nq, nq <= 16384; leaves past nq are
+// -0.0), then the trees over the threads.  The leaves past nq are loaded too
+// (the partials are padded to 5 nq + 256 L), so that a thread's loads take
+// one address.  Subtrees of up to 8 leaves issue every load before the first
+// addition; larger ones sum their first half before loading the second, so
+// that at most 8 leaves are live.
+template <int L>
+__device__ __forceinline__ double ctree(const double *p, int a, int n)
+{
+  if constexpr (L == 1) {
+    const double x = cld(p + a);
+    return a < n ? x : -0.0;
+  } else if constexpr (L <= 8) {
+    const double lo = ctree<L / 2>(p, a, n);
+    return lo + ctree<L / 2>(p, a + L / 2, n);
+  } else {
+    double lo = ctree<L / 2>(p, a, n);
+    asm volatile("" : "+v"(lo)::"memory");
+    return lo + ctree<L / 2>(p, a + L / 2, n);
+  }
+}
+template <int L, int NS>
+__device__ __forceinline__ void leaves(const double *part, int nq, int t, double (&v)[NS])
+{
+  if constexpr (L <= 8) {
+#pragma unroll
+    for (int c = 0; c < NS; ++c) v[c] = ctree<L>(part + (size_t)c * nq, t * L, nq);
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < NS; ++c) v[c] = ctree<L>(part + (size_t)c * nq, t * L, nq);
+  }
+}
+template <int NS>
+__device__ __forceinline__ void thread_leaves(const double *part, int nq, int t, double (&v)[NS])
+{
+  if (nq <= 256) leaves<1>(part, nq, t, v);
+  else if (nq <= 512) leaves<2>(part, nq, t, v);
+  else if (nq <= 1024) leaves<4>(part, nq, t, v);
+  else if (nq <= 2048) leaves<8>(part, nq, t, v);
+  else if (nq <= 4096) leaves<16>(part, nq, t, v);
+  else if (nq <= 8192) leaves<32>(part, nq, t, v);
+  else leaves<64>(part, nq, t, v);
+}
+// the thread sums v into totals out[0 .. NS) (thread 0)
+template <int NS>
+__device__ __forceinline__ void tree_finish(double (&v)[NS], double *out)
+{
+  __shared__ double ws[NS][kWpb];
+  const int t = threadIdx.x, w = t >> 6, lane = lane_id();
+#pragma unroll
+  for (int c = 0; c < NS; ++c) v[c] = wave_tree(v[c]);
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NS; ++c) ws[c][w] = v[c];
+  __syncthreads();
+  if (t == 0)
+    for (int c = 0; c < NS; ++c) out[c] = (ws[c][0] + ws[c][1]) + (ws[c][2] + ws[c][3]);
+}
+
+// The SP2 iteration in one launch.  Each workgroup computes 64 rows, then
+// reduces them -- the five sums to one node of the perfect pairwise tree over
+// all rows (rows past N enter as -0.0, the exact additive identity), the
+// widths to maxima, the kept counts to totals -- into partials xb of
+// nq = ceil(N / 64), and takes a ticket once they are written; the workgroup
+// that takes the last ticket builds the upper levels of the trees, takes the
+// SP2 decision and returns the ticket counter to zero.  With `publish`
+// (mapped pinned host memory, or null) the state afterwards is also written
+// there -- or the unchanged state, when the solve had stopped before this
+// launch.
 template <typename T>
-__global__ __launch_bounds__(256) void k_x2_sym_part(int N, SpanRot3<T> spans, const SP2State *st, T tau,
-                                                     StepScratch s)
+__global__ __launch_bounds__(256) void k_x2_sym_step(int N, SpanRot3<T> spans, SP2State *st, T tau, StepScratch s,
+                                                     SP2Cfg cfg, SP2Hist h, SP2State *publish)
 {
   __shared__ double stk_s[kWpb][kR * kLev];
   __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   __shared__ RowOut ro;
-  if (st->stop) return;  // the same in every workgroup
+  __shared__ int last_s;
+  __shared__ int32_t wsi[3][kWpb];
+  __shared__ long long wsl[2][kWpb];
+  if (st->stop) {  // the same in every workgroup
+    if (publish && blockIdx.x == 0 && threadIdx.x == 0) {
+      *publish = *st;
+      __threadfence_system();
+    }
+    return;
+  }
   const int cur = st->cur;
   const bool up = st->up_next != 0;
   const int w = uni(threadIdx.x >> 6), lane = lane_id();
@@ -573,22 +663,61 @@ __global__ __launch_bounds__(256) void k_x2_sym_part(int N, SpanRot3<T> spans, c
     ro.lo[w * kR + lane] = 0;
   }
   __syncthreads();
-  if (w != 0) return;
   const int nq = s.nq;
-  const bool in = xb * (kWpb * kR) + lane < N;
-  double a[kSums];
+  if (w == 0) {
+    const bool in = xb * (kWpb * kR) + lane < N;
+    double a[kSums];
 #pragma unroll
-  for (int c = 0; c < kSums; ++c) a[c] = wave_tree(in ? ro.s[c][lane] : -0.0);
-  const int m0 = wmax(ro.wy[lane]), m1 = wmax(ro.wo[lane]), m2 = wmax(ro.lo[lane]);
-  const long long ny = wsum(ro.wy[lane]), no = wsum(ro.wo[lane]);
+    for (int c = 0; c < kSums; ++c) a[c] = wave_tree(in ? ro.s[c][lane] : -0.0);
+    const int m0 = wmax(ro.wy[lane]), m1 = wmax(ro.wo[lane]), m2 = wmax(ro.lo[lane]);
+    const long long ny = wsum(ro.wy[lane]), no = wsum(ro.wo[lane]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kSums; ++c) cst(s.part + c * nq + xb, a[c]);
+      cst(s.partw + xb, m0);
+      cst(s.partw + nq + xb, m1);
+      cst(s.partw + 2 * nq + xb, m2);
+      cst(s.partn + xb, (int64_t)ny);
+      cst(s.partn + nq + xb, (int64_t)no);
+      // the partials are complete at agent scope before the ticket is taken
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      last_s = __hip_atomic_fetch_add(s.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    }
+  }
+  __syncthreads();
+  if (!last_s) return;
+  // the last workgroup: every other workgroup's partials are complete
+  const int t = threadIdx.x;
+  double v[kSums];
+  thread_leaves(s.part, nq, t, v);
+  int32_t mx[3] = {0, 0, 0};
+  long long sy = 0, so = 0;
+  for (int b = t; b < nq; b += 256) {
+    for (int c = 0; c < 3; ++c) mx[c] = max(mx[c], cld(s.partw + c * nq + b));
+    sy += cld(s.partn + b);
+    so += cld(s.partn + nq + b);
+  }
+  for (int c = 0; c < 3; ++c) mx[c] = wmax(mx[c]);
+  sy = wsum(sy);
+  so = wsum(so);
   if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < kSums; ++c) s.part[c * nq + xb] = a[c];
-    s.partw[xb] = m0;
-    s.partw[nq + xb] = m1;
-    s.partw[2 * nq + xb] = m2;
-    s.partn[xb] = ny;
-    s.partn[nq + xb] = no;
+    for (int c = 0; c < 3; ++c) wsi[c][w] = mx[c];
+    wsl[0][w] = sy;
+    wsl[1][w] = so;
+  }
+  tree_finish(v, s.out);  // (its barrier also covers wsi, wsl)
+  if (t == 0) {
+    for (int c = 0; c < 3; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
+    s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
+    s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
+    SP2State x = *st;
+    sp2dev::decide_sym(&x, cfg, h, s);
+    *st = x;
+    cst(s.ticket, 0u);
+    if (publish) {
+      *publish = x;
+      __threadfence_system();
+    }
   }
 }
 
@@ -631,101 +760,6 @@ __global__ __launch_bounds__(64) void k_sym_seed_part(int N, SpanRot3<T> spans, 
   }
 }
 
-// Perfect pairwise trees over the nq partials of sums c0 .. c0 + NS - 1, by
-// one workgroup of 256: thread t holds the leaves [t L, t L + L) of each (L
-// the smallest power of two with 256 L >= nq, nq <= 16384), then the trees
-// over the threads.  Every load is issued before the first addition.
-template <int L, int NS>
-__device__ __forceinline__ void leaves(const double *part, int nq, int t, double (&v)[NS])
-{
-  if constexpr (L <= 8) {
-#pragma unroll
-    for (int c = 0; c < NS; ++c) v[c] = leaf_tree<L>(part + (size_t)c * nq, t * L, nq);
-  } else {
-#pragma unroll 1
-    for (int c = 0; c < NS; ++c) v[c] = leaf_tree_lean<L>(part + (size_t)c * nq, t * L, nq);
-  }
-}
-template <int NS>
-__device__ __forceinline__ void thread_leaves(const double *part, int nq, int t, double (&v)[NS])
-{
-  if (nq <= 256) leaves<1>(part, nq, t, v);
-  else if (nq <= 512) leaves<2>(part, nq, t, v);
-  else if (nq <= 1024) leaves<4>(part, nq, t, v);
-  else if (nq <= 2048) leaves<8>(part, nq, t, v);
-  else if (nq <= 4096) leaves<16>(part, nq, t, v);
-  else if (nq <= 8192) leaves<32>(part, nq, t, v);
-  else leaves<64>(part, nq, t, v);
-}
-// the thread sums v into totals out[0 .. NS) (thread 0)
-template <int NS>
-__device__ __forceinline__ void tree_finish(double (&v)[NS], double *out)
-{
-  __shared__ double ws[NS][kWpb];
-  const int t = threadIdx.x, w = t >> 6, lane = lane_id();
-#pragma unroll
-  for (int c = 0; c < NS; ++c) v[c] = wave_tree(v[c]);
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < NS; ++c) ws[c][w] = v[c];
-  __syncthreads();
-  if (t == 0)
-    for (int c = 0; c < NS; ++c) out[c] = (ws[c][0] + ws[c][1]) + (ws[c][2] + ws[c][3]);
-}
-
-// Upper levels of the step's trees, then the SP2 decision (one workgroup).
-// With `publish` (mapped pinned host memory, or null) the state afterwards
-// is also written there -- or the unchanged state, when the solve had stopped
-// before this launch.  The partials are loaded whatever the state says (they
-// are in bounds, and unused when the solve has stopped), so that every load is
-// in flight at once.
-__global__ __launch_bounds__(256) void k_sym_final(SP2State *st, SP2Cfg cfg, SP2Hist h, StepScratch s,
-                                                   SP2State *publish)
-{
-  __shared__ int32_t wsi[3][kWpb];
-  __shared__ long long wsl[2][kWpb];
-  const int t = threadIdx.x, w = t >> 6, lane = lane_id();
-  const int nq = s.nq;
-  double v[kSums];
-  thread_leaves(s.part, nq, t, v);
-  int32_t mx[3] = {0, 0, 0};
-  long long sy = 0, so = 0;
-  for (int b = t; b < nq; b += 256) {
-    for (int c = 0; c < 3; ++c) mx[c] = max(mx[c], s.partw[c * nq + b]);
-    sy += s.partn[b];
-    so += s.partn[nq + b];
-  }
-  SP2State x;
-  if (t == 0) x = *st;
-  if (st->stop) {
-    if (publish && t == 0) {
-      *publish = x;
-      __threadfence_system();
-    }
-    return;
-  }
-  for (int c = 0; c < 3; ++c) mx[c] = wmax(mx[c]);
-  sy = wsum(sy);
-  so = wsum(so);
-  if (lane == 0) {
-    for (int c = 0; c < 3; ++c) wsi[c][w] = mx[c];
-    wsl[0][w] = sy;
-    wsl[1][w] = so;
-  }
-  tree_finish(v, s.out);  // (its barrier also covers wsi, wsl)
-  if (t == 0) {
-    for (int c = 0; c < 3; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
-    s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
-    s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
-    sp2dev::decide_sym(&x, cfg, h, s);
-    *st = x;
-    if (publish) {
-      *publish = x;
-      __threadfence_system();
-    }
-  }
-}
-
 // The branch of the next product from the seed partials (Tr X, Tr X^2 of the
 // current X), by one workgroup.
 __global__ __launch_bounds__(256) void k_sym_seed_final(SP2State *st, SP2Cfg cfg, StepScratch s)
@@ -739,27 +773,20 @@ __global__ __launch_bounds__(256) void k_sym_seed_final(SP2State *st, SP2Cfg cfg
 }  // namespace
 
 template <typename T>
-hipError_t launch_x2_sym_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
-                              hipStream_t stream)
+hipError_t launch_x2_sym_step(int N, SpanRot3<T> spans, SP2State *st, T tau, const StepScratch &s,
+                              const SP2Cfg &cfg, const SP2Hist &h, SP2State *publish, hipStream_t stream)
 {
   const int groups = (N + kR - 1) / kR;
   const int blocks = (groups + kWpb - 1) / kWpb;
-  if (blocks != s.nq || s.nq > 16384) return hipErrorInvalidValue;  // partials sized for N rows
-  hipLaunchKernelGGL(k_x2_sym_part<T>, dim3(blocks), dim3(kWpb * kWave), 0, stream, N, spans, st, tau, s);
+  if (blocks != s.nq || s.nq > 16384 || !s.ticket) return hipErrorInvalidValue;  // partials sized for N rows
+  hipLaunchKernelGGL(k_x2_sym_step<T>, dim3(blocks), dim3(kWpb * kWave), 0, stream, N, spans, st, tau, s, cfg, h,
+                     publish);
   return hipGetLastError();
 }
-template hipError_t launch_x2_sym_part<double>(int, SpanRot3<double>, const SP2State *, double, const StepScratch &,
-                                               hipStream_t);
-template hipError_t launch_x2_sym_part<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
-                                              hipStream_t);
-
-hipError_t launch_sym_final(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s,
-                            SP2State *publish, hipStream_t stream)
-{
-  if (s.nq > 16384) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sym_final, dim3(1), dim3(kWpb * kWave), 0, stream, st, cfg, h, s, publish);
-  return hipGetLastError();
-}
+template hipError_t launch_x2_sym_step<double>(int, SpanRot3<double>, SP2State *, double, const StepScratch &,
+                                               const SP2Cfg &, const SP2Hist &, SP2State *, hipStream_t);
+template hipError_t launch_x2_sym_step<float>(int, SpanRot3<float>, SP2State *, float, const StepScratch &,
+                                              const SP2Cfg &, const SP2Hist &, SP2State *, hipStream_t);
 
 template <typename T>
 hipError_t launch_sym_seed(int N, SpanRot3<T> spans, SP2State *st, const SP2Cfg &cfg, const StepScratch &s,
