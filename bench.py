@@ -24,7 +24,8 @@ X, Tr X and Tr(XH)); the batched workload (256 instances of uneven size in one
 call, against solving them one by one); the dense-block variant at N = 8192
 (BF16x3 against FP64 MFMA products); the paper's model Hamiltonians (one X^2
 of H for metals, semiconductors and soft matter, SP2 on the two gapped
-systems); and the oracle on the host cores as cpu_baseline.
+systems); and the oracle on the host cores as cpu_baseline (OpenMP rows on the
+host share of cores, with the host's STREAM triad bandwidth beside it).
 """
 from __future__ import annotations
 
@@ -48,52 +49,130 @@ TAU_MIXED64, TAU_FP32, SWITCH_ETA = 1e-9, 1e-7, 1e-2
 METRIC = "ELLPACK X² GB/s (%HBM peak) + SP2 solve ms to ‖X²−X‖_F<1e-6, FP64 vs mixed"
 
 
-def cpu_baseline(nnz, idx, val, M, seconds_budget=20.0):
-    """The oracle's X^2 on the same workload, single-threaded on the host:
-    X0 and the first oracle iterates, one X^2 each, until the budget is used."""
+def host_cpu():
+    """The host's processor as lscpu reports it (model, sockets, cores, NUMA
+    nodes), and the CPUs this process may run on."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "threads_per_core": info.get("Thread(s) per core"),
+            "numa_nodes": info.get("NUMA node(s)"), "cpus_usable": len(os.sched_getaffinity(0))}
+
+
+def cpu_threads():
+    """Threads of the CPU baseline: the CPUs this process may use, capped by
+    OMP_NUM_THREADS when that is set (the host share of one GPU)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def cpu_baseline_child(seconds_budget):
+    """The CPU-baseline measurement, run in a process of its own whose OpenMP
+    threads are bound as the paper binds them (OMP_PROC_BIND=spread,
+    OMP_PLACES=cores), with every output row first touched by the thread that
+    fills it: a STREAM triad for the host's memory bandwidth, then the
+    oracle's X^2 on the workload's X0 and following oracle SP2 iterates on all
+    threads until the budget is used, and two of those products on one
+    thread."""
     import numpy as np
 
     import oracle
+    from paper_2102_08505_amd import synth
+
+    threads = oracle.threads(cpu_threads())
+    triad = oracle.stream_triad(1 << 27, 10)
+    nnz, idx, val, M = synth.banded_hamiltonian(N, B)
     H = oracle.Ell(N, M, nnz, idx, val)
     rc, lo, hi = oracle.gershgorin(H)
     rc, X, w = oracle.x0(H, lo, hi, TAU, Mo=M + 1)
-    total_bytes, total_s, calls = 0, 0.0, 0
+    # X0 copied into rows first touched in the row schedule
+    nz, ix, vl = oracle.empty_rows(N, X.M, X.val.dtype)
+    nz[:], ix[:], vl[:] = X.nnz, X.idx, X.val
+    X = oracle.Ell(N, X.M, nz, ix, vl)
+    iterates, times, total_bytes, total_s = [], [], 0, 0.0
     t_start = time.perf_counter()
-    while time.perf_counter() - t_start < seconds_budget and calls < 40:
+    while time.perf_counter() - t_start < seconds_budget and len(iterates) < 40:
+        iterates.append(X)
         t0 = time.perf_counter()
         rc, Y, d1, d2, wy = oracle.x2(X, TAU, M2=512)
         dt = time.perf_counter() - t0
+        times.append(dt)
         nx, ny = int(X.nnz.sum()), int(Y.nnz.sum())
         total_bytes += nx * 12 + 4 * N + ny * 12 + 4 * N
         total_s += dt
-        calls += 1
         up = abs(2 * oracle.pairwise(d1) - oracle.pairwise(d2) - N / 4) < abs(oracle.pairwise(d2) - N / 4)
         if up:
             rc, X, w = oracle.update(X, Y, TAU, Mo=512)
         else:
             X = Y
-    return {"value": total_bytes / total_s / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle X^2 (single thread) on X0 and the next {calls - 1} oracle SP2 iterates of the "
-                      f"same N={N} b={B} tau={TAU:g} workload, {calls} calls, {total_s:.1f} s"}
+    oracle.threads(1)
+    one_bytes, one_s = 0, 0.0
+    for Xi in iterates[:2]:
+        t0 = time.perf_counter()
+        rc, Y, d1, d2, wy = oracle.x2(Xi, TAU, M2=512)
+        one_s += time.perf_counter() - t0
+        one_bytes += int(Xi.nnz.sum()) * 12 + int(Y.nnz.sum()) * 12 + 8 * N
+    value = total_bytes / total_s / 1e9
+    return {"value": value, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle X^2 (OpenMP rows, {threads} threads, OMP_PROC_BIND=spread OMP_PLACES=cores, "
+                      f"first-touch rows) on X0 and the next {len(iterates) - 1} oracle SP2 iterates of the same "
+                      f"N={N} b={B} tau={TAU:g} workload, {len(iterates)} calls, {total_s:.1f} s",
+            "single_thread": {"value": one_bytes / one_s / 1e9, "unit": "GB/s",
+                              "sample": f"the first {min(2, len(iterates))} of those products on one thread",
+                              "speedup_of_threads": one_s / sum(times[:2])},
+            "stream_triad_GBs": triad, "frac_of_triad": value / triad if triad > 0 else None,
+            "host": host_cpu()}
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """Runs cpu_baseline_child in a child process (its OpenMP binding is set
+    before the runtime starts and it never touches the GPU)."""
+    import subprocess
+    env = dict(os.environ, OMP_PROC_BIND="spread", OMP_PLACES="cores", OMP_NUM_THREADS=str(cpu_threads()))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+                        "--cpu-seconds", str(seconds_budget)], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("CPU baseline failed:\n" + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "x2_sym_f64_n32768_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2102_08505_amd", "csrc", "ell_sym16.hip")
 
 
+def code_sha256(path):
+    """SHA-256 of a C++ source with its // comments, trailing blanks and empty
+    lines removed: it changes with the code, not with its comments."""
+    import hashlib
+    import re
+    with open(path, encoding="utf-8") as f:
+        lines = [re.sub(r"\s*//.*$", "", ln).rstrip() for ln in f]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs, scaled by the copy-kernel calibration; None
-    when the kernel source has changed since the counters were taken."""
-    import hashlib
+    runs (L2-to-memory requests split by size, checked against a plain copy);
+    None when the kernel's code has changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = code_sha256(KERNEL_SOURCE)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    if rec.get("kernel_code_sha256") != sha:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -385,7 +464,13 @@ def main():
                          "for profiling the step kernel at a size beyond the last-level cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for scaling the HBM counters)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only the CPU baseline (host cores, no GPU): one JSON object")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="time budget of the CPU baseline's X^2 calls")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_child(args.cpu_seconds)))
+        return
     if args.profile_size and not args.main_only:
         print("--profile-size goes with --main-only", file=sys.stderr)
         sys.exit(2)
@@ -506,7 +591,7 @@ def main():
     if not args.no_model:
         line["model_hamiltonians"] = model_leg(E, synth, torch)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(nnz, idx, val, M)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

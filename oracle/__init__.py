@@ -31,12 +31,12 @@ DENSE_F64, DENSE_BF16X3 = 0, 1
 
 
 def build(force=True):
-    """Compile liboracle.so with gcc (plain C11, no FP contraction, optional OpenMP off)."""
+    """Compile liboracle.so with gcc (plain C11, no FP contraction, OpenMP row loops)."""
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-o", tmp, _SRC, "-lm"]
+    cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-o", tmp, _SRC, os.path.join(_HERE, "host_stream.c"), "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     os.replace(tmp, _LIB)
     return _LIB
@@ -75,6 +75,12 @@ def lib():
         L.orc_check_ell.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
         L.orc_x2_fma_count.restype = C.c_int64
         L.orc_x2_fma_count.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
+        L.orc_threads.restype = C.c_int32
+        L.orc_threads.argtypes = [C.c_int32]
+        L.orc_rows_init.restype = None
+        L.orc_rows_init.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_void_p, C.c_int32]
+        L.orc_stream_triad.restype = C.c_double
+        L.orc_stream_triad.argtypes = [C.c_int64, C.c_int32]
         L.orc_x2_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_double, C.c_int32,
                                  i32p, i32p, f64p, f64p, f64p, i32p]
         L.orc_x2_f32.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f32p, C.c_float, C.c_int32,
@@ -169,24 +175,41 @@ def fma_count(A):
     return int(lib().orc_x2_fma_count(A.N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p)))
 
 
+def threads(n=0):
+    """Sets the oracle's OpenMP thread count when n > 0; returns the count in use."""
+    return int(lib().orc_threads(int(n)))
+
+
+def stream_triad(n, reps=10):
+    """Host memory bandwidth (GB/s), best of `reps` STREAM triads over n doubles."""
+    return float(lib().orc_stream_triad(int(n), int(reps)))
+
+
+def empty_rows(N, M, dtype):
+    """(nnz, idx, val) of an N x M ELLPACK matrix with nothing stored, first
+    touched row by row in the oracle's static row schedule."""
+    nnz = np.empty(N, np.int32)
+    idx = np.empty(N * M, np.int32)
+    val = np.empty(N * M, dtype)
+    lib().orc_rows_init(N, M, _p(nnz, i32p), _p(idx, i32p), val.ctypes.data, val.itemsize)
+    return nnz, idx, val
+
+
 def x2(A, tau, M2=None):
     """Returns (status, X2 Ell, d1, d2, maxw).  FP64 or FP32 by A's value dtype."""
     L = lib()
     N = A.N
     if M2 is None:
         M2 = N
-    nnz2 = np.zeros(N, np.int32)
-    idx2 = np.full(N * M2, -1, np.int32)
+    nnz2, idx2, val2 = empty_rows(N, M2, A.val.dtype)
     d1 = np.zeros(N)
     d2 = np.zeros(N)
     w = C.c_int32(0)
     if A.val.dtype == np.float32:
-        val2 = np.zeros(N * M2, np.float32)
         rc = L.orc_x2_f32(N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p), _p(A.val, f32p), C.c_float(tau),
                           M2, _p(nnz2, i32p), _p(idx2, i32p), _p(val2, f32p), _p(d1, f64p),
                           _p(d2, f64p), C.byref(w))
     else:
-        val2 = np.zeros(N * M2, np.float64)
         rc = L.orc_x2_f64(N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p), _p(A.val, f64p), float(tau), M2,
                           _p(nnz2, i32p), _p(idx2, i32p), _p(val2, f64p), _p(d1, f64p),
                           _p(d2, f64p), C.byref(w))
@@ -222,17 +245,14 @@ def update(X, Y, tau, Mo=None):
     N = X.N
     if Mo is None:
         Mo = N
-    nnzo = np.zeros(N, np.int32)
-    idxo = np.full(N * Mo, -1, np.int32)
+    nnzo, idxo, valo = empty_rows(N, Mo, X.val.dtype)
     w = C.c_int32(0)
     L = lib()
     if X.val.dtype == np.float32:
-        valo = np.zeros(N * Mo, np.float32)
         rc = L.orc_update_f32(N, X.M, _p(X.nnz, i32p), _p(X.idx, i32p), _p(X.val, f32p), Y.M,
                               _p(Y.nnz, i32p), _p(Y.idx, i32p), _p(Y.val, f32p), C.c_float(tau), Mo,
                               _p(nnzo, i32p), _p(idxo, i32p), _p(valo, f32p), C.byref(w))
     else:
-        valo = np.zeros(N * Mo, np.float64)
         rc = L.orc_update_f64(N, X.M, _p(X.nnz, i32p), _p(X.idx, i32p), _p(X.val, f64p), Y.M,
                               _p(Y.nnz, i32p), _p(Y.idx, i32p), _p(Y.val, f64p), float(tau), Mo,
                               _p(nnzo, i32p), _p(idxo, i32p), _p(valo, f64p), C.byref(w))

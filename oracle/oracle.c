@@ -1,16 +1,45 @@
 /*
  * CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Build: gcc -std=c11 -O2 -ffp-contract=off -fPIC -shared oracle.c -lm
+ * Build: gcc -std=c11 -O2 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -lm
  * (-ffp-contract=off: every multiply-add below is exactly the fma() call or
  * the separate multiply and add that is written, nothing is fused behind the
- * reader's back).
+ * reader's back).  The row loops of X^2 and of the update run on OpenMP
+ * threads: each output row depends only on the inputs, so the result does not
+ * depend on the thread count.
  */
 #include "oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int32_t orc_threads(int32_t n)
+{
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+/* Empty rows (nnz 0, indices -1, values 0), written row by row in the static
+ * schedule of the row loops below: with threads bound to cores, the pages of
+ * a row land on the memory node of the thread that will fill it. */
+void orc_rows_init(int32_t N, int32_t M, int32_t *nnz, int32_t *idx, void *val, int32_t val_size)
+{
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < N; ++i) {
+    nnz[i] = 0;
+    for (int32_t s = 0; s < M; ++s) idx[(int64_t)i * M + s] = -1;
+    memset((char *)val + (int64_t)i * M * val_size, 0, (size_t)M * (size_t)val_size);
+  }
+}
 
 /* ------------------------------------------------------------------------ */
 /* pairwise tree sum (the fixed summation order of every trace and norm)     */
@@ -80,102 +109,118 @@ int orc_x2_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, con
                double tau, int32_t M2, int32_t *nnz2, int32_t *idx2, double *val2,
                double *d1, double *d2, int32_t *maxw)
 {
-  double *acc = (double *)calloc((size_t)N, sizeof(double));
-  char *mark = (char *)calloc((size_t)N, 1);
-  int32_t *touched = (int32_t *)malloc((size_t)N * sizeof(int32_t));
-  if (!acc || !mark || !touched) { free(acc); free(mark); free(touched); return ORC_ENOMEM; }
-  int status = ORC_OK;
+  int failed = 0, overflow = 0;
   int32_t widest = 0;
-  for (int32_t i = 0; i < N; ++i) {
-    const int32_t *ci = idx + (int64_t)i * M;
-    const double *vi = val + (int64_t)i * M;
-    int32_t nt = 0;
-    double xii = 0.0;
-    for (int32_t s = 0; s < nnz[i]; ++s) {
-      int32_t k = ci[s];
-      double a = vi[s];
-      if (k == i) xii = a;
-      const int32_t *ck = idx + (int64_t)k * M;
-      const double *vk = val + (int64_t)k * M;
-      for (int32_t t = 0; t < nnz[k]; ++t) {
-        int32_t j = ck[t];
-        if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
-        acc[j] = fma(a, vk[t], acc[j]);
-      }
-    }
-    if (d1) d1[i] = xii;
-    if (d2) d2[i] = acc[i];
-    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
-    int32_t c = 0;
-    for (int32_t q = 0; q < nt; ++q) {
-      int32_t j = touched[q];
-      if (fabs(acc[j]) > tau) {
-        if (c < M2) {
-          idx2[(int64_t)i * M2 + c] = j;
-          val2[(int64_t)i * M2 + c] = acc[j];
+#pragma omp parallel reduction(| : failed, overflow) reduction(max : widest)
+  {
+    /* the dense accumulator of one row, its marks and touched columns */
+    double *acc = (double *)calloc((size_t)N, sizeof(double));
+    char *mark = (char *)calloc((size_t)N, 1);
+    int32_t *touched = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    const int ok = acc && mark && touched;
+    if (!ok) failed = 1;
+#pragma omp for schedule(static)
+    for (int32_t i = 0; i < N; ++i) {
+      if (!ok) continue;
+      const int32_t *ci = idx + (int64_t)i * M;
+      const double *vi = val + (int64_t)i * M;
+      int32_t nt = 0;
+      double xii = 0.0;
+      for (int32_t s = 0; s < nnz[i]; ++s) {
+        int32_t k = ci[s];
+        double a = vi[s];
+        if (k == i) xii = a;
+        const int32_t *ck = idx + (int64_t)k * M;
+        const double *vk = val + (int64_t)k * M;
+        for (int32_t t = 0; t < nnz[k]; ++t) {
+          int32_t j = ck[t];
+          if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
+          acc[j] = fma(a, vk[t], acc[j]);
         }
-        ++c;
       }
-      acc[j] = 0.0;
-      mark[j] = 0;
+      if (d1) d1[i] = (double)xii;
+      if (d2) d2[i] = (double)acc[i];
+      qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+      int32_t c = 0;
+      for (int32_t q = 0; q < nt; ++q) {
+        int32_t j = touched[q];
+        if (fabs(acc[j]) > tau) {
+          if (c < M2) {
+            idx2[(int64_t)i * M2 + c] = j;
+            val2[(int64_t)i * M2 + c] = acc[j];
+          }
+          ++c;
+        }
+        acc[j] = 0.0;
+        mark[j] = 0;
+      }
+      if (c > M2) { overflow = 1; nnz2[i] = M2; } else nnz2[i] = c;
+      if (c > widest) widest = c;
     }
-    if (c > M2) { status = ORC_EOVERFLOW; nnz2[i] = M2; } else nnz2[i] = c;
-    if (c > widest) widest = c;
+    free(acc); free(mark); free(touched);
   }
+  if (failed) return ORC_ENOMEM;
   if (maxw) *maxw = widest;
-  free(acc); free(mark); free(touched);
-  return status;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 
 int orc_x2_f32(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const float *val,
                float tau, int32_t M2, int32_t *nnz2, int32_t *idx2, float *val2,
                double *d1, double *d2, int32_t *maxw)
 {
-  float *acc = (float *)calloc((size_t)N, sizeof(float));
-  char *mark = (char *)calloc((size_t)N, 1);
-  int32_t *touched = (int32_t *)malloc((size_t)N * sizeof(int32_t));
-  if (!acc || !mark || !touched) { free(acc); free(mark); free(touched); return ORC_ENOMEM; }
-  int status = ORC_OK;
+  int failed = 0, overflow = 0;
   int32_t widest = 0;
-  for (int32_t i = 0; i < N; ++i) {
-    const int32_t *ci = idx + (int64_t)i * M;
-    const float *vi = val + (int64_t)i * M;
-    int32_t nt = 0;
-    float xii = 0.0f;
-    for (int32_t s = 0; s < nnz[i]; ++s) {
-      int32_t k = ci[s];
-      float a = vi[s];
-      if (k == i) xii = a;
-      const int32_t *ck = idx + (int64_t)k * M;
-      const float *vk = val + (int64_t)k * M;
-      for (int32_t t = 0; t < nnz[k]; ++t) {
-        int32_t j = ck[t];
-        if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
-        acc[j] = fmaf(a, vk[t], acc[j]);
-      }
-    }
-    if (d1) d1[i] = (double)xii;
-    if (d2) d2[i] = (double)acc[i];
-    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
-    int32_t c = 0;
-    for (int32_t q = 0; q < nt; ++q) {
-      int32_t j = touched[q];
-      if (fabsf(acc[j]) > tau) {
-        if (c < M2) {
-          idx2[(int64_t)i * M2 + c] = j;
-          val2[(int64_t)i * M2 + c] = acc[j];
+#pragma omp parallel reduction(| : failed, overflow) reduction(max : widest)
+  {
+    /* the dense accumulator of one row, its marks and touched columns */
+    float *acc = (float *)calloc((size_t)N, sizeof(float));
+    char *mark = (char *)calloc((size_t)N, 1);
+    int32_t *touched = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    const int ok = acc && mark && touched;
+    if (!ok) failed = 1;
+#pragma omp for schedule(static)
+    for (int32_t i = 0; i < N; ++i) {
+      if (!ok) continue;
+      const int32_t *ci = idx + (int64_t)i * M;
+      const float *vi = val + (int64_t)i * M;
+      int32_t nt = 0;
+      float xii = 0.0f;
+      for (int32_t s = 0; s < nnz[i]; ++s) {
+        int32_t k = ci[s];
+        float a = vi[s];
+        if (k == i) xii = a;
+        const int32_t *ck = idx + (int64_t)k * M;
+        const float *vk = val + (int64_t)k * M;
+        for (int32_t t = 0; t < nnz[k]; ++t) {
+          int32_t j = ck[t];
+          if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
+          acc[j] = fmaf(a, vk[t], acc[j]);
         }
-        ++c;
       }
-      acc[j] = 0.0f;
-      mark[j] = 0;
+      if (d1) d1[i] = (double)xii;
+      if (d2) d2[i] = (double)acc[i];
+      qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+      int32_t c = 0;
+      for (int32_t q = 0; q < nt; ++q) {
+        int32_t j = touched[q];
+        if (fabsf(acc[j]) > tau) {
+          if (c < M2) {
+            idx2[(int64_t)i * M2 + c] = j;
+            val2[(int64_t)i * M2 + c] = acc[j];
+          }
+          ++c;
+        }
+        acc[j] = 0.0f;
+        mark[j] = 0;
+      }
+      if (c > M2) { overflow = 1; nnz2[i] = M2; } else nnz2[i] = c;
+      if (c > widest) widest = c;
     }
-    if (c > M2) { status = ORC_EOVERFLOW; nnz2[i] = M2; } else nnz2[i] = c;
-    if (c > widest) widest = c;
+    free(acc); free(mark); free(touched);
   }
+  if (failed) return ORC_ENOMEM;
   if (maxw) *maxw = widest;
-  free(acc); free(mark); free(touched);
-  return status;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -321,8 +366,9 @@ int orc_update_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
                    int32_t M2, const int32_t *nnz2, const int32_t *idx2, const double *val2, double tau,
                    int32_t Mo, int32_t *nnzo, int32_t *idxo, double *valo, int32_t *maxw)
 {
-  int status = ORC_OK;
+  int overflow = 0;
   int32_t widest = 0;
+#pragma omp parallel for schedule(static) reduction(| : overflow) reduction(max : widest)
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const double *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
@@ -340,19 +386,20 @@ int orc_update_f64(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
         ++c;
       }
     }
-    if (c > Mo) { status = ORC_EOVERFLOW; nnzo[i] = Mo; } else nnzo[i] = c;
+    if (c > Mo) { overflow = 1; nnzo[i] = Mo; } else nnzo[i] = c;
     if (c > widest) widest = c;
   }
   if (maxw) *maxw = widest;
-  return status;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 
 int orc_update_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *idxX, const float *valX,
                    int32_t M2, const int32_t *nnz2, const int32_t *idx2, const float *val2, float tau,
                    int32_t Mo, int32_t *nnzo, int32_t *idxo, float *valo, int32_t *maxw)
 {
-  int status = ORC_OK;
+  int overflow = 0;
   int32_t widest = 0;
+#pragma omp parallel for schedule(static) reduction(| : overflow) reduction(max : widest)
   for (int32_t i = 0; i < N; ++i) {
     const int32_t *cx = idxX + (int64_t)i * MX, *cy = idx2 + (int64_t)i * M2;
     const float *vx = valX + (int64_t)i * MX, *vy = val2 + (int64_t)i * M2;
@@ -370,11 +417,11 @@ int orc_update_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
         ++c;
       }
     }
-    if (c > Mo) { status = ORC_EOVERFLOW; nnzo[i] = Mo; } else nnzo[i] = c;
+    if (c > Mo) { overflow = 1; nnzo[i] = Mo; } else nnzo[i] = c;
     if (c > widest) widest = c;
   }
   if (maxw) *maxw = widest;
-  return status;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

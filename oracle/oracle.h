@@ -5,8 +5,10 @@
  * benchmark's CPU-baseline leg may load or call this code.  The GPU library
  * shares no code, header, table or helper with it.
  *
- * Plain single-threaded C11, every step written in the order the definition
- * states it; no blocking, fusion or reordering.  Matrices are row-major
+ * Plain C11, every step written in the order the definition states it; no
+ * blocking, fusion or reordering.  The row loops of X^2 and of the update
+ * are shared out over OpenMP threads, row by row: a row's result depends on
+ * the inputs alone, so it is the same for any thread count.  Matrices are row-major
  * ELLPACK (the field set of the paper's ELLPACK listings, section "NUMA Aware
  * Data": N, M, nnz[N], index[N*M], value[N*M]); row i occupies slots
  * i*M .. i*M + nnz[i] - 1 with strictly ascending columns.
@@ -56,6 +58,21 @@ int orc_check_finite_f64(int32_t N, int32_t M, const int32_t *nnz, const double 
 
 /* Number of scalar FMAs of X.X: sum over rows i, over k in row i, of nnz[k]. */
 int64_t orc_x2_fma_count(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx);
+
+/* Sets the OpenMP thread count when n > 0; returns the count in use. */
+int32_t orc_threads(int32_t n);
+
+/* Fills rows of an N x M ELLPACK matrix with nothing stored (nnz 0, index -1,
+ * value 0; val_size bytes per value) in the row loops' static schedule, so
+ * that first touch places each row's pages with the thread that writes it. */
+void orc_rows_init(int32_t N, int32_t M, int32_t *nnz, int32_t *idx, void *val, int32_t val_size);
+
+/* Host memory bandwidth in GB/s: the best of `reps` runs of the STREAM triad
+ * a = b + s c over arrays of n doubles (24 bytes per element counted), on the
+ * OpenMP threads, arrays first touched in the same static schedule.  Returns
+ * a negative value when the arrays cannot be allocated.  (host_stream.c; not
+ * part of the oracle's arithmetic: it sizes the CPU baseline.) */
+double orc_stream_triad(int64_t n, int32_t reps);
 
 /* X2 = prune(X.X, tau).  d1, d2 (length N, may be NULL) receive X_ii and the
  * unpruned (X.X)_ii.  *maxw receives the largest surviving row width (also on

@@ -1,9 +1,10 @@
-// The SP2 iteration's product on the matrix cores for a bitwise symmetric
-// span-form X, with the iteration's branch fixed before the product: one
-// launch squares X (FP64 or FP32), writes only the iterate the branch selects
-// (the pruned X^2, or the pruned 2X - X^2), and leaves per 64-row workgroup
-// the nodes of the pairwise trees of Tr X, the unpruned Tr X^2, the norm
-// ||X^2 - X||_F^2, and Tr X' and Tr X'^2 of the iterate X' it wrote: the
+// The SP2 iteration on the matrix cores for a bitwise symmetric span-form X,
+// with the iteration's branch fixed before the product: one launch squares X
+// (FP64 or FP32), writes only the iterate the branch selects (the pruned X^2,
+// or the pruned 2X - X^2), reduces per 64-row workgroup the nodes of the
+// pairwise trees of Tr X, the unpruned Tr X^2, the norm ||X^2 - X||_F^2, and
+// Tr X' and Tr X'^2 of the iterate X' it wrote, and the workgroup that
+// finishes last completes the trees and takes the decision: the
 // "SP2 Loop X2", "SP2 Loop Norm" and "SP2 Loop Misc" steps of the paper's
 // section "Performance Evaluation using an ExaSP2 Application", on the
 // ELLPACK matrix-matrix multiply of its section "Performance Evaluation using

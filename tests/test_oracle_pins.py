@@ -107,6 +107,41 @@ def test_x2_bit_exact_against_dense_brute_force(sym, f32):
     assert np.array_equal(d1, np.diag(D).astype(np.float64))
 
 
+@pytest.mark.parametrize("f32", [False, True])
+def test_row_loops_do_not_depend_on_thread_count(f32):
+    """X^2 and the update share their rows out over OpenMP threads; every
+    output (rows, traces, widths, status -- overflow included) is the same
+    bits on one thread and on several."""
+    rng = np.random.default_rng(31 + f32)
+    dt = np.float32 if f32 else np.float64
+    D, A = random_sparse(301, 0.04, rng, symmetric=True, dtype=dt, extra=[("full", 17), ("empty", 3)])
+    before = oracle.threads()
+    try:
+        runs = []
+        for th in (1, 5):
+            oracle.threads(th)
+            assert oracle.threads() == th
+            out = []
+            for M2 in (None, 40):  # 40: row 17 overflows
+                rc, Y, d1, d2, w = oracle.x2(A, 0.01, M2=M2)
+                rcu, Z, wu = oracle.update(A, Y, 0.01, Mo=M2)
+                out.append((rc, Y, d1, d2, w, rcu, Z, wu))
+            runs.append(out)
+    finally:
+        oracle.threads(before)
+    assert runs[0][1][0] == oracle.EOVERFLOW and runs[0][1][5] == oracle.EOVERFLOW
+    for (a, b) in zip(*runs):
+        assert a[0] == b[0] and a[4] == b[4] and a[5] == b[5] and a[7] == b[7]
+        for Ea, Eb in ((a[1], b[1]), (a[6], b[6])):
+            assert np.array_equal(Ea.nnz, Eb.nnz) and np.array_equal(Ea.idx, Eb.idx)
+            assert np.array_equal(Ea.val.view(np.uint8), Eb.val.view(np.uint8))
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_stream_triad_reports_a_bandwidth():
+    assert oracle.stream_triad(1 << 20, 2) > 0
+
+
 def test_x2_tau_zero_keeps_every_nonzero_and_drops_exact_zeros():
     # X with an exact cancellation: row 0 = [1, 1], row 1 = [1, -1] -> (X^2)[0,1] = 1 - 1 = 0
     D = np.array([[1.0, 1.0], [1.0, -1.0]])
