@@ -358,6 +358,76 @@ def fp64_target_leg(E, H, torch, tau=1e-10, target=1e-8, reps=3):
             "alu_last_product": last_product_alu(D, prof)}
 
 
+def prune_mode_leg(E, synth, torch, H, reps=5, n_small=4096):
+    """One pruning per iteration against two (sp2_params.prune_once), FP64, to
+    ||X^2 - X||_F < 1e-6 on the benchmark H: two prunings at tau = 1e-8 (the
+    headline solve), one pruning at tau = 1e-8 and at 1e-9 (its norm includes
+    the pruned tail of X^2, so at 1e-8 it stalls above the target and the stall
+    rule stops it) -- time, iterations, eta, the step kernel's per-launch time,
+    and how far each density matrix and energy Tr(DH) ends from the headline
+    solve's; then, at N = 4096 with the same recipe, each configuration's
+    distance to the exact projector onto the N/4 lowest eigenvectors of H
+    (FP64 eigendecomposition on the GPU)."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    def csr(D):
+        N_, M_, dn, di, dv = D.download()
+        rows = np.repeat(np.arange(N_), dn)
+        keep = (np.arange(M_)[None, :] < dn[:, None]).reshape(-1)
+        return sp.csr_matrix((dv[keep], (rows, di[keep])), shape=(N_, N_))
+
+    configs = (("two_prunings_tau1e-8", 0, 1e-8), ("one_pruning_tau1e-8", 1, 1e-8),
+               ("one_pruning_tau1e-9", 1, 1e-9))
+    out = {"workload": f"FP64 SP2 of the benchmark H (N={N}, half-bandwidth {B}) to ||X^2-X||_F<{TARGET:g} "
+                       f"with two prunings per iteration and with one; distance to the exact projector at "
+                       f"N={n_small}"}
+    mats, energy = {}, {}
+    for name, once, tau in configs:
+        D = E.DeviceEll(N, M_CAP)
+        p = E.sp2_params(N / 4, tau, TARGET, max_iter=200, prune_once=once)
+        E.sp2_solve(H.h, D.h, p, history=False)  # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, rep = E.sp2_solve(H.h, D.h, p, history=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        p.profile = 1
+        _, prof = E.sp2_solve(H.h, D.h, p, history=False)
+        out[name] = {"status": int(rc), "solve_ms": float(np.median(times)) * 1e3,
+                     "solve_ms_device": rep["seconds"] * 1e3, "iterations": rep["iterations"], "eta": rep["eta"],
+                     "x2_us_per_launch": prof["x2_seconds"] / prof["x2_launches"] * 1e6}
+        mats[name] = csr(D)
+        rc_e, energy[name] = E.ellpack_trace_product(D.h, H.h)
+        if rc_e != E.ELL_OK:
+            raise RuntimeError(E.ellpack_strerror(rc_e))
+    ref = configs[0][0]
+    for name, _, _ in configs[1:]:
+        dX = mats[name] - mats[ref]
+        out[name]["fro_dD_vs_two_prunings"] = float(np.sqrt(dX.multiply(dX).sum()))
+        out[name]["abs_dTrDH_vs_two_prunings"] = float(abs(energy[name] - energy[ref]))
+    # the exact projector at a size an eigendecomposition takes in a moment
+    nnz, idx, val, m = synth.banded_hamiltonian(n_small, B, seed=0)
+    Hs = E.DeviceEll.from_host(n_small, m, nnz, idx, val)
+    Hd = np.zeros((n_small, n_small))
+    for i in range(n_small):
+        Hd[i, idx[i * m:i * m + nnz[i]]] = val[i * m:i * m + nnz[i]]
+    w, V = torch.linalg.eigh(torch.from_numpy(Hd).cuda())
+    Vo = V[:, :n_small // 4]
+    P = (Vo @ Vo.T).cpu().numpy()
+    small = {"N": n_small, "gap_at_fermi": float(w[n_small // 4] - w[n_small // 4 - 1])}
+    for name, once, tau in configs:
+        D = E.DeviceEll(n_small, M_CAP)
+        rc, rep = E.sp2_solve(Hs.h, D.h, E.sp2_params(n_small / 4, tau, TARGET, max_iter=200, prune_once=once),
+                              history=False)
+        small[name] = {"status": int(rc), "iterations": rep["iterations"], "eta": rep["eta"],
+                       "fro_D_minus_P": float(np.linalg.norm(csr(D).toarray() - P))}
+    out["vs_projector"] = small
+    return out
+
+
 def model_leg(E, synth, torch, reps=5):
     """The paper's model Hamiltonians (metals, semiconductors, soft matter,
     section "On the Generation of Model Hamiltonian System Matrices"): one FP64
@@ -467,6 +537,8 @@ def main():
     ap.add_argument("--no-model", action="store_true", help="skip the paper's model Hamiltonians")
     ap.add_argument("--no-fp64-target", action="store_true",
                     help="skip the FP64 solve to ||X^2-X||_F < 1e-8 (tau = 1e-10)")
+    ap.add_argument("--no-prune-mode", action="store_true",
+                    help="skip the comparison of one and two prunings per iteration")
     ap.add_argument("--main-only", action="store_true",
                     help="only the FP64 solves of the headline line (for profiling the step kernel)")
     ap.add_argument("--profile-size", type=int, default=0,
@@ -487,6 +559,7 @@ def main():
     if args.main_only:
         args.no_cpu = args.no_mixed = args.no_batched = args.no_dense = True
         args.no_accuracy = args.no_x2_single = args.no_model = args.no_fp64_target = True
+        args.no_prune_mode = True
     if args.copy_calibration:
         copy_calibration()
         return
@@ -590,6 +663,8 @@ def main():
     }
     if not args.no_fp64_target:
         line["fp64_to_1e-8"] = fp64_target_leg(E, H, torch)
+    if not args.no_prune_mode:
+        line["prune_modes"] = prune_mode_leg(E, synth, torch, H)
     if not args.no_x2_single:
         line["x2_single_tau1e-5"] = x2_single_leg(E, H)
     if not args.no_batched:

@@ -178,6 +178,13 @@ typedef struct {
   int32_t stall_stop;      /* nonzero: once eta < 1e-2, stop (ENOCONV) when the best eta of
                               the last two steps is no better than that of the two before */
   int32_t profile;         /* nonzero: time every X^2 step kernel with hipEvents (report x2_*) */
+  int32_t prune_once;      /* 0: two prunings per iteration -- X^2 is pruned, and 2X - X^2 and the
+                              norm ||X^2 - X||_F are formed from the pruned X^2, then 2X - X^2 is
+                              pruned again; nonzero: one pruning -- 2X - X^2 and the norm are formed
+                              from the unpruned X^2, and only the iterate taken is pruned (the
+                              paper's "SP2 Loop X2", "Norm" and "Misc" steps fused into one pass;
+                              its text does not say where the pruning falls).  Branch, traces and
+                              every other rule are the same. */
 } sp2_params_t;
 
 typedef struct {

@@ -53,7 +53,8 @@ f32p = C.POINTER(C.c_float)
 class SP2Params(C.Structure):
     _fields_ = [("n_occ", C.c_double), ("tau", C.c_double), ("idem_target", C.c_double),
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("fp64_tail_steps", C.c_int32),
-                ("stall_stop", C.c_int32), ("tau_fp32", C.c_double), ("switch_eta", C.c_double)]
+                ("stall_stop", C.c_int32), ("tau_fp32", C.c_double), ("switch_eta", C.c_double),
+                ("prune_once", C.c_int32)]
 
 
 class SP2Report(C.Structure):
@@ -75,6 +76,10 @@ def lib():
         L.orc_check_ell.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
         L.orc_x2_fma_count.restype = C.c_int64
         L.orc_x2_fma_count.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
+        L.orc_prune_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_double, C.c_int32,
+                                    i32p, i32p, f64p, i32p]
+        L.orc_prune_f32.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f32p, C.c_float, C.c_int32,
+                                    i32p, i32p, f32p, i32p]
         L.orc_threads.restype = C.c_int32
         L.orc_threads.argtypes = [C.c_int32]
         L.orc_rows_init.restype = None
@@ -259,6 +264,23 @@ def update(X, Y, tau, Mo=None):
     return rc, Ell(N, Mo, nnzo, idxo, valo), int(w.value)
 
 
+def prune(Y, tau, Mo=None):
+    """(status, prune(Y, tau), maxw): the entries with |v| > tau."""
+    N = Y.N
+    if Mo is None:
+        Mo = max(Y.M, 1)
+    nnzo, idxo, valo = empty_rows(N, Mo, Y.val.dtype)
+    w = C.c_int32(0)
+    L = lib()
+    if Y.val.dtype == np.float32:
+        rc = L.orc_prune_f32(N, Y.M, _p(Y.nnz, i32p), _p(Y.idx, i32p), _p(Y.val, f32p), C.c_float(tau), Mo,
+                             _p(nnzo, i32p), _p(idxo, i32p), _p(valo, f32p), C.byref(w))
+    else:
+        rc = L.orc_prune_f64(N, Y.M, _p(Y.nnz, i32p), _p(Y.idx, i32p), _p(Y.val, f64p), float(tau), Mo,
+                             _p(nnzo, i32p), _p(idxo, i32p), _p(valo, f64p), C.byref(w))
+    return rc, Ell(N, Mo, nnzo, idxo, valo), int(w.value)
+
+
 def gershgorin(H):
     lo, hi = C.c_double(0), C.c_double(0)
     rc = lib().orc_gershgorin(H.N, H.M, _p(H.nnz, i32p), _p(H.idx, i32p), _p(_f64(H.val), f64p),
@@ -286,9 +308,10 @@ def x0(H, emin, emax, tau, Mo=None, fp32=False):
 
 
 def make_params(n_occ, tau, idem_target, max_iter=100, precision=PREC_F64, fp64_tail_steps=2,
-                stall_stop=1, tau_fp32=1e-7, switch_eta=1e-3):
+                stall_stop=1, tau_fp32=1e-7, switch_eta=1e-3, prune_once=0):
     return SP2Params(float(n_occ), float(tau), float(idem_target), int(max_iter), int(precision),
-                     int(fp64_tail_steps), int(stall_stop), float(tau_fp32), float(switch_eta))
+                     int(fp64_tail_steps), int(stall_stop), float(tau_fp32), float(switch_eta),
+                     int(prune_once))
 
 
 class _Hist:

@@ -425,6 +425,51 @@ int orc_update_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
 }
 
 /* ------------------------------------------------------------------------ */
+/* prune: keep |v| > tau (the single pruning of the one-pruning SP2 mode)    */
+/* ------------------------------------------------------------------------ */
+int orc_prune_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val, double tau,
+                  int32_t Mo, int32_t *nnzo, int32_t *idxo, double *valo, int32_t *maxw)
+{
+  int overflow = 0;
+  int32_t widest = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t c = 0;
+    for (int32_t s = 0; s < nnz[i]; ++s) {
+      const double v = val[(int64_t)i * M + s];
+      if (fabs(v) > tau) {
+        if (c < Mo) { idxo[(int64_t)i * Mo + c] = idx[(int64_t)i * M + s]; valo[(int64_t)i * Mo + c] = v; }
+        ++c;
+      }
+    }
+    if (c > Mo) { overflow = 1; nnzo[i] = Mo; } else nnzo[i] = c;
+    if (c > widest) widest = c;
+  }
+  if (maxw) *maxw = widest;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+int orc_prune_f32(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const float *val, float tau,
+                  int32_t Mo, int32_t *nnzo, int32_t *idxo, float *valo, int32_t *maxw)
+{
+  int overflow = 0;
+  int32_t widest = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    int32_t c = 0;
+    for (int32_t s = 0; s < nnz[i]; ++s) {
+      const float v = val[(int64_t)i * M + s];
+      if (fabsf(v) > tau) {
+        if (c < Mo) { idxo[(int64_t)i * Mo + c] = idx[(int64_t)i * M + s]; valo[(int64_t)i * Mo + c] = v; }
+        ++c;
+      }
+    }
+    if (c > Mo) { overflow = 1; nnzo[i] = Mo; } else nnzo[i] = c;
+    if (c > widest) widest = c;
+  }
+  if (maxw) *maxw = widest;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Gershgorin bounds and the initial guess X0                               */
 /* ------------------------------------------------------------------------ */
 int orc_gershgorin(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
@@ -604,6 +649,20 @@ static int sp2_update_grow(omat *X, const omat *Y, omat *T, double tau, float ta
   }
 }
 
+static int sp2_prune_grow(const omat *Y, omat *P, double tau, float tau32, int32_t *maxw)
+{
+  for (;;) {
+    int rc;
+    if (Y->f)
+      rc = orc_prune_f32(Y->N, Y->M, Y->nnz, Y->idx, Y->f, tau32, P->M, P->nnz, P->idx, P->f, maxw);
+    else
+      rc = orc_prune_f64(Y->N, Y->M, Y->nnz, Y->idx, Y->v, tau, P->M, P->nnz, P->idx, P->v, maxw);
+    if (rc != ORC_EOVERFLOW) return rc;
+    rc = omat_alloc(P, Y->N, roundup32(*maxw), Y->f != NULL);
+    if (rc) return rc;
+  }
+}
+
 static void omat_swap(omat *a, omat *b) { omat t = *a; *a = *b; *b = t; }
 
 /* widen an FP32 matrix to FP64 (exact) */
@@ -641,7 +700,8 @@ int orc_sp2(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const 
   double target2 = p->idem_target * p->idem_target;
   double switch2 = p->switch_eta * p->switch_eta;
 
-  omat X = {0}, Y = {0}, T = {0};
+  const int once = p->prune_once != 0;
+  omat X = {0}, Y = {0}, T = {0}, P = {0};
   double *d1 = (double *)malloc((size_t)N * sizeof(double));
   double *d2 = (double *)malloc((size_t)N * sizeof(double));
   double *hist = (double *)malloc((size_t)p->max_iter * sizeof(double));
@@ -674,7 +734,19 @@ int orc_sp2(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const 
   for (n = 0; n < p->max_iter; ++n) {
     int32_t maxw = 0;
     int in32 = X.f != NULL;
-    rc = sp2_x2_grow(&X, &Y, p->tau, tau32, d1, d2, &maxw);
+    if (once) {
+      /* Y = X.X unpruned (every nonzero entry); P = prune(Y), the X^2 branch's iterate */
+      rc = sp2_x2_grow(&X, &Y, 0.0, 0.0f, d1, d2, &maxw);
+      if (rc) goto done;
+      if (P.M == 0 || (P.f != NULL) != in32) {
+        omat_free(&P);
+        rc = omat_alloc(&P, N, X.M, in32);
+        if (rc) goto done;
+      }
+      rc = sp2_prune_grow(&Y, &P, p->tau, tau32, &maxw);
+    } else {
+      rc = sp2_x2_grow(&X, &Y, p->tau, tau32, d1, d2, &maxw);
+    }
     if (rc) goto done;
     trx = orc_pairwise(N, d1);
     double trx2 = orc_pairwise(N, d2);
@@ -721,11 +793,11 @@ int orc_sp2(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const 
     int up = a < b;
     if (r->hist_up) r->hist_up[n] = (int8_t)up;
     if (up) {
-      rc = sp2_update_grow(&X, &Y, &T, p->tau, tau32);
+      rc = sp2_update_grow(&X, &Y, &T, p->tau, tau32);  /* once: Y unpruned, one pruning */
       if (rc) goto done;
       omat_swap(&X, &T);
     } else {
-      omat_swap(&X, &Y);
+      omat_swap(&X, once ? &P : &Y);
     }
     if (!in32) ++fp64_updates;
     /* keep the scratch matrices at least as wide as X */
@@ -754,7 +826,7 @@ int orc_sp2(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const 
   rc = final_status;
 done:
   r->status = rc;
-  omat_free(&X); omat_free(&Y); omat_free(&T);
+  omat_free(&X); omat_free(&Y); omat_free(&T); omat_free(&P);
   free(d1); free(d2); free(hist);
   return rc;
 }

@@ -108,6 +108,12 @@ int orc_update_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
                    int32_t M2, const int32_t *nnz2, const int32_t *idx2, const float *val2, float tau,
                    int32_t Mo, int32_t *nnzo, int32_t *idxo, float *valo, int32_t *maxw);
 
+/* A = prune(Y, tau): the entries of Y with |v| > tau, in order. */
+int orc_prune_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val, double tau,
+                  int32_t Mo, int32_t *nnzo, int32_t *idxo, double *valo, int32_t *maxw);
+int orc_prune_f32(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const float *val, float tau,
+                  int32_t Mo, int32_t *nnzo, int32_t *idxo, float *valo, int32_t *maxw);
+
 /* Gershgorin interval of H. */
 int orc_gershgorin(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
                    double *emin, double *emax);
@@ -130,6 +136,10 @@ typedef struct {
   int32_t stall_stop;    /* nonzero: apply the stall rule */
   double tau_fp32;       /* mixed: FP32 drop tolerance (rounded to float) */
   double switch_eta;     /* mixed: switch to FP64 when eta < switch_eta */
+  int32_t prune_once;    /* 0: X2 = prune(X.X) enters the norm and 2X - X2, which is pruned
+                            again (two prunings); nonzero: the unpruned product Y = X.X enters
+                            the norm and 2X - Y, and only the iterate taken is pruned:
+                            prune(Y) or prune(2X - Y) (one pruning) */
 } orc_sp2_params;
 
 typedef struct {

@@ -1242,6 +1242,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   hs.cap = cap;
   hs.sw = mixed ? S32.SW : S64.SW;
   hs.nnz_cur = (int64_t)nnz0;
+  hs.once = p->prune_once ? 1 : 0;
   HIP_TRY(hipMemcpyAsync(S.state.p, &hs, sizeof(hs), hipMemcpyHostToDevice, st));
 
   SP2Cfg cfg{};
@@ -2063,6 +2064,7 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     h.cap = INT_MAX;
     h.sw = sw;
     h.nnz_cur = (int64_t)I.nnz0;
+    h.once = P.prune_once ? 1 : 0;
     if (I.solo) {  // never enters the loop
       h.stop = 1;
       h.status = ST_FALLBACK;

@@ -173,9 +173,11 @@ __device__ __forceinline__ int row_set(int v, int g, int x) { return lane_id() =
 // of all 8 rows in registers (k ascending), then sweep it for each row --
 // threshold, compaction of X^2 and 2X - X^2 (ELLPACK and/or span form), and
 // the lane tree of the norm's squared differences for that aligned block.
+// `once`: 2X - X^2 and the norm take the unpruned X^2 (one pruning per
+// iteration); otherwise the pruned X^2.
 template <typename T, bool WITH_U, bool OUT_ELL, bool OUT_SPAN>
 __device__ void band_rows(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
-                          const SpanView<T> SU, const EllView<T> Y, const EllView<T> U, const T tau,
+                          const SpanView<T> SU, const EllView<T> Y, const EllView<T> U, const T tau, const bool once,
                           const StepScratch &s, double *bsum, int32_t *fallback)
 {
   const int lane = lane_id();
@@ -346,6 +348,7 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
       }
       const bool ky = absv(y) > tau;
       const T yk = ky ? y : T(0);
+      const T ym = once ? y : yk;  // the X^2 value 2X - X^2 and the norm see
       const uint64_t my = __ballot(ky);
       int cy = row_get(st_cy, g);
       if (OUT_ELL && ky) {
@@ -367,7 +370,7 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
         if ((unsigned)o < (unsigned)SY.SW) SY.val[(size_t)i * SY.SW + o] = yk;
       }
       if (WITH_U) {
-        const T v = T(2) * x - yk;
+        const T v = T(2) * x - ym;
         const bool ku = absv(v) > tau;
         const uint64_t mu = __ballot(ku);
         const int cu = row_get(st_cu, g);
@@ -390,7 +393,7 @@ __device__ void band_rows(const int N, const int i0, const int nrows, const Span
           if ((unsigned)o < (unsigned)SU.SW) SU.val[(size_t)i * SU.SW + o] = ku ? v : T(0);
         }
       }
-      const double dd = (double)yk - (double)x;
+      const double dd = (double)ym - (double)x;
       const double t = wave_tree(dd * dd);
       if (lane == 0 && rel < kNormBlocks) bsum[g * kNormBlocks + rel] = t;
     }
@@ -440,9 +443,11 @@ __global__ __launch_bounds__(256) void k_x2_band(int N, SpanRot3<T> spans, Rot3<
 {
   __shared__ double bsum_s[kWavesPerBlock][kG * kNormBlocks];
   int cur = 0;
+  bool once = false;
   if (st) {
     if (st->stop) return;
     cur = st->cur;
+    once = st->once != 0;
   }
   const int w = uni(threadIdx.x >> 6);
   const int grp = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(256) void k_x2_band(int N, SpanRot3<T> spans, Rot3<
   const int nrows = min(kG, N - i0);
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
   band_rows<T, WITH_U, OUT_ELL, OUT_SPAN>(N, i0, nrows, spans.b[cur], spans.b[cy], spans.b[cu], ells.b[cy],
-                                          ells.b[cu], tau, s, bsum_s[w], fallback);
+                                          ells.b[cu], tau, once, s, bsum_s[w], fallback);
 }
 
 // Batched form: the instances' rows are stacked in one span matrix, instance m
@@ -490,7 +495,8 @@ __global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> 
   if (i0 >= n) return;  // alignment rows after the instance's last row
   const EllView<T> none{nullptr, nullptr, nullptr, 0};
   band_rows<T, true, false, true>(n, i0, min(kG, n - i0), shift_rows(spans.b[cur], r0), shift_rows(spans.b[cy], r0),
-                                  shift_rows(spans.b[cu], r0), none, none, taus[m], ss[m], bsum_s[w], flags + m);
+                                  shift_rows(spans.b[cu], r0), none, none, taus[m], st->once != 0, ss[m], bsum_s[w],
+                                  flags + m);
 }
 
 // ---- conversions between ELLPACK and span form -----------------------------------------

@@ -145,10 +145,12 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
 }
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
+// `once`: 2X - X^2 and the norm take the unpruned X^2 (one pruning per
+// iteration); otherwise the pruned X^2.
 template <typename T>
 __device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
-                       const SpanView<T> SU, const T tau, const StepScratch &s, double *stk, double *sq,
-                       int2 *meta, [[maybe_unused]] int32_t *fallback)
+                       const SpanView<T> SU, const T tau, const bool once, const StepScratch &s, double *stk,
+                       double *sq, int2 *meta, [[maybe_unused]] int32_t *fallback)
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -313,10 +315,11 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
         const T y = acc[p][t], x = xv[t][p];
         ky[p] = act && absv(y) > tau;
         yk[p] = ky[p] ? y : T(0);
-        const T v = T(2) * x - yk[p];
+        const T ym = once ? y : yk[p];  // the X^2 value 2X - X^2 and the norm see
+        const T v = T(2) * x - ym;
         ku[p] = act && absv(v) > tau;
         uk[p] = ku[p] ? v : T(0);
-        const double d = (double)yk[p] - (double)x;
+        const double d = (double)ym - (double)x;
         e[p] = d * d;
       }
       uint64_t my[kP], mu[kP];
@@ -440,17 +443,19 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
   __shared__ double sq_s[kWpb][kR * kWave];
   __shared__ int2 meta_s[kWpb][kMeta];
   int cur = 0;
+  bool once = false;
   if (st) {
     if (st->stop) return;
     cur = st->cur;
+    once = st->once != 0;
   }
   const int w = uni(threadIdx.x >> 6);
   const int grp = xcd_block(blockIdx.x, gridDim.x) * kWpb + w;
   const int i0 = grp * kR;
   if (i0 >= N) return;
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, stk_s[w], sq_s[w], meta_s[w],
-            fallback);
+  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, once, s, stk_s[w], sq_s[w],
+            meta_s[w], fallback);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,8 +482,8 @@ __global__ __launch_bounds__(256) void k_x2_band16_part(int N, SpanRot3<T> spans
   const int i0 = (xb * kWpb + w) * kR;
   if (i0 < N) {
     const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-    rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, s, stk_s[w], sq_s[w],
-              meta_s[w], s.flags);
+    rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, st->once != 0, s, stk_s[w],
+              sq_s[w], meta_s[w], s.flags);
   }
   __syncthreads();  // the row outputs of all four wavefronts are written
   if (w != 0) return;
@@ -605,7 +610,7 @@ __global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T
   const int i0 = grp * kR - r0;
   if (i0 >= n) return;  // alignment rows after the instance's last row
   rows16<T>(n, i0, min(kR, n - i0), rows_from(spans.b[cur], r0), rows_from(spans.b[cy], r0),
-            rows_from(spans.b[cu], r0), taus[m], ss[m], stk_s[w], sq_s[w], meta_s[w], flags + m);
+            rows_from(spans.b[cu], r0), taus[m], st->once != 0, ss[m], stk_s[w], sq_s[w], meta_s[w], flags + m);
 }
 
 }  // namespace

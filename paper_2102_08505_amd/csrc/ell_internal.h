@@ -64,7 +64,8 @@ struct SP2State {
   // symmetric span iteration: the branch of the next product (1: 2X - X^2),
   // fixed from the traces of the current X that the step which wrote it
   // predicted, Tr X and the unpruned Tr X^2; the next step checks them
-  int32_t up_next, pad_;
+  int32_t up_next;
+  int32_t once;         // 1: 2X - X^2 and the norm from the unpruned X^2 (one pruning per iteration)
   double ptrx, ptrx2;
 };
 

@@ -134,9 +134,11 @@ __device__ __forceinline__ void push_block(double *stk, uint32_t &pend, const in
 // Sweep one accumulator window in ascending column order (the window starts
 // on a multiple of 64 columns): compact the kept entries of X^2 (and of
 // 2X - X^2), and reduce each aligned 64-column block of the norm's squared
-// differences by the lane tree into the row's block tree (lane 0).
+// differences by the lane tree into the row's block tree (lane 0).  `once`:
+// 2X - X^2 and the norm take the unpruned X^2 (one pruning per iteration);
+// otherwise the pruned X^2.
 template <typename T, bool WITH_U>
-__device__ __forceinline__ void sweep_window(const int i, const int wlo, const int wlen, const T tau,
+__device__ __forceinline__ void sweep_window(const int i, const int wlo, const int wlen, const T tau, const bool once,
                                              const T *acc, const T *xw, const int b_first, double *stk,
                                              const EllView<T> &Y, const EllView<T> &U, SweepState &st)
 {
@@ -157,9 +159,9 @@ __device__ __forceinline__ void sweep_window(const int i, const int wlo, const i
       }
     }
     st.cy += __popcll(my);
-    const T yk = ky ? y : T(0);
+    const T ym = (ky || once) ? y : T(0);  // the X^2 value 2X - X^2 and the norm see
     if (WITH_U) {
-      const T v = T(2) * x - yk;
+      const T v = T(2) * x - ym;
       const bool ku = in && absv(v) > tau;
       const uint64_t mu = __ballot(ku);
       if (ku) {
@@ -171,7 +173,7 @@ __device__ __forceinline__ void sweep_window(const int i, const int wlo, const i
       }
       st.cu += __popcll(mu);
     }
-    const double dd = (double)yk - (double)x;
+    const double dd = (double)ym - (double)x;
     const double t = wave_tree(dd * dd);
     if (lane == 0) push_block(stk, st.pend, (wlo + q0) >> 6, b_first, t);
   }
@@ -258,7 +260,7 @@ __device__ __forceinline__ void accumulate_window(const int wi, const int wlo, c
 template <typename T, bool WITH_U>
 __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int32_t *__restrict__ xidx,
                        const T *__restrict__ xval, const int M, EllView<T> Y, EllView<T> U, const T tau,
-                       T *acc, T *xw, double *stk, const StepScratch &s)
+                       const bool once, T *acc, T *xw, double *stk, const StepScratch &s)
 {
   const int lane = lane_id();
   const int wi = uniform_i(xnnz[i]);
@@ -364,7 +366,7 @@ __device__ void x2_row(const int i, const int32_t *__restrict__ xnnz, const int3
     }
     wave_sync();
     if (i >= wlo && i < wlo + wlen) d2 = (double)acc[i - wlo];
-    sweep_window<T, WITH_U>(i, wlo, wlen, tau, acc, xw, b_first, stk, Y, U, st);
+    sweep_window<T, WITH_U>(i, wlo, wlen, tau, once, acc, xw, b_first, stk, Y, U, st);
   }
   const double ev = finish_norm(stk, st.pend);
   if (lane == 0) {
@@ -401,9 +403,11 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
   __shared__ T xw_s[kWavesPerBlock][kWin];
   __shared__ double stk_s[kWavesPerBlock][kLev];
   int cur = 0;
+  bool once = false;
   if (st) {
     if (st->stop) return;
     cur = st->cur;
+    once = st->once != 0;
   }
   const int w = uniform_i(threadIdx.x >> 6);
   const int i = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
   const EllView<T> X = bufs.b[cur];
   const EllView<T> Y = bufs.b[cur == 2 ? 0 : cur + 1];
   const EllView<T> U = bufs.b[cur == 0 ? 2 : cur - 1];
-  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, acc_s[w], xw_s[w], stk_s[w], s);
+  x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, once, acc_s[w], xw_s[w], stk_s[w], s);
 }
 
 // --------------------------------------------------------------------------

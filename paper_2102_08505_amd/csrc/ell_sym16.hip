@@ -223,10 +223,13 @@ struct RowOut {
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16).  X is read, the
 // iterate the branch selects (UP: 2X - X^2, else X^2) is written to SO.  rw:
-// the wave's 16 rows in the workgroup's RowOut.
+// the wave's 16 rows in the workgroup's RowOut.  `once`: 2X - X^2 and the
+// norm take the unpruned X^2 (one pruning per iteration); otherwise the
+// pruned X^2.
 template <typename T, bool UP>
 __device__ void rows16_sym(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SO,
-                           const T tau, double *stk, double *sq, int2 *meta, RowOut &ro, const int rw)
+                           const T tau, const bool once, double *stk, double *sq, int2 *meta, RowOut &ro,
+                           const int rw)
 {
   constexpr int G = Run<T>::G, H = Run<T>::H;
   const int lane = lane_id();
@@ -393,15 +396,16 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
           const T y = acc[kP * sb + p][t], x = xv[t][p];
           ky[p] = act && absv(y) > tau;
           const T yk = ky[p] ? y : T(0);
+          const T ym = once ? y : yk;  // the X^2 value 2X - X^2 and the norm see
           if (UP) {
-            const T v = T(2) * x - yk;
+            const T v = T(2) * x - ym;
             kv[p] = act && absv(v) > tau;
             vk[p] = kv[p] ? v : T(0);
           } else {  // the iterate is the pruned X^2 itself
             kv[p] = ky[p];
             vk[p] = yk;
           }
-          const double d = (double)yk - (double)x;
+          const double d = (double)ym - (double)x;
           sq[rr * kWave + (run_col<T>(0, p / G, r) + p % G)] = d * d;
           vks[t][p] = vk[p];
         }
@@ -651,12 +655,13 @@ __global__ __launch_bounds__(256) void k_x2_sym_step(int N, SpanRot3<T> spans, S
     // the iterate goes where the decision will find it: X^2 to slot cur + 1,
     // 2X - X^2 to slot cur + 2 (mod 3)
     const int co = up ? (cur == 0 ? 2 : cur - 1) : (cur == 2 ? 0 : cur + 1);
+    const bool once = st->once != 0;
     if (up)
-      rows16_sym<T, true>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, stk_s[w], sq_s[w], meta_s[w], ro,
-                          w * kR);
+      rows16_sym<T, true>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, once, stk_s[w], sq_s[w],
+                          meta_s[w], ro, w * kR);
     else
-      rows16_sym<T, false>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, stk_s[w], sq_s[w], meta_s[w], ro,
-                           w * kR);
+      rows16_sym<T, false>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[co], tau, once, stk_s[w], sq_s[w],
+                           meta_s[w], ro, w * kR);
   } else if (lane < kR) {
     for (int c = 0; c < kSums; ++c) ro.s[c][w * kR + lane] = -0.0;
     ro.wy[w * kR + lane] = 0;

@@ -37,7 +37,7 @@ class SP2Params(C.Structure):
     _fields_ = [("n_occ", C.c_double), ("tau", C.c_double), ("idem_target", C.c_double),
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("fp64_tail_steps", C.c_int32),
                 ("poll_every", C.c_int32), ("tau_fp32", C.c_double), ("switch_eta", C.c_double),
-                ("stall_stop", C.c_int32), ("profile", C.c_int32)]
+                ("stall_stop", C.c_int32), ("profile", C.c_int32), ("prune_once", C.c_int32)]
 
 
 class SP2Report(C.Structure):
@@ -218,10 +218,10 @@ def ellpack_trace_product(a, b):
 
 
 def sp2_params(n_occ, tau, idem_target, max_iter=100, precision=SP2_F64, fp64_tail_steps=2,
-               poll_every=4, tau_fp32=1e-7, switch_eta=1e-3, stall_stop=1, profile=0):
+               poll_every=4, tau_fp32=1e-7, switch_eta=1e-3, stall_stop=1, profile=0, prune_once=0):
     return SP2Params(float(n_occ), float(tau), float(idem_target), int(max_iter), int(precision),
                      int(fp64_tail_steps), int(poll_every), float(tau_fp32), float(switch_eta),
-                     int(stall_stop), int(profile))
+                     int(stall_stop), int(profile), int(prune_once))
 
 
 class _Hist:
