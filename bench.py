@@ -431,17 +431,15 @@ def prune_mode_leg(E, synth, torch, H, reps=5, n_small=4096):
 def model_leg(E, synth, torch, reps=5):
     """The paper's model Hamiltonians (metals, semiconductors, soft matter,
     section "On the Generation of Model Hamiltonian System Matrices"): one FP64
-    X^2 of H itself at tau = 1e-5 on each system, at 32000 orbitals where the
-    product's rows fit the library's 4096-entry capacity (metals, soft matter)
-    and at 4096 for semiconductors (at 32000 their X^2 rows reach about 4900
-    entries); then SP2, FP64 and mixed, on the two gapped systems at 4096
-    orbitals, N_occ = the eigenvalues below the 0 eV Fermi level."""
+    X^2 of H itself at tau = 1e-5 on each system at 32000 orbitals; then SP2,
+    FP64 and mixed, on the two gapped systems at 4096 orbitals, N_occ = the
+    eigenvalues below the 0 eV Fermi level."""
     import numpy as np
     out = {"workload": "model Hamiltonians (A/B two-level chains, drop threshold 1e-5): X^2 of H at tau 1e-5; "
                        f"SP2 at N=4096, FP64 tau {TAU_MIXED64:g}, mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}, to "
                        f"||X^2-X||_F<{TARGET:g}"}
     x2 = {}
-    for kind, n in (("metal", 32000), ("semiconductor", 4096), ("soft_matter", 32000)):
+    for kind, n in (("metal", 32000), ("semiconductor", 32000), ("soft_matter", 32000)):
         nnz, idx, val, m = synth.model_hamiltonian(kind, n)
         X = E.DeviceEll.from_host(n, m, nnz, idx, val)
         Y = E.DeviceEll(n, min(4096, n))

@@ -87,7 +87,7 @@ int ellpack_check_host(int32_t N, int32_t M, const int32_t *nnz, const int32_t *
 /* Allocate an N x N matrix with capacity M slots per row on the current
  * device, every row empty.  The library owns the device buffers (released by
  * ellpack_free).  hip_stream: a hipStream_t, or NULL.
- * Limits: 1 <= N <= 2^20, 1 <= M <= 4096.
+ * Limits: 1 <= N <= 2^20, 1 <= M <= 65536.
  * Errors: ELL_EINVAL (N or M out of range, bad prec), ELL_ENODEV, ELL_ENOMEM. */
 int ellpack_alloc(ellpack_t **A, int32_t N, int32_t M, ell_prec_t prec, void *hip_stream);
 
@@ -229,7 +229,7 @@ int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p, sp2_repor
  * p: n parameter sets (one per instance); p[0].poll_every = K, or 0 to pick K
  * by timing the first graph replays.  Each instance's result, history and
  * status are bit-identical to sp2_solve on it alone; an instance the stacked
- * form cannot hold (X0 with exact zeros or rows wider than 4096 columns, or a
+ * form cannot hold (X0 with exact zeros or rows wider than 65536 columns, or a
  * stride overflow beyond that) is finished by sp2_solve on its own.  r: n
  * reports (may be NULL); `seconds` is the whole batch's device time, and the
  * x2 timing fields are 0 (the step kernel serves all instances at once).

@@ -76,6 +76,8 @@ def lib():
         L.orc_check_ell.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
         L.orc_x2_fma_count.restype = C.c_int64
         L.orc_x2_fma_count.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
+        L.orc_x2_rows_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_double, C.c_int32, i32p,
+                                      C.c_int32, i32p, i32p, f64p, f64p]
         L.orc_prune_f64.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f64p, C.c_double, C.c_int32,
                                     i32p, i32p, f64p, i32p]
         L.orc_prune_f32.argtypes = [C.c_int32, C.c_int32, i32p, i32p, f32p, C.c_float, C.c_int32,
@@ -178,6 +180,20 @@ def check_ell(A):
 
 def fma_count(A):
     return int(lib().orc_x2_fma_count(A.N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p)))
+
+
+def x2_rows(A, tau, rows, M2):
+    """(status, nnz[nr], idx[nr, M2], val[nr, M2], d2[nr]): rows `rows` of the
+    FP64 prune(A.A, tau), each as x2 computes it."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    nr = rows.size
+    nnz2 = np.zeros(nr, np.int32)
+    idx2 = np.full(nr * M2, -1, np.int32)
+    val2 = np.zeros(nr * M2, np.float64)
+    d2 = np.zeros(nr)
+    rc = lib().orc_x2_rows_f64(A.N, A.M, _p(A.nnz, i32p), _p(A.idx, i32p), _p(_f64(A.val), f64p), float(tau), nr,
+                               _p(rows, i32p), M2, _p(nnz2, i32p), _p(idx2, i32p), _p(val2, f64p), _p(d2, f64p))
+    return rc, nnz2, idx2.reshape(nr, M2), val2.reshape(nr, M2), d2
 
 
 def threads(n=0):

@@ -105,6 +105,47 @@ static int cmp_i32(const void *a, const void *b)
 /* accumulator (SPA).  For row i, k runs over row i in ascending order, j    */
 /* over row k in ascending order, acc[j] = fma(X_ik, X_kj, acc[j]).          */
 /* ------------------------------------------------------------------------ */
+/* Row i of prune(X.X, tau) in FP64 into (idx2r, val2r) (at most M2 entries):
+ * returns the surviving count (which may exceed M2); *xii = X_ii, *dii = the
+ * unpruned (X.X)_ii.  acc, mark: N zeros on entry and on return; touched: N. */
+static int32_t x2_row_f64(int32_t i, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
+                          double tau, int32_t M2, int32_t *idx2r, double *val2r, double *acc, char *mark,
+                          int32_t *touched, double *xii, double *dii)
+{
+  const int32_t *ci = idx + (int64_t)i * M;
+  const double *vi = val + (int64_t)i * M;
+  int32_t nt = 0;
+  *xii = 0.0;
+  for (int32_t s = 0; s < nnz[i]; ++s) {
+    int32_t k = ci[s];
+    double a = vi[s];
+    if (k == i) *xii = a;
+    const int32_t *ck = idx + (int64_t)k * M;
+    const double *vk = val + (int64_t)k * M;
+    for (int32_t t = 0; t < nnz[k]; ++t) {
+      int32_t j = ck[t];
+      if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
+      acc[j] = fma(a, vk[t], acc[j]);
+    }
+  }
+  *dii = acc[i];
+  qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+  int32_t c = 0;
+  for (int32_t q = 0; q < nt; ++q) {
+    int32_t j = touched[q];
+    if (fabs(acc[j]) > tau) {
+      if (c < M2) {
+        idx2r[c] = j;
+        val2r[c] = acc[j];
+      }
+      ++c;
+    }
+    acc[j] = 0.0;
+    mark[j] = 0;
+  }
+  return c;
+}
+
 int orc_x2_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
                double tau, int32_t M2, int32_t *nnz2, int32_t *idx2, double *val2,
                double *d1, double *d2, int32_t *maxw)
@@ -122,38 +163,11 @@ int orc_x2_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, con
 #pragma omp for schedule(static)
     for (int32_t i = 0; i < N; ++i) {
       if (!ok) continue;
-      const int32_t *ci = idx + (int64_t)i * M;
-      const double *vi = val + (int64_t)i * M;
-      int32_t nt = 0;
-      double xii = 0.0;
-      for (int32_t s = 0; s < nnz[i]; ++s) {
-        int32_t k = ci[s];
-        double a = vi[s];
-        if (k == i) xii = a;
-        const int32_t *ck = idx + (int64_t)k * M;
-        const double *vk = val + (int64_t)k * M;
-        for (int32_t t = 0; t < nnz[k]; ++t) {
-          int32_t j = ck[t];
-          if (!mark[j]) { mark[j] = 1; touched[nt++] = j; }
-          acc[j] = fma(a, vk[t], acc[j]);
-        }
-      }
-      if (d1) d1[i] = (double)xii;
-      if (d2) d2[i] = (double)acc[i];
-      qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
-      int32_t c = 0;
-      for (int32_t q = 0; q < nt; ++q) {
-        int32_t j = touched[q];
-        if (fabs(acc[j]) > tau) {
-          if (c < M2) {
-            idx2[(int64_t)i * M2 + c] = j;
-            val2[(int64_t)i * M2 + c] = acc[j];
-          }
-          ++c;
-        }
-        acc[j] = 0.0;
-        mark[j] = 0;
-      }
+      double xii, dii;
+      const int32_t c = x2_row_f64(i, M, nnz, idx, val, tau, M2, idx2 + (int64_t)i * M2, val2 + (int64_t)i * M2,
+                                   acc, mark, touched, &xii, &dii);
+      if (d1) d1[i] = xii;
+      if (d2) d2[i] = dii;
       if (c > M2) { overflow = 1; nnz2[i] = M2; } else nnz2[i] = c;
       if (c > widest) widest = c;
     }
@@ -161,6 +175,35 @@ int orc_x2_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, con
   }
   if (failed) return ORC_ENOMEM;
   if (maxw) *maxw = widest;
+  return overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+int orc_x2_rows_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
+                    double tau, int32_t nr, const int32_t *rows, int32_t M2, int32_t *nnz2, int32_t *idx2,
+                    double *val2, double *d2)
+{
+  for (int32_t q = 0; q < nr; ++q)
+    if (rows[q] < 0 || rows[q] >= N) return ORC_EINVAL;
+  int failed = 0, overflow = 0;
+#pragma omp parallel reduction(| : failed, overflow)
+  {
+    double *acc = (double *)calloc((size_t)N, sizeof(double));
+    char *mark = (char *)calloc((size_t)N, 1);
+    int32_t *touched = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    const int ok = acc && mark && touched;
+    if (!ok) failed = 1;
+#pragma omp for schedule(dynamic)
+    for (int32_t q = 0; q < nr; ++q) {
+      if (!ok) continue;
+      double xii, dii;
+      const int32_t c = x2_row_f64(rows[q], M, nnz, idx, val, tau, M2, idx2 + (int64_t)q * M2,
+                                   val2 + (int64_t)q * M2, acc, mark, touched, &xii, &dii);
+      if (d2) d2[q] = dii;
+      if (c > M2) { overflow = 1; nnz2[q] = M2; } else nnz2[q] = c;
+    }
+    free(acc); free(mark); free(touched);
+  }
+  if (failed) return ORC_ENOMEM;
   return overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 

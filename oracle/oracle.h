@@ -108,6 +108,14 @@ int orc_update_f32(int32_t N, int32_t MX, const int32_t *nnzX, const int32_t *id
                    int32_t M2, const int32_t *nnz2, const int32_t *idx2, const float *val2, float tau,
                    int32_t Mo, int32_t *nnzo, int32_t *idxo, float *valo, int32_t *maxw);
 
+/* Rows rows[0 .. nr) of prune(X.X, tau) in FP64, computed as orc_x2_f64
+ * computes them, into output rows 0 .. nr (capacity M2), and the unpruned
+ * diagonal entries (X.X)_ii of those rows in d2 (may be NULL): for checking
+ * sampled rows of products too large to form whole. */
+int orc_x2_rows_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val,
+                    double tau, int32_t nr, const int32_t *rows, int32_t M2, int32_t *nnz2, int32_t *idx2,
+                    double *val2, double *d2);
+
 /* A = prune(Y, tau): the entries of Y with |v| > tau, in order. */
 int orc_prune_f64(int32_t N, int32_t M, const int32_t *nnz, const int32_t *idx, const double *val, double tau,
                   int32_t Mo, int32_t *nnzo, int32_t *idxo, double *valo, int32_t *maxw);

@@ -105,7 +105,7 @@ struct StepScratch {
 
 constexpr int kRedBlock = 1024;  // rows per partial-reduction block
 constexpr int kMaxFinal = 1024;  // partials the final reduction handles in one block
-constexpr int kMaxCap = 4096;    // largest supported capacity M
+constexpr int kMaxCap = 1 << 16;  // largest supported capacity M (entries per row)
 constexpr int kMaxN = kRedBlock * kMaxFinal;  // two reduction levels cover every row
 
 // Record a failed HIP call as the library's last device error; returns the

@@ -639,3 +639,24 @@ def test_trace_product_diagonal_closed_form():
     A = oracle.Ell(5, 1, (a != 0).astype(np.int32), np.where(a != 0, np.arange(5), -1).astype(np.int32), a.copy())
     B = oracle.Ell(5, 1, (b != 0).astype(np.int32), np.where(b != 0, np.arange(5), -1).astype(np.int32), b.copy())
     assert oracle.trace_product(A, B) == float((a * b).sum())  # dyadic: every sum is exact
+
+
+def test_x2_rows_equal_the_rows_of_the_whole_product():
+    """The sampled-row product (for checking products too large to form
+    whole) gives exactly the rows, widths and unpruned diagonal of x2."""
+    rng = np.random.default_rng(21)
+    D, A = random_sparse(230, 0.08, rng, extra=[("full", 40), ("empty", 7)])
+    rc, Y, d1, d2, w = oracle.x2(A, 0.05)
+    assert rc == 0
+    rows = np.array([0, 7, 40, 41, 117, 229])
+    rc, nz, ix, vl, dd = oracle.x2_rows(A, 0.05, rows, M2=Y.M)
+    assert rc == 0
+    for q, i in enumerate(rows):
+        c, v = Y.rows()[i]
+        assert nz[q] == len(c)
+        assert np.array_equal(ix[q, :nz[q]], c) and np.array_equal(vl[q, :nz[q]], v)
+        assert dd[q] == d2[i]
+    rc, nz, ix, vl, dd = oracle.x2_rows(A, 0.05, rows, M2=3)
+    assert rc == oracle.EOVERFLOW
+    rc, *_ = oracle.x2_rows(A, 0.05, np.array([230]), M2=4)
+    assert rc == oracle.EINVAL
