@@ -428,6 +428,64 @@ def prune_mode_leg(E, synth, torch, H, reps=5, n_small=4096):
     return out
 
 
+def nonbanded_leg(E, synth, torch, reps=10):
+    """Products whose rows are not intervals: one FP64 step (X^2, 2X - X^2,
+    traces, norm) of the nearest-neighbour Hamiltonian of a 32^3 cubic lattice
+    (N = 32768, 7 entries per row spread over 2049 columns; the products of a
+    row fit the hashed row accumulator), and of a random symmetric matrix with
+    about 100 entries per row spread over all of N = 20000 columns (rows of
+    about 9000 products: the window kernel)."""
+    import numpy as np
+    out = {"workload": "one FP64 step (tau 1e-5) of the 32^3 lattice Hamiltonian (hashed accumulator) and of a "
+                       "random symmetric N=20000 matrix with ~100 scattered entries per row (window kernel)"}
+    rng = np.random.default_rng(5)
+
+    def scattered(n, per_row):
+        i = np.repeat(np.arange(n), per_row)
+        j = rng.integers(0, n, size=n * per_row)
+        keep = i != j
+        lo, hi = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
+        key = np.unique(lo.astype(np.int64) * n + hi)
+        lo, hi = key // n, key % n
+        v = rng.uniform(-1, 1, size=lo.size) * 0.1
+        rows = np.concatenate([lo, hi, np.arange(n)])
+        cols = np.concatenate([hi, lo, np.arange(n)])
+        vals = np.concatenate([v, v, rng.uniform(-1, 1, size=n)])
+        order = np.lexsort((cols, rows))
+        rows, cols, vals = rows[order], cols[order], vals[order]
+        nnz = np.bincount(rows, minlength=n).astype(np.int32)
+        m = int(nnz.max())
+        start = np.concatenate([[0], np.cumsum(nnz)[:-1]])
+        slot = np.arange(rows.size) - start[rows]
+        idx = np.full(n * m, -1, np.int32)
+        val = np.zeros(n * m)
+        idx[rows * m + slot] = cols
+        val[rows * m + slot] = vals
+        return nnz, idx, val, m
+
+    cases = (("lattice_32", 32768, synth.grid3d_hamiltonian(32), 64),
+             ("scattered_20000", 20000, scattered(20000, 50), 12288))
+    for name, n, (nnz, idx, val, m), cap in cases:
+        X = E.DeviceEll.from_host(n, m, nnz, idx, val)
+        Y = E.DeviceEll(n, cap)
+        U = E.DeviceEll(n, cap)
+        rc, res, widths = E.ellpack_x2_step(X.h, Y.h, U.h, 1e-5)  # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, res, widths = E.ellpack_x2_step(X.h, Y.h, U.h, 1e-5)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        ny = int(Y.download()[2].sum())
+        fma = int(sum(int(nnz[idx[i * m:i * m + nnz[i]]].sum()) for i in range(n)))
+        byt = int(nnz.sum()) * 12 + ny * 12 + 8 * n
+        out[name] = {"status": int(rc), "N": n, "width_X": int(nnz.max()), "width_X2": int(widths[0]), "ms": ms,
+                     "fma": fma, "GBs": byt / ms / 1e6, "gfma_per_s": fma / ms / 1e6}
+    return out
+
+
 def model_leg(E, synth, torch, reps=5):
     """The paper's model Hamiltonians (metals, semiconductors, soft matter,
     section "On the Generation of Model Hamiltonian System Matrices"): one FP64
@@ -535,6 +593,7 @@ def main():
     ap.add_argument("--no-model", action="store_true", help="skip the paper's model Hamiltonians")
     ap.add_argument("--no-fp64-target", action="store_true",
                     help="skip the FP64 solve to ||X^2-X||_F < 1e-8 (tau = 1e-10)")
+    ap.add_argument("--no-nonbanded", action="store_true", help="skip the non-banded products")
     ap.add_argument("--no-prune-mode", action="store_true",
                     help="skip the comparison of one and two prunings per iteration")
     ap.add_argument("--main-only", action="store_true",
@@ -557,7 +616,7 @@ def main():
     if args.main_only:
         args.no_cpu = args.no_mixed = args.no_batched = args.no_dense = True
         args.no_accuracy = args.no_x2_single = args.no_model = args.no_fp64_target = True
-        args.no_prune_mode = True
+        args.no_prune_mode = args.no_nonbanded = True
     if args.copy_calibration:
         copy_calibration()
         return
@@ -663,6 +722,8 @@ def main():
         line["fp64_to_1e-8"] = fp64_target_leg(E, H, torch)
     if not args.no_prune_mode:
         line["prune_modes"] = prune_mode_leg(E, synth, torch, H)
+    if not args.no_nonbanded:
+        line["nonbanded"] = nonbanded_leg(E, synth, torch)
     if not args.no_x2_single:
         line["x2_single_tau1e-5"] = x2_single_leg(E, H)
     if not args.no_batched:

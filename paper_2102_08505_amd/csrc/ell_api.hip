@@ -498,7 +498,17 @@ int run_step(const ellpack *X, ellpack *Y, ellpack *U, double tau, double out[3]
     }
   }
   const StepScratch se = ell_scratch(m.s);
-  HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, se, X->stream));
+  if (!dense) {
+    // rows that fill little of their column intervals: the hashed accumulator,
+    // then the window kernel for rows with too many products for its table
+    DevMem left, nleft;
+    HIP_TRY(left.alloc(sizeof(int32_t) * N));
+    HIP_TRY(nleft.alloc(sizeof(int32_t)));
+    HIP_TRY(launch_x2_hash<T>(N, bufs, U != nullptr, (T)tau, se, left.as<int32_t>(), nleft.as<int32_t>(),
+                              X->stream));
+  } else {
+    HIP_TRY(launch_x2_step<T>(N, bufs, nullptr, U != nullptr, (T)tau, se, X->stream));
+  }
   HIP_TRY(launch_reduce(N, nullptr, se, X->stream));
   HIP_TRY(launch_final_only(se, X->stream));
   return finish_step<T>(X, Y, U, m, out, widths);

@@ -117,6 +117,12 @@ void set_device_error(const char *what);
 template <typename T>
 hipError_t launch_x2_step(int N, Rot3<T> bufs, const SP2State *st, bool with_u, T tau,
                           const StepScratch &s, hipStream_t stream);
+// The standalone step with the hashed row accumulator (ell_kernels.hip) for
+// rows with at most 512 products, then the window kernel on the rows left in
+// `left` (N entries) / *nleft (one word, cleared here).
+template <typename T>
+hipError_t launch_x2_hash(int N, Rot3<T> bufs, bool with_u, T tau, const StepScratch &s, int32_t *left,
+                          int32_t *nleft, hipStream_t stream);
 hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream);
 hipError_t launch_decide(SP2State *st, SP2Cfg cfg, SP2Hist hist, const StepScratch &s,
                          hipStream_t stream);

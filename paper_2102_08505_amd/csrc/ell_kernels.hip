@@ -395,9 +395,10 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
   return (b % kXcd) * per + b / kXcd;
 }
 
+// rows: null (row = wave index), or a list of *nrows rows to compute.
 template <typename T, bool WITH_U>
 __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2State *st, T tau,
-                                                 StepScratch s)
+                                                 StepScratch s, const int32_t *rows, const int32_t *nrows)
 {
   __shared__ T acc_s[kWavesPerBlock][kWin];
   __shared__ T xw_s[kWavesPerBlock][kWin];
@@ -410,12 +411,290 @@ __global__ __launch_bounds__(256) void k_x2_step(int N, Rot3<T> bufs, const SP2S
     once = st->once != 0;
   }
   const int w = uniform_i(threadIdx.x >> 6);
-  const int i = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  int i = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  if (rows) {
+    if (i >= *nrows) return;
+    i = uniform_i(rows[i]);
+  }
   if (i >= N) return;
   const EllView<T> X = bufs.b[cur];
   const EllView<T> Y = bufs.b[cur == 2 ? 0 : cur + 1];
   const EllView<T> U = bufs.b[cur == 0 ? 2 : cur - 1];
   x2_row<T, WITH_U>(i, X.nnz, X.idx, X.val, X.M, Y, U, tau, once, acc_s[w], xw_s[w], stk_s[w], s);
+}
+
+// --------------------------------------------------------------------------
+// the same row product with a hashed accumulator
+// --------------------------------------------------------------------------
+// For rows whose products are few and spread over a wide column range (the
+// window kernel would sweep every 64-column block of the range): the row's
+// distinct columns -- those of the rows k it references and its own -- go
+// into an open-addressing table in LDS, are sorted (bitonic), and each gets
+// its accumulator slot; the products are then added with fma in ascending k as
+// in the window kernel, and the sorted columns are swept 64 at a time.  The
+// norm's tree over column positions is built from the aligned 64-column
+// blocks that hold columns, in ascending order; a block that holds none is a
+// +0 subtree (x + 0 == x for these sums of squares), so the blocks combine at
+// their lowest common ancestors, with the same bits as the window kernel.
+// Rows with more than kHashCols products go to a list for the window kernel.
+constexpr int kHashSlots = 1024;  // table slots per wave (a power of two)
+constexpr int kHashCols = 512;    // products (and so distinct columns) a row may have here
+
+template <typename T>
+struct HashArena {
+  int32_t key[kHashSlots];  // column, or -1
+  int32_t pos[kHashSlots];  // position of the slot's column in col
+  int32_t col[kHashCols];   // the row's columns, ascending
+  T acc[kHashCols];         // (X.X)_ij at those columns
+  T xv[kHashCols];          // X_ij at those columns
+  double blk[kWave];        // squared differences of one aligned 64-column block
+  double sv[kLev + 1];      // the norm's stack of subtree sums ...
+  int32_t sl[kLev + 1];     // ... and the level at which each joins its left neighbour
+};
+
+__device__ __forceinline__ int hash_slot(int j) { return (int)(((uint32_t)j * 2654435761u) >> 22); }
+
+// inserts j; true if it was not there
+__device__ __forceinline__ bool hash_insert(int32_t *key, int j)
+{
+  int h = hash_slot(j);
+  for (;;) {
+    int expect = -1;
+    if (__hip_atomic_compare_exchange_strong(&key[h], &expect, j, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WAVEFRONT))
+      return true;
+    if (expect == j) return false;
+    h = (h + 1) & (kHashSlots - 1);
+  }
+}
+// slot of j, or -1 when j is not in the table
+__device__ __forceinline__ int hash_find(const int32_t *key, int j)
+{
+  int h = hash_slot(j);
+  for (;;) {
+    const int k = key[h];
+    if (k == j) return h;
+    if (k < 0) return -1;
+    h = (h + 1) & (kHashSlots - 1);
+  }
+}
+
+// Block b (ascending, any gaps) with total t joins the norm's tree: stack
+// entries whose lowest common ancestor with their left neighbour lies below
+// the one of b with the previous block form complete subtrees and are summed
+// (left + right) first.  Lane 0.
+template <typename T>
+__device__ __forceinline__ void push_lca(HashArena<T> &ar, int &depth, int &prev, const int b, const double t)
+{
+  const int L = depth ? 32 - __builtin_clz((unsigned)(prev ^ b)) : INT_MAX;
+  while (depth >= 2 && ar.sl[depth - 1] < L) {
+    ar.sv[depth - 2] = ar.sv[depth - 2] + ar.sv[depth - 1];
+    --depth;
+  }
+  ar.sv[depth] = t;
+  ar.sl[depth] = L;
+  ++depth;
+  prev = b;
+}
+
+template <typename T, bool WITH_U>
+__global__ __launch_bounds__(256) void k_x2_hash(int N, Rot3<T> bufs, T tau, StepScratch s, int32_t *left,
+                                                 int32_t *nleft)
+{
+  __shared__ HashArena<T> ar_s[kWavesPerBlock];
+  const int w = uniform_i(threadIdx.x >> 6), lane = lane_id();
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+  if (i >= N) return;
+  HashArena<T> &ar = ar_s[w];
+  const EllView<T> X = bufs.b[0], Y = bufs.b[1], U = bufs.b[2];
+  const int M = X.M;
+  const int wi = uniform_i(X.nnz[i]);
+  const int32_t *ci = X.idx + (size_t)i * M;
+  const T *vi = X.val + (size_t)i * M;
+
+  // products of the row (an upper bound on its distinct columns with wi)
+  int P = 0;
+  for (int s0 = 0; s0 < wi; s0 += kWave) {
+    const int sl = s0 + lane;
+    if (sl < wi) P += X.nnz[ci[sl]];
+  }
+  for (int o = 32; o > 0; o >>= 1) P += __shfl_xor(P, o, kWave);
+  if (uniform_i(P) + wi > kHashCols) {
+    if (lane == 0) left[atomicAdd(nleft, 1)] = i;
+    return;
+  }
+
+  // the set of columns
+  for (int h = lane; h < kHashSlots; h += kWave) ar.key[h] = -1;
+  wave_sync();
+  int E = 0;
+  for (int s0 = 0; s0 < wi; s0 += kWave) {
+    const int sl = s0 + lane;
+    const bool ins = sl < wi && hash_insert(ar.key, ci[sl]);
+    E += __popcll(__ballot(ins));
+  }
+  for (int s1 = 0; s1 < wi; ++s1) {
+    const int k = uniform_i(ci[s1]);
+    const int nk = uniform_i(X.nnz[k]);
+    const int32_t *ck = X.idx + (size_t)k * M;
+    for (int t0 = 0; t0 < nk; t0 += kWave) {
+      const int t = t0 + lane;
+      const bool ins = t < nk && hash_insert(ar.key, ck[t]);
+      E += __popcll(__ballot(ins));
+    }
+  }
+  wave_sync();
+  E = uniform_i(E);
+
+  // sorted columns and their slots
+  int E2 = 1;
+  while (E2 < E) E2 <<= 1;
+  {
+    int base = 0;
+    for (int h0 = 0; h0 < kHashSlots; h0 += kWave) {
+      const int key = ar.key[h0 + lane];
+      const uint64_t m = __ballot(key >= 0);
+      if (key >= 0) ar.col[base + lanes_below(m)] = key;
+      base += __popcll(m);
+    }
+    for (int q = E + lane; q < E2; q += kWave) ar.col[q] = INT_MAX;
+    wave_sync();
+  }
+  for (int size = 2; size <= E2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int p = lane; p < E2 / 2; p += kWave) {
+        const int lo = 2 * stride * (p / stride) + (p % stride), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int a = ar.col[lo], b = ar.col[hi];
+        if ((a > b) == up) {
+          ar.col[lo] = b;
+          ar.col[hi] = a;
+        }
+      }
+      wave_sync();
+    }
+  for (int q = lane; q < E; q += kWave) {
+    ar.pos[hash_find(ar.key, ar.col[q])] = q;
+    ar.acc[q] = T(0);
+    ar.xv[q] = T(0);
+  }
+  wave_sync();
+
+  // X's own row, then the products, k ascending (the columns of one row k are
+  // distinct, so lanes never meet in a slot)
+  double d1 = 0.0;
+  bool has_diag = false;
+  for (int s0 = 0; s0 < wi; s0 += kWave) {
+    const int sl = s0 + lane;
+    if (sl < wi) {
+      const int c = ci[sl];
+      ar.xv[ar.pos[hash_find(ar.key, c)]] = vi[sl];
+      if (c == i) {
+        has_diag = true;
+        d1 = (double)vi[sl];
+      }
+    }
+  }
+  const uint64_t dm = __ballot(has_diag);
+  if (dm) d1 = __shfl(d1, __builtin_ctzll(dm), kWave);
+  wave_sync();
+  for (int s1 = 0; s1 < wi; ++s1) {
+    const int k = uniform_i(ci[s1]);
+    const T a = vi[s1];
+    const int nk = uniform_i(X.nnz[k]);
+    const int32_t *ck = X.idx + (size_t)k * M;
+    const T *vk = X.val + (size_t)k * M;
+    for (int t = lane; t < nk; t += kWave) {
+      const int q = ar.pos[hash_find(ar.key, ck[t])];
+      ar.acc[q] = fmadd(a, vk[t], ar.acc[q]);
+    }
+    wave_sync();
+  }
+  double d2 = 0.0;
+  {
+    const int h = hash_find(ar.key, i);
+    if (h >= 0) d2 = (double)ar.acc[ar.pos[h]];
+  }
+
+  // sweep the sorted columns
+  int cy = 0, cu = 0;
+  int depth = 0, prev = 0, cb = -1;
+  ar.blk[lane] = 0.0;
+  wave_sync();
+  for (int q0 = 0; q0 < E; q0 += kWave) {
+    const int q = q0 + lane;
+    const bool in = q < E;
+    const int j = in ? ar.col[q] : INT_MAX;
+    const T y = in ? ar.acc[q] : T(0);
+    const T x = in ? ar.xv[q] : T(0);
+    const bool ky = in && absv(y) > tau;
+    const uint64_t my = __ballot(ky);
+    if (ky) {
+      const int p = cy + lanes_below(my);
+      if (p < Y.M) {
+        Y.idx[(size_t)i * Y.M + p] = j;
+        Y.val[(size_t)i * Y.M + p] = y;
+      }
+    }
+    cy += __popcll(my);
+    const T yk = ky ? y : T(0);
+    if (WITH_U) {
+      const T v = T(2) * x - yk;
+      const bool ku = in && absv(v) > tau;
+      const uint64_t mu = __ballot(ku);
+      if (ku) {
+        const int p = cu + lanes_below(mu);
+        if (p < U.M) {
+          U.idx[(size_t)i * U.M + p] = j;
+          U.val[(size_t)i * U.M + p] = v;
+        }
+      }
+      cu += __popcll(mu);
+    }
+    const double dd = (double)yk - (double)x;
+    const double sq = dd * dd;
+    // the chunk's blocks in ascending order
+    const int b = in ? (j >> 6) : INT_MAX;
+    uint64_t todo = __ballot(in);
+    while (todo) {
+      const int bb = uniform_i(__shfl(b, (int)__builtin_ctzll(todo), kWave));
+      if (bb != cb) {
+        if (cb >= 0) {
+          const double t = wave_tree(ar.blk[lane]);
+          if (lane == 0) push_lca(ar, depth, prev, cb, t);
+          wave_sync();
+          ar.blk[lane] = 0.0;
+          wave_sync();
+        }
+        cb = bb;
+      }
+      if (in && b == bb) ar.blk[j & 63] = sq;
+      wave_sync();
+      todo &= ~__ballot(in && b == bb);
+    }
+  }
+  if (cb >= 0) {
+    const double t = wave_tree(ar.blk[lane]);
+    if (lane == 0) push_lca(ar, depth, prev, cb, t);
+  }
+  if (lane == 0) {
+    while (depth >= 2) {
+      ar.sv[depth - 2] = ar.sv[depth - 2] + ar.sv[depth - 1];
+      --depth;
+    }
+    const double ev = depth ? ar.sv[0] : 0.0;
+    Y.nnz[i] = min(cy, Y.M);
+    s.wy[i] = cy;
+    if (WITH_U) {
+      U.nnz[i] = min(cu, U.M);
+      s.wu[i] = cu;
+    } else {
+      s.wu[i] = 0;
+    }
+    s.d1[i] = d1;
+    s.d2[i] = d2;
+    s.e[i] = ev;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -854,16 +1133,43 @@ hipError_t launch_x2_step(int N, Rot3<T> bufs, const SP2State *st, bool with_u, 
                           const StepScratch &s, hipStream_t stream)
 {
   const dim3 grid((N + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
+  const int32_t *none = nullptr;
   if (with_u)
-    hipLaunchKernelGGL((k_x2_step<T, true>), grid, block, 0, stream, N, bufs, st, tau, s);
+    hipLaunchKernelGGL((k_x2_step<T, true>), grid, block, 0, stream, N, bufs, st, tau, s, none, none);
   else
-    hipLaunchKernelGGL((k_x2_step<T, false>), grid, block, 0, stream, N, bufs, st, tau, s);
+    hipLaunchKernelGGL((k_x2_step<T, false>), grid, block, 0, stream, N, bufs, st, tau, s, none, none);
   return hipGetLastError();
 }
 template hipError_t launch_x2_step<double>(int, Rot3<double>, const SP2State *, bool, double,
                                            const StepScratch &, hipStream_t);
 template hipError_t launch_x2_step<float>(int, Rot3<float>, const SP2State *, bool, float,
                                           const StepScratch &, hipStream_t);
+
+template <typename T>
+hipError_t launch_x2_hash(int N, Rot3<T> bufs, bool with_u, T tau, const StepScratch &s, int32_t *left,
+                          int32_t *nleft, hipStream_t stream)
+{
+  const dim3 grid((N + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
+  hipError_t e = launch_zero_words(1, nleft, stream);
+  if (e != hipSuccess) return e;
+  if (with_u)
+    hipLaunchKernelGGL((k_x2_hash<T, true>), grid, block, 0, stream, N, bufs, tau, s, left, nleft);
+  else
+    hipLaunchKernelGGL((k_x2_hash<T, false>), grid, block, 0, stream, N, bufs, tau, s, left, nleft);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the rows the table could not take, on the window kernel
+  if (with_u)
+    hipLaunchKernelGGL((k_x2_step<T, true>), grid, block, 0, stream, N, bufs, (const SP2State *)nullptr, tau, s,
+                       (const int32_t *)left, (const int32_t *)nleft);
+  else
+    hipLaunchKernelGGL((k_x2_step<T, false>), grid, block, 0, stream, N, bufs, (const SP2State *)nullptr, tau, s,
+                       (const int32_t *)left, (const int32_t *)nleft);
+  return hipGetLastError();
+}
+template hipError_t launch_x2_hash<double>(int, Rot3<double>, bool, double, const StepScratch &, int32_t *,
+                                           int32_t *, hipStream_t);
+template hipError_t launch_x2_hash<float>(int, Rot3<float>, bool, float, const StepScratch &, int32_t *, int32_t *,
+                                          hipStream_t);
 
 hipError_t launch_reduce(int N, const SP2State *st, const StepScratch &s, hipStream_t stream)
 {

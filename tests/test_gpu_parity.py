@@ -135,6 +135,43 @@ def test_x2_step_row_windows_wider_than_12288_columns(f32):
 
 
 @pytest.mark.parametrize("f32", [False, True])
+def test_x2_step_hashed_and_window_rows_in_one_product(f32):
+    """A scattered pattern (a handful of entries per row spread over the
+    whole row) goes to the hashed row accumulator; two full rows, and the few
+    rows that reference them, have more products than its table takes and go
+    to the window kernel in the same call.  Both against the oracle, bit for bit."""
+    N = 4000
+    A = long_range_ell(N, (1, 977, 2011), seed=72)
+    D = np.zeros((N, N))
+    for i, (c, v) in enumerate(A.rows()):
+        D[i, c] = v
+    rng = np.random.default_rng(73)
+    for r in (100, 2500):
+        D[r, :] = rng.uniform(-1, 1, N) * 1e-2
+    nnz, idx, val, M = synth.dense_to_ell(D)
+    if f32:
+        val = val.astype(np.float32)
+    A = oracle.Ell(N, M, nnz, idx, val)
+    tau = np.float32(1e-4) if f32 else 1e-4
+    prec = E.ELL_F32 if f32 else E.ELL_F64
+    rc, Y, d1, d2, wy = oracle.x2(A, tau, M2=N)
+    assert rc == 0
+    X = dev_from_oracle(A, prec)
+    Yd = E.DeviceEll(N, N, prec)
+    U = E.DeviceEll(N, N, prec)
+    rc, out, widths = E.ellpack_x2_step(X.h, Yd.h, U.h, tau)
+    assert rc == E.ELL_OK, E.ellpack_strerror(rc)
+    assert widths[0] == wy
+    assert_same_rows(oracle_from_dev(Yd, f32), Y, "X^2")
+    eta2, _ = oracle.norm2(A, Y)
+    assert same_float(out[2], eta2)
+    assert same_float(out[0], oracle.pairwise(d1)) and same_float(out[1], oracle.pairwise(d2))
+    rcu, Uo, wu = oracle.update(A, Y, tau, Mo=N)
+    assert rcu == 0 and widths[1] == wu
+    assert_same_rows(oracle_from_dev(U, f32), Uo, "2X - X^2")
+
+
+@pytest.mark.parametrize("f32", [False, True])
 @pytest.mark.parametrize("sparse_rows", [False, True])
 def test_x2_step_subnormal_operands_tau0(f32, sparse_rows):
     """tau = 0 keeps every nonzero, so products that land in the subnormal
