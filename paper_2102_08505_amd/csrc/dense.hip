@@ -102,6 +102,7 @@ __global__ __launch_bounds__(256) void k_split(int N, DSel<float> sel, uint16_t 
     th[ty + 8 * q][tx] = h;
     tl[ty + 8 * q][tx] = l;
   }
+  if (!hiT) return;  // (a symmetric X is its own transpose)
   __syncthreads();
   for (int q = 0; q < 4; ++q) {
     const int r = c0 + ty + 8 * q, c = r0 + tx;  // position in the transpose
@@ -183,16 +184,25 @@ __device__ __forceinline__ void fetch_tiles(int N, const uint16_t *const (&src)[
     }
 }
 
-template <bool VEC>
+// SYM (X symmetric): X is its own transpose, so the B operands come from hi
+// and lo themselves; only the tiles on and above the diagonal are computed,
+// each written to its place and to its mirror image (the split products
+// hi.lo and lo.hi then give C a symmetric rounding as well).
+template <bool VEC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__restrict__ hi,
                                                      const uint16_t *__restrict__ lo,
                                                      const uint16_t *__restrict__ hiT,
                                                      const uint16_t *__restrict__ loT, DSel<float> sel)
 {
   __shared__ __attribute__((aligned(16))) uint16_t T4[4][kBM][kLdsK];  // A hi, A lo, B hi, B lo
+  if (SYM && blockIdx.y > blockIdx.x) return;
   const float *unused;
   float *C;
   if (!resolve(sel, unused, C)) return;
+  if (SYM) {
+    hiT = hi;
+    loT = lo;
+  }
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int row0 = blockIdx.y * kBM, col0 = blockIdx.x * kBM;
@@ -255,7 +265,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
       for (int e = 0; e < 16; ++e) {
         const int r = row0 + wm * 64 + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const int c = col0 + wn * 64 + b * 32 + (lane & 31);
-        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
+        if (r < N && c < N) {
+          C[(size_t)r * N + c] = acc[a][b][e];
+          if (SYM && blockIdx.x != blockIdx.y) C[(size_t)c * N + r] = acc[a][b][e];
+        }
       }
 }
 
@@ -288,13 +301,19 @@ __device__ __forceinline__ void fetch_pair(int N, const double *__restrict__ src
   v1 = gr < N && gk + 1 < N ? src[(size_t)gr * N + gk + 1] : 0.0;
 }
 
-template <bool VEC>
+// SYM (X bitwise symmetric): X is its own transpose, and C = X.X is bitwise
+// symmetric (C_ji sums the products of C_ij in the same k order), so only the
+// tiles on and above the diagonal are computed, each written to its place and
+// to its mirror image, with the same bits as the whole product.
+template <bool VEC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restrict__ AT, DSel<double> sel)
 {
   __shared__ double As[kDM][kDK + 1], Bs[kDM][kDK + 1];
+  if (SYM && blockIdx.y > blockIdx.x) return;
   const double *A;
   double *C;
   if (!resolve(sel, A, C)) return;
+  if (SYM) AT = A;
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int row0 = blockIdx.y * kDM, col0 = blockIdx.x * kDM;
@@ -355,7 +374,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restric
       for (int e = 0; e < 4; ++e) {
         const int r = row0 + wm * 64 + a * 16 + (lane >> 4) + 4 * e;
         const int c = col0 + wn * 64 + b * 16 + (lane & 15);
-        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
+        if (r < N && c < N) {
+          C[(size_t)r * N + c] = acc[a][b][e];
+          if (SYM && blockIdx.x != blockIdx.y) C[(size_t)c * N + r] = acc[a][b][e];
+        }
       }
 }
 
@@ -453,29 +475,58 @@ struct DMem {
     if (e_ != hipSuccess) return device_error(e_, #expr);   \
   } while (0)
 
+// sym: X is bitwise symmetric (no transposed copies; the upper triangle of
+// tiles, mirrored)
 hipError_t product_f32(int N, DSel<float> sel, uint16_t *hi, uint16_t *lo, uint16_t *hiT, uint16_t *loT,
-                       hipStream_t s)
+                       hipStream_t s, bool sym = false)
 {
   const dim3 tb((N + 31) / 32, (N + 31) / 32);
-  hipLaunchKernelGGL(k_split, tb, dim3(256), 0, s, N, sel, hi, lo, hiT, loT);
+  hipLaunchKernelGGL(k_split, tb, dim3(256), 0, s, N, sel, hi, lo, sym ? nullptr : hiT, sym ? nullptr : loT);
   const dim3 gb((N + kBM - 1) / kBM, (N + kBM - 1) / kBM);
-  if (N % 8 == 0)
-    hipLaunchKernelGGL(k_gemm_bf16x3<true>, gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
-  else
-    hipLaunchKernelGGL(k_gemm_bf16x3<false>, gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+  if (N % 8 == 0) {
+    if (sym) hipLaunchKernelGGL((k_gemm_bf16x3<true, true>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+    else hipLaunchKernelGGL((k_gemm_bf16x3<true, false>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+  } else {
+    if (sym) hipLaunchKernelGGL((k_gemm_bf16x3<false, true>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+    else hipLaunchKernelGGL((k_gemm_bf16x3<false, false>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
+  }
   return hipGetLastError();
 }
 
-hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s)
+hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s, bool sym = false)
 {
   const dim3 tb((N + 31) / 32, (N + 31) / 32);
-  hipLaunchKernelGGL(k_transpose64, tb, dim3(256), 0, s, N, sel, XT);
+  if (!sym) hipLaunchKernelGGL(k_transpose64, tb, dim3(256), 0, s, N, sel, XT);
   const dim3 gb((N + kDM - 1) / kDM, (N + kDM - 1) / kDM);
-  if (N % 2 == 0)
-    hipLaunchKernelGGL(k_gemm_f64<true>, gb, dim3(256), 0, s, N, XT, sel);
-  else
-    hipLaunchKernelGGL(k_gemm_f64<false>, gb, dim3(256), 0, s, N, XT, sel);
+  if (N % 2 == 0) {
+    if (sym) hipLaunchKernelGGL((k_gemm_f64<true, true>), gb, dim3(256), 0, s, N, XT, sel);
+    else hipLaunchKernelGGL((k_gemm_f64<true, false>), gb, dim3(256), 0, s, N, XT, sel);
+  } else {
+    if (sym) hipLaunchKernelGGL((k_gemm_f64<false, true>), gb, dim3(256), 0, s, N, XT, sel);
+    else hipLaunchKernelGGL((k_gemm_f64<false, false>), gb, dim3(256), 0, s, N, XT, sel);
+  }
   return hipGetLastError();
+}
+
+// flag |= 1 if some A[r][c] and A[c][r] differ in their bits (32 x 32 tiles)
+__global__ __launch_bounds__(256) void k_dense_asym(int N, const double *__restrict__ A, int32_t *flag)
+{
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  if (blockIdx.y > blockIdx.x) return;  // each pair of tiles once
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    t[ty + 8 * q][tx] = (r < N && c < N) ? A[(size_t)r * N + c] : 0.0;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int q = 0; q < 4; ++q) {
+    const int r = c0 + ty + 8 * q, c = r0 + tx;  // A[r][c] against A[c][r] of the tile above
+    if (r < N && c < N)
+      bad |= __double_as_longlong(A[(size_t)r * N + c]) != __double_as_longlong(t[tx][ty + 8 * q]);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
 }  // namespace
@@ -533,10 +584,22 @@ extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_
   hipLaunchKernelGGL(k_dense_gersh, dim3((N + 255) / 256), dim3(256), 0, s, N, d_H, (double *)glo.p,
                      (double *)ghi.p);
   DTRY(hipGetLastError());
+  // a bitwise symmetric H keeps every iterate bitwise symmetric (X0 is; X^2
+  // sums the same products for (i, j) and (j, i); 2X - X^2 is entrywise): the
+  // products then take the upper triangle of tiles only
+  DMem asym;
+  DTRY(asym.alloc(sizeof(int32_t)));
+  DTRY(hipMemsetAsync(asym.p, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_dense_asym, dim3((N + 31) / 32, (N + 31) / 32), dim3(256), 0, s, N, d_H,
+                     (int32_t *)asym.p);
+  DTRY(hipGetLastError());
   std::vector<double> hlo(N), hhi(N);
+  int32_t hasym = 0;
   DTRY(hipMemcpyAsync(hlo.data(), glo.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));
   DTRY(hipMemcpyAsync(hhi.data(), ghi.p, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  DTRY(hipMemcpyAsync(&hasym, asym.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   DTRY(hipStreamSynchronize(s));
+  const bool sym = hasym == 0;
   double emin = INFINITY, emax = -INFINITY;
   for (int i = 0; i < N; ++i) {
     if (!std::isfinite(hlo[i]) || !std::isfinite(hhi[i])) return ELL_ENONFINITE;
@@ -557,11 +620,13 @@ extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_
     for (auto &b : b32) DTRY(b.alloc(nn * 4));
     DTRY(hi.alloc(nn * 2));
     DTRY(lo.alloc(nn * 2));
-    DTRY(hiT.alloc(nn * 2));
-    DTRY(loT.alloc(nn * 2));
+    if (!sym) {  // (transposed copies: a symmetric X is its own transpose)
+      DTRY(hiT.alloc(nn * 2));
+      DTRY(loT.alloc(nn * 2));
+    }
   }
   for (auto &b : b64) DTRY(b.alloc(nn * 8));
-  DTRY(xt.alloc(nn * 8));
+  if (!sym) DTRY(xt.alloc(nn * 8));
   float *p32[3] = {(float *)b32[0].p, (float *)b32[1].p, (float *)b32[2].p};
   double *p64[3] = {(double *)b64[0].p, (double *)b64[1].p, (double *)b64[2].p};
   DTRY(ptrs32.alloc(sizeof(p32)));
@@ -662,9 +727,10 @@ extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_
     for (int q = 0; q < poll; ++q) {
       if (p->profile) DTRY(hipEventRecord(ev[2 + 2 * q], s));
       if (hs.phase32)
-        DTRY(product_f32(N, sel32, (uint16_t *)hi.p, (uint16_t *)lo.p, (uint16_t *)hiT.p, (uint16_t *)loT.p, s));
+        DTRY(product_f32(N, sel32, (uint16_t *)hi.p, (uint16_t *)lo.p, (uint16_t *)hiT.p, (uint16_t *)loT.p, s,
+                         sym));
       else
-        DTRY(product_f64(N, sel64, (double *)xt.p, s));
+        DTRY(product_f64(N, sel64, (double *)xt.p, s, sym));
       if (p->profile) DTRY(hipEventRecord(ev[3 + 2 * q], s));
       if (hs.phase32)
         hipLaunchKernelGGL((k_dense_rows<float>), rowgrid, dim3(256), 0, s, N, (float *const *)ptrs32.p, dst, sc);

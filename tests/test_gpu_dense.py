@@ -133,6 +133,22 @@ def test_dense_sp2_f64_matches_oracle(N, b):
     assert np.linalg.norm(D - P) < 1e-6
 
 
+def test_dense_sp2_f64_hamiltonian_not_bitwise_symmetric():
+    """One coupling's two sides one ulp apart: the solve takes the full
+    product (a transposed copy, every tile) instead of the mirrored upper
+    triangle, with the oracle's bits all the same."""
+    N = 257
+    H = synth.dense_hamiltonian(N, 8, seed=7)
+    H[3, 7] = np.nextafter(H[3, 7], np.inf)
+    assert H[3, 7] != H[7, 3]
+    rc, D, rep = _solve(H, E.DENSE_F64, 1e-8, N // 4)
+    orc, Do, ro = oracle.dense_sp2(H, oracle.DENSE_F64, _oracle_params(N // 4, 1e-8))
+    assert rc == orc == E.ELL_OK
+    for k in ("trx", "trx2", "eta2"):
+        assert np.array_equal(rep[k].view(np.uint64), ro[k].view(np.uint64)), k
+    assert np.array_equal(D.view(np.uint64), Do.view(np.uint64))
+
+
 @pytest.mark.parametrize("N,b", [(128, 4), (300, 6)])
 def test_dense_sp2_bf16x3_reaches_fp64_accuracy(N, b):
     H = synth.dense_hamiltonian(N, b, seed=11)
