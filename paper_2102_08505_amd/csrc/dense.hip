@@ -185,9 +185,9 @@ __device__ __forceinline__ void fetch_tiles(int N, const uint16_t *const (&src)[
 }
 
 // SYM (X symmetric): X is its own transpose, so the B operands come from hi
-// and lo themselves; only the tiles on and above the diagonal are computed,
-// each written to its place and to its mirror image (the split products
-// hi.lo and lo.hi then give C a symmetric rounding as well).
+// and lo themselves, and only the tiles on and above the diagonal are
+// computed; k_mirror copies them below it (the split products hi.lo and lo.hi
+// then give C a symmetric rounding as well).
 template <bool VEC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__restrict__ hi,
                                                      const uint16_t *__restrict__ lo,
@@ -265,10 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
       for (int e = 0; e < 16; ++e) {
         const int r = row0 + wm * 64 + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const int c = col0 + wn * 64 + b * 32 + (lane & 31);
-        if (r < N && c < N) {
-          C[(size_t)r * N + c] = acc[a][b][e];
-          if (SYM && blockIdx.x != blockIdx.y) C[(size_t)c * N + r] = acc[a][b][e];
-        }
+        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
       }
 }
 
@@ -303,8 +300,8 @@ __device__ __forceinline__ void fetch_pair(int N, const double *__restrict__ src
 
 // SYM (X bitwise symmetric): X is its own transpose, and C = X.X is bitwise
 // symmetric (C_ji sums the products of C_ij in the same k order), so only the
-// tiles on and above the diagonal are computed, each written to its place and
-// to its mirror image, with the same bits as the whole product.
+// tiles on and above the diagonal are computed; k_mirror copies them below it,
+// with the same bits as the whole product.
 template <bool VEC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restrict__ AT, DSel<double> sel)
 {
@@ -374,11 +371,31 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restric
       for (int e = 0; e < 4; ++e) {
         const int r = row0 + wm * 64 + a * 16 + (lane >> 4) + 4 * e;
         const int c = col0 + wn * 64 + b * 16 + (lane & 15);
-        if (r < N && c < N) {
-          C[(size_t)r * N + c] = acc[a][b][e];
-          if (SYM && blockIdx.x != blockIdx.y) C[(size_t)c * N + r] = acc[a][b][e];
-        }
+        if (r < N && c < N) C[(size_t)r * N + c] = acc[a][b][e];
       }
+}
+
+// The part of C below the GEMM's diagonal tiles (row tile above column tile,
+// in tiles of TILE) from its transpose above them, 32 x 32 blocks through LDS.
+template <typename T, int TILE>
+__global__ __launch_bounds__(256) void k_mirror(int N, DSel<T> sel)
+{
+  __shared__ T t[32][33];
+  if ((int)(blockIdx.y * 32) / TILE <= (int)(blockIdx.x * 32) / TILE) return;  // computed by the GEMM
+  const T *unused;
+  T *C;
+  if (!resolve(sel, unused, C)) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;  // the block to fill
+  for (int q = 0; q < 4; ++q) {
+    const int r = c0 + ty + 8 * q, c = r0 + tx;  // its transpose
+    t[ty + 8 * q][tx] = (r < N && c < N) ? C[(size_t)r * N + c] : T(0);
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    if (r < N && c < N) C[(size_t)r * N + c] = t[tx][ty + 8 * q];
+  }
 }
 
 // ---- per-row step outputs: U = 2X - Y, diagonals, norm row term ---------------------
@@ -490,6 +507,7 @@ hipError_t product_f32(int N, DSel<float> sel, uint16_t *hi, uint16_t *lo, uint1
     if (sym) hipLaunchKernelGGL((k_gemm_bf16x3<false, true>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
     else hipLaunchKernelGGL((k_gemm_bf16x3<false, false>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
   }
+  if (sym) hipLaunchKernelGGL((k_mirror<float, kBM>), tb, dim3(256), 0, s, N, sel);
   return hipGetLastError();
 }
 
@@ -505,6 +523,7 @@ hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s, bool 
     if (sym) hipLaunchKernelGGL((k_gemm_f64<false, true>), gb, dim3(256), 0, s, N, XT, sel);
     else hipLaunchKernelGGL((k_gemm_f64<false, false>), gb, dim3(256), 0, s, N, XT, sel);
   }
+  if (sym) hipLaunchKernelGGL((k_mirror<double, kDM>), tb, dim3(256), 0, s, N, sel);
   return hipGetLastError();
 }
 
