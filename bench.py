@@ -726,24 +726,22 @@ def main():
                      "bytes_per_launch": prof["x2_bytes"] / launches,
                      "alu": alu},
     }
-    if not args.no_fp64_target:
-        line["fp64_to_1e-8"] = fp64_target_leg(E, H, torch)
-    if not args.no_prune_mode:
-        line["prune_modes"] = prune_mode_leg(E, synth, torch, H)
-    if not args.no_nonbanded:
-        line["nonbanded"] = nonbanded_leg(E, synth, torch)
-    if not args.no_x2_single:
-        line["x2_single_tau1e-5"] = x2_single_leg(E, H)
-    if not args.no_batched:
-        line["batched"] = batched_leg(E, synth, torch)
-    if not args.no_dense:
-        line["dense"] = dense_leg(E, synth, torch)
-    if not args.no_accuracy:
-        line["mixed_accuracy"] = accuracy_leg(E, synth, torch)
-    if not args.no_model:
-        line["model_hamiltonians"] = model_leg(E, synth, torch)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    legs = (("fp64_to_1e-8", args.no_fp64_target, lambda: fp64_target_leg(E, H, torch)),
+            ("prune_modes", args.no_prune_mode, lambda: prune_mode_leg(E, synth, torch, H)),
+            ("nonbanded", args.no_nonbanded, lambda: nonbanded_leg(E, synth, torch)),
+            ("x2_single_tau1e-5", args.no_x2_single, lambda: x2_single_leg(E, H)),
+            ("batched", args.no_batched, lambda: batched_leg(E, synth, torch)),
+            ("dense", args.no_dense, lambda: dense_leg(E, synth, torch)),
+            ("mixed_accuracy", args.no_accuracy, lambda: accuracy_leg(E, synth, torch)),
+            ("model_hamiltonians", args.no_model, lambda: model_leg(E, synth, torch)),
+            ("cpu_baseline", args.no_cpu, lambda: cpu_baseline(args.cpu_seconds)))
+    for name, skip, leg in legs:
+        if skip:
+            continue
+        t0 = time.perf_counter()
+        line[name] = leg()
+        # progress on stderr (stdout carries the one JSON line)
+        print(f"bench: {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
