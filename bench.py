@@ -229,6 +229,8 @@ def batched_leg(E, synth, torch, count=256):
                         f"half-bandwidth max(4, N/32), mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}, "
                         f"to ||X^2-X||_F<{TARGET:g}",
             "status": int(rc_b), "ok": sum(1 for r in reps_b if r["status"] == 0),
+            "tuned": {"iterations_per_graph": reps_b[0]["batch_k"],
+                      "step_kernel": "register-tiled VALU" if reps_b[0]["batch_kernel"] else "matrix cores"},
             "batched_ms": tb * 1e3, "sequential_ms": ts * 1e3, "speedup_vs_sequential": ts / tb,
             "max_iterations": max(r["iterations"] for r in reps_b),
             "max_eta": max(r["eta"] for r in reps_b),

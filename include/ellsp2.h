@@ -209,6 +209,9 @@ typedef struct {
      (dense_sp2_solve: the duration of each product and its bytes, p->profile != 0 only) */
   double *hist_x2_seconds;
   int64_t *hist_x2_bytes;
+  int32_t batch_k;         /* sp2_solve_batched: iterations per graph replay it used; else 0 */
+  int32_t batch_kernel;    /* sp2_solve_batched: its step kernel, 0 matrix cores, 1 register-tiled
+                              VALU (the same results); else 0 */
 } sp2_report_t;
 
 /* SP2 purification of the FP64 Hamiltonian H into the density matrix D
@@ -227,7 +230,10 @@ int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p, sp2_repor
  * kernel over all of them, replayed from a captured HIP graph of K iterations,
  * with per-instance state (buffers, precision phase, stop) on the device.
  * p: n parameter sets (one per instance); p[0].poll_every = K, or 0 to pick K
- * by timing the first graph replays.  Each instance's result, history and
+ * and then the step kernel (matrix cores or register-tiled VALU) by timing the
+ * first graph replays; that choice is kept for the life of the process per
+ * device architecture, precision mix and size class (log2 of the stacked rows
+ * and of the row stride), and later calls of the same class replay at once.  Each instance's result, history and
  * status are bit-identical to sp2_solve on it alone; an instance the stacked
  * form cannot hold (X0 with exact zeros or rows wider than 65536 columns, or a
  * stride overflow beyond that) is finished by sp2_solve on its own.  r: n

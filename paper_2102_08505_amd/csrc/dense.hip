@@ -591,6 +591,7 @@ extern "C" int dense_sp2_solve(const double *d_H, int32_t N, double *d_D, int32_
     r->eta = r->trace_x = r->emin = r->emax = r->seconds = r->x2_seconds = 0.0;
     r->x2_bytes = 0;
     r->x2_launches = 0;
+    r->batch_k = r->batch_kernel = 0;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const size_t nn = (size_t)N * N;

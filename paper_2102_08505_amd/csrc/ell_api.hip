@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -1138,6 +1139,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     r->x2_seconds = 0.0;
     r->x2_bytes = 0;
     r->x2_launches = 0;
+    r->batch_k = r->batch_kernel = 0;
   }
   rc = ensure_valid(H);
   if (rc) return rc;
@@ -1590,6 +1592,51 @@ struct BatchInst {
   bool solo = false;         // finished by sp2_solve on its own (the batch cannot hold it)
 };
 
+// What the batched solve's tuner chose -- graph length and step kernel -- per
+// device architecture, precision mix and size class (log2 of the stacked rows
+// and of the row stride), kept for the life of the process.
+struct BatchTune {
+  int K = 0, kernel = 0;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, BatchTune>> g_tune;
+
+std::string batch_tune_key(int NT, int SW, bool any32)
+{
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  auto lg = [](int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+  };
+  return arch + (any32 ? "|mixed|" : "|f64|") + std::to_string(lg(NT)) + "|" + std::to_string(lg(SW));
+}
+
+bool batch_tune_get(const std::string &key, BatchTune *t)
+{
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto &e : g_tune)
+    if (e.first == key) {
+      *t = e.second;
+      return true;
+    }
+  return false;
+}
+
+void batch_tune_put(const std::string &key, BatchTune t)
+{
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto &e : g_tune)
+    if (e.first == key) {
+      e.second = t;
+      return;
+    }
+  g_tune.emplace_back(key, t);
+}
+
 struct Batch {
   hipStream_t st = nullptr;
   int n = 0, NT = 0, ngroups = 0, nblocks = 0, SW = 0;
@@ -1604,6 +1651,8 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_iters = 0;
+  int kernel = 0;            // step kernel: 0 matrix cores, 1 register-tiled VALU (same results)
+  int graph_kernel = 0;      // the kernel the graph was captured with
   ~Batch()
   {
     drop_graph();
@@ -1646,10 +1695,10 @@ struct Batch {
     if (any32)
       HIP_TRY(launch_x2_band_batch<float>(ngroups, A32.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
                                           inst_rows.as<int32_t>(), stp, 1, taus32.as<float>(),
-                                          ss.as<StepScratch>(), flags.as<int32_t>(), st));
+                                          ss.as<StepScratch>(), flags.as<int32_t>(), st, kernel == 0));
     HIP_TRY(launch_x2_band_batch<double>(ngroups, A64.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
                                          inst_rows.as<int32_t>(), stp, 0, taus64.as<double>(), ss.as<StepScratch>(),
-                                         flags.as<int32_t>(), st));
+                                         flags.as<int32_t>(), st, kernel == 0));
     HIP_TRY(launch_reduce_batch(nblocks, blk_inst.as<int32_t>(), blk_local.as<int32_t>(), inst_rows.as<int32_t>(),
                                 ss.as<StepScratch>(), stp, st));
     HIP_TRY(launch_decide_batch(n, states.as<SP2State>(), cfgs.as<SP2Cfg>(), hists.as<SP2Hist>(),
@@ -1673,6 +1722,7 @@ struct Batch {
     graph = g;
     HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     graph_iters = iters;
+    graph_kernel = kernel;
     return ELL_OK;
   }
 };
@@ -1762,6 +1812,7 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
       r[q].eta = r[q].trace_x = r[q].emin = r[q].emax = r[q].seconds = r[q].x2_seconds = 0.0;
       r[q].x2_bytes = 0;
       r[q].x2_launches = 0;
+      r[q].batch_k = r[q].batch_kernel = 0;
     }
   if (n == 0) return ELL_OK;
   for (int32_t q = 0; q < n; ++q) {
@@ -2109,10 +2160,33 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   for (const BatchInst &I : B.in) max_iter_all = std::max<int64_t>(max_iter_all, p[I.q].max_iter);
   const int poll_hint = p[B.in[0].q].poll_every;
   const int candidates[] = {2, 4, 8, 16};
-  int K = poll_hint > 0 ? poll_hint : 0;  // 0: autotune
+  int K = poll_hint > 0 ? poll_hint : 0;  // 0: autotune (K, then the step kernel), unless cached
   int tune = 0;
   double best = 0.0;
   int bestK = 4;
+  // after K: replays with the VALU kernel, the matrix cores, the VALU kernel
+  // (the middle one against the mean of the two around it, which cancels the
+  // steady growth of the rows), then the choice
+  const int kernel_trials[] = {1, 0, 1};
+  double trial_ms[3] = {0, 0, 0};
+  bool trial_fair[3] = {false, false, false};
+  int ktrial = 0;
+  const std::string tkey = batch_tune_key(B.NT, B.SW, B.any32);
+  bool kernel_tuned = K > 0;
+  if (const char *force = std::getenv("ELLSP2_BATCH_KERNEL")) {  // a fixed step kernel (tests)
+    if (force[0] == '0' || force[0] == '1') {
+      B.kernel = force[0] - '0';
+      kernel_tuned = true;
+    }
+  }
+  if (K == 0 && !kernel_tuned) {
+    BatchTune t;
+    if (batch_tune_get(tkey, &t)) {
+      K = t.K;
+      B.kernel = t.kernel;
+      kernel_tuned = true;
+    }
+  }
   hipEvent_t ta = nullptr, tb = nullptr;
   struct Ev2 {
     hipEvent_t &a, &b;
@@ -2134,8 +2208,10 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     for (int m = 0; m < B.n; ++m) running = running || !B.hs[m].stop;
     if (!running) break;
     const bool tuning = K == 0 && tune < 4;
+    const bool ktuning = !tuning && !kernel_tuned && ktrial < 3;
+    if (ktuning) B.kernel = kernel_trials[ktrial];
     const int iters = K > 0 ? K : (tuning ? candidates[tune] : bestK);
-    if (!B.exec || B.graph_iters != iters) {
+    if (!B.exec || B.graph_iters != iters || B.graph_kernel != B.kernel) {
       int rc = B.capture(iters);
       if (rc) return rc;
     }
@@ -2159,6 +2235,21 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
         }
       }
       ++tune;
+    } else if (ktuning) {
+      int adv = 0;
+      for (int m = 0; m < B.n; ++m) adv = std::max(adv, B.hs[m].iter - before[m]);
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ta, tb));
+      trial_ms[ktrial] = ms / iters;
+      trial_fair[ktrial] = adv == iters;
+      if (++ktrial == 3) {
+        // keep the matrix cores unless both VALU samples around them were fair and faster
+        const bool valu = trial_fair[0] && trial_fair[1] && trial_fair[2] &&
+                          0.5 * (trial_ms[0] + trial_ms[2]) < trial_ms[1];
+        B.kernel = valu ? 1 : 0;
+        kernel_tuned = true;
+        batch_tune_put(tkey, BatchTune{bestK, B.kernel});
+      }
     }
     // events of stopped instances
     bool dirty = false;
@@ -2245,6 +2336,8 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     R.eta = std::sqrt(h.eta2);
     R.trace_x = h.trx;
     R.seconds = batch_ms * 1e-3;
+    R.batch_k = K > 0 ? K : bestK;
+    R.batch_kernel = B.kernel;
     int f32 = 0;
     int64_t bytes = 0;
     for (int q = 0; q < h.iter; ++q) {

@@ -226,11 +226,13 @@ hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wma
 // rows start at inst_r0[m] (a multiple of kBatchAlign) and it has inst_rows[m]
 // of them (local columns); per-instance state, drop tolerance, row-output
 // scratch view and fallback flag.  Takes the matrix-core kernel when the stack
-// fits its 2^31-byte buffer range.
+// fits its 2^31-byte buffer range and matrix_cores is set, else the
+// register-tiled VALU kernel (the same results).
 template <typename T>
 hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                 const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
-                                const StepScratch *ss, int32_t *flags, hipStream_t stream);
+                                const StepScratch *ss, int32_t *flags, hipStream_t stream,
+                                bool matrix_cores = true);
 constexpr int kGroupRows = 8;   // rows per wavefront of the register-tiled span step kernel
 constexpr int kBatchAlign = 16; // instance alignment in a batch: a whole number of both kernels' row groups
 template <typename TS, typename TD>

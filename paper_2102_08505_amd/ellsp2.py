@@ -47,7 +47,7 @@ class SP2Report(C.Structure):
                 ("hist_trx", f64p), ("hist_trx2", f64p), ("hist_eta2", f64p), ("hist_up", i8p),
                 ("hist_maxw", i32p), ("hist_prec", i8p), ("x2_seconds", C.c_double),
                 ("x2_bytes", C.c_int64), ("x2_launches", C.c_int32), ("hist_x2_seconds", f64p),
-                ("hist_x2_bytes", i64p)]
+                ("hist_x2_bytes", i64p), ("batch_k", C.c_int32), ("batch_kernel", C.c_int32)]
 
 
 _lib = None

@@ -171,3 +171,30 @@ def test_batched_256_instance_workload_sample_equals_single():
     rc_b, reps_b, Db, singles, _ = _run(inst, params)
     _check(rc_b, reps_b, Db, singles)
     assert all(r["status"] == E.ELL_OK for r in reps_b)
+
+
+def test_batched_register_tiled_kernel_gives_the_same_bits(monkeypatch):
+    """The tuner may pick the register-tiled VALU step kernel instead of the
+    matrix cores: forced here, every instance still equals its single solve."""
+    monkeypatch.setenv("ELLSP2_BATCH_KERNEL", "1")
+    specs = [(64, 4, 1), (257, 8, 3), (513, 16, 5), (130, 4, 10)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-8, 1e-6, mixed=(q % 2 == 1)) for q, (N, *_r) in enumerate(inst)]
+    rc_b, reps_b, Db, singles, Hs = _run(inst, params)
+    _check(rc_b, reps_b, Db, singles)
+    assert all(r["batch_kernel"] == 1 for r in reps_b)
+
+
+def test_batched_tuner_choice_is_reported_and_kept():
+    specs = [(300, 9, 21), (700, 20, 22), (1000, 31, 23), (150, 5, 24)]
+    inst = _instances(specs)
+    params = [_params(N, 1e-8, 1e-6, poll=0) for (N, *_r) in inst]
+    Hs = [E.DeviceEll.from_host(N, Mh, nnz, idx, val) for (N, Mh, nnz, idx, val) in inst]
+    choices = []
+    for _ in range(2):
+        Db = [E.DeviceEll(N, 64) for (N, *_r) in inst]
+        rc, reps = E.sp2_solve_batched([h.h for h in Hs], [d.h for d in Db], params)
+        assert rc == E.ELL_OK
+        assert all(r["batch_k"] in (2, 4, 8, 16) and r["batch_kernel"] in (0, 1) for r in reps)
+        choices.append((reps[0]["batch_k"], reps[0]["batch_kernel"]))
+    assert choices[0] == choices[1]
