@@ -1048,7 +1048,15 @@ __global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> 
       const int j = H.idx[(size_t)i * H.M + s];
       const double v = H.val[(size_t)i * H.M + s];
       const int32_t *cj = H.idx + (size_t)j * H.M;
-      int lo = 0, hi = H.nnz[j] - 1;
+      // first the mirror slot, where (j, i) sits when rows i and j are bands of
+      // the same width (a slot below the capacity: in bounds whatever it holds)
+      const int pm = n - 1 - s;
+      const int nj = H.nnz[j];
+      if (pm < H.M && cj[pm] == i && pm < nj) {
+        bad = bad || __double_as_longlong(H.val[(size_t)j * H.M + pm]) != __double_as_longlong(v);
+        continue;
+      }
+      int lo = 0, hi = nj - 1;
       bool found = false;
       while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
