@@ -492,11 +492,16 @@ def model_leg(E, synth, torch, reps=5):
     """The paper's model Hamiltonians (metals, semiconductors, soft matter,
     section "On the Generation of Model Hamiltonian System Matrices"): one FP64
     X^2 of H itself at tau = 1e-5 on each system at 32000 orbitals; then SP2,
-    FP64 and mixed, on the two gapped systems at 4096 orbitals, N_occ = the
-    eigenvalues below the 0 eV Fermi level."""
+    FP64 and mixed, on the two gapped systems at 4096 orbitals and at the
+    32000 orbitals of the paper's ExaSP2 runs, N_occ = the eigenvalues below
+    the 0 eV Fermi level (dense spectrum at 4096; at 32000 Sylvester's inertia
+    of block Schur complements, counted for the semiconductor at 0.05, inside
+    its gap (0, 0.93), since its highest occupied states round to within
+    1e-9 of 0)."""
     import numpy as np
     out = {"workload": "model Hamiltonians (A/B two-level chains, drop threshold 1e-5): X^2 of H at tau 1e-5; "
-                       f"SP2 at N=4096, FP64 tau {TAU_MIXED64:g}, mixed tau {TAU_FP32:g}/{TAU_MIXED64:g}, to "
+                       f"SP2 at N=4096 and 32000, FP64 tau {TAU_MIXED64:g} at 4096 and {0.1 * TAU_MIXED64:g} at 32000 "
+                       f"(also the mixed solves' FP64 steps), mixed FP32 tau {TAU_FP32:g}, to "
                        f"||X^2-X||_F<{TARGET:g}"}
     x2 = {}
     for kind, n in (("metal", 32000), ("semiconductor", 32000), ("soft_matter", 32000)):
@@ -522,15 +527,24 @@ def model_leg(E, synth, torch, reps=5):
         del X, Y
     out["x2"] = x2
     sp2 = {}
-    n = 4096
-    for kind in ("semiconductor", "soft_matter"):
+    for n, kind in ((4096, "semiconductor"), (4096, "soft_matter"), (32000, "semiconductor"),
+                    (32000, "soft_matter")):
         nnz, idx, val, m = synth.model_hamiltonian(kind, n)
-        n_occ, w = synth.fermi_occupation(nnz, idx, val, m)
+        if n <= 4096:
+            n_occ, w = synth.fermi_occupation(nnz, idx, val, m)
+            res = {"N": n, "n_occ": n_occ, "gap_at_fermi": float(w[n_occ] - w[n_occ - 1]),
+                   "spectrum": [float(w[0]), float(w[-1])]}
+        else:
+            mu = 0.05 if kind == "semiconductor" else 0.0
+            n_occ, margin = synth.fermi_occupation_banded(nnz, idx, val, m, mu=mu)
+            res = {"N": n, "n_occ": n_occ, "n_occ_below": mu, "inertia_margin": margin}
         H = E.DeviceEll.from_host(n, m, nnz, idx, val)
-        res = {"N": n, "n_occ": n_occ, "gap_at_fermi": float(w[n_occ] - w[n_occ - 1]),
-               "spectrum": [float(w[0]), float(w[-1])]}
-        # tau = 1e-8 leaves FP64 above eta = 1e-6 on these spectra: both solves use the mixed run's FP64 tau
-        for name, prec, tau in (("f64", E.SP2_F64, TAU_MIXED64), ("mixed", E.SP2_MIXED, TAU_MIXED64)):
+        # tau = 1e-8 leaves FP64 above eta = 1e-6 on these spectra: both solves use the mixed run's FP64
+        # tau; at 32000 orbitals 1e-9 leaves the semiconductor's mixed solve stalled at eta = 3.1e-6
+        # (rows of 3500 entries pruned at 1e-9), so both solves there prune at 1e-10
+        tau = TAU_MIXED64 if n <= 4096 else 0.1 * TAU_MIXED64
+        res["tau_fp64"] = tau
+        for name, prec in (("f64", E.SP2_F64), ("mixed", E.SP2_MIXED)):
             D = E.DeviceEll(n, 256)
             p = E.sp2_params(n_occ, tau, TARGET, max_iter=200, precision=prec, tau_fp32=TAU_FP32,
                              switch_eta=SWITCH_ETA)
@@ -542,7 +556,9 @@ def model_leg(E, synth, torch, reps=5):
             res[name] = {"status": int(rc), "solve_ms": (time.perf_counter() - t0) * 1e3,
                          "iterations": rep["iterations"], "fp32_iterations": rep["fp32_iterations"],
                          "eta": rep["eta"], "trace": rep["trace_x"], "final_M": rep["final_M"]}
-        sp2[kind] = res
+            del D
+        sp2[f"{kind}_{n}"] = res
+        del H
     out["sp2"] = sp2
     return out
 

@@ -285,6 +285,53 @@ def fermi_occupation(nnz, idx, val, M, mu=0.0):
     return int((w < mu).sum()), w
 
 
+def fermi_occupation_banded(nnz, idx, val, M, mu=0.0):
+    """N_occ without the spectrum, for banded sizes a dense eigensolver does
+    not reach (the model Hamiltonians at 32000 orbitals): by Sylvester's law
+    of inertia the number of eigenvalues of H below mu equals the number of
+    negative eigenvalues of D in any congruence H - mu I = L D L^T.  Rows are
+    cut into blocks of the half-bandwidth w, so H - mu I is block tridiagonal
+    (diagonal blocks A_k, couplings B_k to the next block) and its block
+    LDL^T has the Schur complements S_1 = A_1, S_k = A_k - B_{k-1}^T
+    S_{k-1}^{-1} B_{k-1} as D (Haynsworth's inertia additivity).  Costs about
+    N w^2 flops against N^3 for the spectrum.
+
+    Returns (N_occ, smallest |eigenvalue| over all S_k): the second is a
+    conditioning check; it stays of the order of the gap at mu when mu lies
+    in a gap."""
+    N = len(nnz)
+    nnz = np.asarray(nnz)
+    idx2 = np.asarray(idx).reshape(N, M)
+    val2 = np.asarray(val).reshape(N, M)
+    slot = np.arange(M)[None, :] < nnz[:, None]
+    rows = np.repeat(np.arange(N)[:, None], M, axis=1)[slot]  # row-major: rows ascend
+    cols = idx2[slot].astype(np.int64)
+    vals = val2[slot]
+    start = np.concatenate(([0], np.cumsum(nnz, dtype=np.int64)))
+    w = max(1, int(np.abs(cols - rows).max(initial=0)))
+    count, smallest = 0, np.inf
+    C = None  # B_{k-1}^T S_{k-1}^{-1} B_{k-1}
+    for s in range(0, N, w):
+        e = min(N, s + w)
+        e2 = min(N, e + w)
+        r, c, v = (a[start[s]:start[e]] for a in (rows, cols, vals))
+        sel = c >= s  # the entries left of the block belong to B_{k-1}^T
+        blk = np.zeros((e - s, e2 - s))
+        blk[r[sel] - s, c[sel] - s] = v[sel]
+        S = blk[:, :e - s] - mu * np.eye(e - s)
+        if C is not None:
+            S = S - C
+        S = 0.5 * (S + S.T)
+        ev, V = np.linalg.eigh(S)
+        count += int((ev < 0).sum())
+        smallest = min(smallest, float(np.abs(ev).min()))
+        B = blk[:, e - s:]
+        if B.shape[1]:
+            VB = V.T @ B
+            C = VB.T @ (VB / ev[:, None])
+    return count, smallest
+
+
 # ---- storage moves (no arithmetic) -------------------------------------------------
 
 def ell_to_dense(N, M, nnz, idx, val, dtype=np.float64):

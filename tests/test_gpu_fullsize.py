@@ -36,17 +36,17 @@ def _as_f32(A):
     return oracle.Ell(A.N, A.M, A.nnz, A.idx, v)
 
 
-def oracle_step(X, tau, n_occ):
+def oracle_step(X, tau, n_occ, width=WIDTH):
     """One SP2 step of the oracle on X (FP32 mode when X holds float values)."""
     tau = np.float32(tau) if X.val.dtype == np.float32 else tau
-    rc, Y, d1, d2, wy = oracle.x2(X, tau, M2=WIDTH)
+    rc, Y, d1, d2, wy = oracle.x2(X, tau, M2=width)
     assert rc == 0
     trx, trx2 = oracle.pairwise(d1), oracle.pairwise(d2)
     eta2, _ = oracle.norm2(X, Y)
     up = abs(2.0 * trx - trx2 - n_occ) < abs(trx2 - n_occ)
     nxt = Y
     if up:
-        rc, nxt, _ = oracle.update(X, Y, tau, Mo=WIDTH)
+        rc, nxt, _ = oracle.update(X, Y, tau, Mo=width)
         assert rc == 0
     return trx, trx2, eta2, up, nxt
 
@@ -65,15 +65,16 @@ def _cut(Hd, N, params, it):
     return oracle_from_dev(D), rep
 
 
-def induction(N, params, k, n_occ, phase_f32, tau):
-    nnz, idx, val, M = synth.banded_hamiltonian(N, 64)
+def induction(N, params, k, n_occ, phase_f32, tau, ham=None, width=WIDTH):
+    """`ham` = (nnz, idx, val, M) of H, else the banded generator's."""
+    nnz, idx, val, M = ham if ham is not None else synth.banded_hamiltonian(N, 64)
     Hd = E.DeviceEll.from_host(N, M, nnz, idx, val)
     Xa, rep_a = _cut(Hd, N, params, k)
     Xb, rep_b = _cut(Hd, N, params, k + 1)
     assert rep_b["prec"][k - 1] == (1 if phase_f32 else 0)
     if phase_f32:
         Xa, Xb = _as_f32(Xa), _as_f32(Xb)
-    trx, trx2, eta2, up, want = oracle_step(Xa, tau, n_occ)
+    trx, trx2, eta2, up, want = oracle_step(Xa, tau, n_occ, width)
     for rep in (rep_a, rep_b):
         _hist_entry(rep, k - 1, trx, trx2, eta2)
     assert rep_b["up"][k - 1] == (1 if up else 0)
@@ -81,7 +82,7 @@ def induction(N, params, k, n_occ, phase_f32, tau):
     # the product of X_k itself: its history entry in the longer solve
     tau_b = tau if rep_b["prec"][k] == rep_b["prec"][k - 1] else None
     if tau_b is not None:
-        trx, trx2, eta2, _, _ = oracle_step(Xb, tau_b, n_occ)
+        trx, trx2, eta2, _, _ = oracle_step(Xb, tau_b, n_occ, width)
         _hist_entry(rep_b, k, trx, trx2, eta2)
 
 

@@ -3,6 +3,7 @@ Model Hamiltonian System Matrices"), against the oracle, bit for bit: the X^2
 product on all three systems, SP2 on the two the paper solves (semiconductors
 and soft matter, gapped at the 0 eV Fermi level); and a non-banded pattern, a
 3D lattice, through both the span form and the ELLPACK kernels."""
+import numpy as np
 import pytest
 
 import oracle
@@ -106,3 +107,68 @@ def test_sp2_on_the_3d_lattice_bitwise():
     rc_g, rg = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 2, 1e-8, 1e-6, max_iter=200))
     assert rc_o == 0
     assert_same_trajectory((rc_o, Do, ro), (rc_g, Dd, rg))
+
+
+# ------------------------------------------------ the paper's ExaSP2 size: 32000 orbitals
+#
+# SP2 at 32000 orbitals with the benchmark's settings there (FP64 tau 1e-10,
+# target 1e-6; N_occ the inertia count below the Fermi level), by induction
+# over steps as for the banded solves: cut the solve at q and q + 1 products and
+# apply one oracle step to the GPU's X_{q-1}.  The cut points are taken from the
+# solve's own branch history so that both branches are stepped.
+
+N_EXA, TAU_EXA = 32000, 1e-10
+
+
+def _branch_points(Hd, n_occ, lo, hi, **kw):
+    """(q with branch 2X - X^2 at product q - 1, q with branch X^2), lo <= q < hi."""
+    D = E.DeviceEll(N_EXA, 256)
+    rc, rep = E.sp2_solve(Hd.h, D.h, E.sp2_params(n_occ, TAU_EXA, 1e-6, max_iter=hi, **kw))
+    assert rc == E.ELL_ENOCONV and rep["iterations"] == hi
+    up = [int(u) for u in rep["up"][:hi]]
+    q_up = next(q for q in range(lo, hi) if up[q - 1] == 1)
+    q_sq = next(q for q in range(lo, hi) if up[q - 1] == 0)
+    return q_up, q_sq
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sp2_on_soft_matter_at_32000_orbitals_by_induction(mixed):
+    """Soft matter, whole matrices: FP64, and the mixed solve inside its FP32
+    phase (tau_fp32 1e-7), at products 20 .. 24 (rows of 500 - 900 entries)."""
+    from tests.test_gpu_fullsize import induction
+    nnz, idx, val, M = synth.model_hamiltonian("soft_matter", N_EXA)
+    n_occ, _ = synth.fermi_occupation_banded(nnz, idx, val, M)
+    kw = dict(precision=E.SP2_MIXED, tau_fp32=1e-7, switch_eta=1e-2) if mixed else {}
+    Hd = E.DeviceEll.from_host(N_EXA, M, nnz, idx, val)
+    for q in _branch_points(Hd, n_occ, 20, 25, **kw):
+        p = E.sp2_params(n_occ, TAU_EXA, 1e-6, max_iter=200, **kw)
+        induction(N_EXA, p, q, n_occ, mixed, 1e-7 if mixed else TAU_EXA, ham=(nnz, idx, val, M), width=2048)
+
+
+def test_sp2_on_semiconductor_at_32000_orbitals_sampled_rows():
+    """Semiconductor (rows of 3000 - 3500 entries: whole oracle products are
+    too slow here): at an X^2 step between products 15 and 25, sampled rows of
+    the GPU's X_q against the oracle's rows of prune(X_{q-1}^2), and Tr X_{q-1}
+    against the pairwise tree of the GPU's X_{q-1} diagonal."""
+    from tests.test_gpu_fullsize import _cut
+    nnz, idx, val, M = synth.model_hamiltonian("semiconductor", N_EXA)
+    n_occ = N_EXA // 2  # the inertia count below 0.05, inside the gap (0, 0.93)
+    Hd = E.DeviceEll.from_host(N_EXA, M, nnz, idx, val)
+    _, q = _branch_points(Hd, n_occ, 15, 25)
+    # cut after q and q + 1 products: X_{q-1} (squared by product q - 1) and X_q
+    Xa, _ = _cut(Hd, N_EXA, E.sp2_params(n_occ, TAU_EXA, 1e-6, max_iter=200), q)
+    Xb, rep_b = _cut(Hd, N_EXA, E.sp2_params(n_occ, TAU_EXA, 1e-6, max_iter=200), q + 1)
+    assert rep_b["up"][q - 1] == 0
+    ia = Xa.idx.reshape(N_EXA, Xa.M)
+    va = Xa.val.reshape(N_EXA, Xa.M)
+    diag = np.array([va[i, :Xa.nnz[i]][ia[i, :Xa.nnz[i]] == i].sum() for i in range(N_EXA)])
+    assert same_float(rep_b["trx"][q - 1], oracle.pairwise(diag))
+    rows = np.array([0, 1, 2, 3, 1220, 1221, 5000, 9999, 16000, 16001, 23457, N_EXA - 1221, N_EXA - 2, N_EXA - 1])
+    rc, nz, ix, vl, _ = oracle.x2_rows(Xa, TAU_EXA, rows, M2=8192)
+    assert rc == 0
+    ib = Xb.idx.reshape(N_EXA, Xb.M)
+    vb = Xb.val.reshape(N_EXA, Xb.M)
+    for r, i in enumerate(rows):
+        assert Xb.nnz[i] == nz[r], (i, Xb.nnz[i], nz[r])
+        assert np.array_equal(ib[i, :nz[r]], ix[r, :nz[r]]), i
+        assert np.array_equal(vb[i, :nz[r]].view(np.uint64), vl[r, :nz[r]].view(np.uint64)), i

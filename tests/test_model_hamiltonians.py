@@ -119,6 +119,37 @@ def test_fermi_occupation_counts_eigenvalues_below_zero():
     assert n == 2 and np.allclose(w, [-2.0, -0.5, 0.25, 3.0])
 
 
+@pytest.mark.parametrize("kind,N,mus", [("banded", 700, (-1.0, 0.0, 0.37)),
+                                         ("soft_matter", 1500, (0.0, -0.5)),
+                                         ("semiconductor", 1500, (0.05, -0.3, 1.0)),
+                                         ("metal", 1200, (0.0, 0.02))])
+def test_banded_occupation_is_the_eigenvalue_count(kind, N, mus):
+    """Sylvester's inertia over block Schur complements gives the number of
+    eigenvalues below mu that the dense spectrum gives."""
+    if kind == "banded":
+        nnz, idx, val, M = synth.banded_hamiltonian(N, 9, seed=3)
+    else:
+        nnz, idx, val, M = synth.model_hamiltonian(kind, N)
+    _, w = synth.fermi_occupation(nnz, idx, val, M)
+    for mu in mus:
+        n, smallest = synth.fermi_occupation_banded(nnz, idx, val, M, mu=mu)
+        assert n == int((w < mu).sum()), (kind, mu)
+        assert smallest > 0
+
+
+def test_semiconductor_occupation_counts_its_zero_energy_band():
+    """The semiconductor's A orbitals carry no onsite energy and no A-A
+    coupling: the upper half of its occupied states crowds against 0 from
+    below (the highest round to negatives of order 1e-10), and nothing lies in
+    (0, 0.93).  The count below 0 (dense spectrum) is the well-conditioned
+    count below 0.05 (banded inertia): N / 2."""
+    N = 2000
+    nnz, idx, val, M = synth.model_hamiltonian("semiconductor", N)
+    n0, w = synth.fermi_occupation(nnz, idx, val, M)
+    assert n0 == N // 2 and w[n0] > 0.9 and abs(w[n0 - 1]) < 1e-6
+    assert synth.fermi_occupation_banded(nnz, idx, val, M, mu=0.05)[0] == N // 2
+
+
 # ------------------------------------------------------- oracle pins on these inputs
 def test_oracle_x2_of_a_model_hamiltonian_is_the_dense_product():
     N = 200
