@@ -371,6 +371,43 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
     for (int sb = 0; sb < kSB; ++sb) {
       if (pc + sb >= nblk) break;  // (past the window: nothing to sweep)
       const int p0 = wlo + (pc + sb) * kWave;
+      const bool diag = p0 <= i0 + kR - 1 && p0 + kWave - 1 >= i0;  // a diagonal entry lies in the block
+      // Block p0 / 64 enters row g's pairwise norm tree over all aligned
+      // blocks (outside the window: +0) with total tb: as a right child it
+      // joins its left sibling and climbs; as a left child it waits on the
+      // stack.  Lanes 4 g.
+      auto enter = [&](double tb) {
+        const int g = lane >> 2;
+        int node = p0 >> 6, lvl = 0;
+        while (node & 1) {
+          if ((node << lvl) > b_first) tb = stk[g * kLev + lvl] + tb;
+          pend &= ~(1u << lvl);
+          node >>= 1;
+          ++lvl;
+        }
+        stk[g * kLev + lvl] = tb;
+        pend |= 1u << lvl;
+      };
+      // A block outside every row's interval of X (x = 0 there), without a
+      // diagonal entry and with no entry of X^2 above tau keeps nothing and
+      // writes nothing; when the norm takes the pruned X^2, each of its
+      // squared differences is (+0 - +0)^2 = +0, so its norm node is +0, and
+      // its terms of the iterate's chain of squares are fma(0, 0, c) = c.
+      // Only that +0 node is entered, the sweep is skipped.  (Outside the
+      // rows' intervals of the iterate, such blocks are most of a window's
+      // ends: the unpruned product reaches twice as far as the pruned one.)
+      if (!once && !diag) {
+        const bool xin = r < nrows && lA > 0 && bA <= p0 + kWave - 1 && bA + lA - 1 >= p0;
+        bool big = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int p = 0; p < kP; ++p) big |= Mfma<T>::row(q, t) < nrows && absv(acc[kP * sb + p][t]) > tau;
+        if (__ballot(xin || big) == 0) {
+          if ((lane & 3) == 0) enter(0.0);
+          continue;
+        }
+      }
       // X at the block's output positions (for 2X - X^2 and the norm)
       T xv[4][kP];
 #pragma unroll
@@ -382,7 +419,6 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
         }
       // sweep the block, four rows per set t (a row's 64 columns are the 16
       // lanes of its lane row q, G consecutive columns per run)
-      const bool diag = p0 <= i0 + kR - 1 && p0 + kWave - 1 >= i0;  // a diagonal entry lies in the block
       T vks[4][kP];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -471,20 +507,7 @@ __device__ void rows16_sym(const int N, const int i0, const int nrows, const Spa
         double tb = v[0];
         tb = tb + dpp<0xb1>(tb);
         tb = tb + dpp<0x4e>(tb);
-        if (j == 0) {
-          // block p0 / 64 enters row g's pairwise tree over all aligned blocks
-          // (outside the window: +0): as a right child it joins its left
-          // sibling and climbs; as a left child it waits on the stack
-          int node = p0 >> 6, lvl = 0;
-          while (node & 1) {
-            if ((node << lvl) > b_first) tb = stk[g * kLev + lvl] + tb;
-            pend &= ~(1u << lvl);
-            node >>= 1;
-            ++lvl;
-          }
-          stk[g * kLev + lvl] = tb;
-          pend |= 1u << lvl;
-        }
+        if (j == 0) enter(tb);
       }
       // The iterate's chain of squares: its values of the block to the same
       // table [row][column], then lane g < 16 runs row g's 64 columns in order.
@@ -602,9 +625,10 @@ __device__ __forceinline__ void thread_leaves(const double *part, int nq, int t,
   else if (nq <= 8192) leaves<32>(part, nq, t, v);
   else leaves<64>(part, nq, t, v);
 }
-// the thread sums v into totals out[0 .. NS) (thread 0)
+// the thread sums v into totals out[0 .. NS) (thread 0, which also keeps them
+// in tot)
 template <int NS>
-__device__ __forceinline__ void tree_finish(double (&v)[NS], double *out)
+__device__ __forceinline__ void tree_finish(double (&v)[NS], double *out, double *tot = nullptr)
 {
   __shared__ double ws[NS][kWpb];
   const int t = threadIdx.x, w = t >> 6, lane = lane_id();
@@ -615,7 +639,11 @@ __device__ __forceinline__ void tree_finish(double (&v)[NS], double *out)
     for (int c = 0; c < NS; ++c) ws[c][w] = v[c];
   __syncthreads();
   if (t == 0)
-    for (int c = 0; c < NS; ++c) out[c] = (ws[c][0] + ws[c][1]) + (ws[c][2] + ws[c][3]);
+    for (int c = 0; c < NS; ++c) {
+      const double x = (ws[c][0] + ws[c][1]) + (ws[c][2] + ws[c][3]);
+      out[c] = x;
+      if (tot) tot[c] = x;
+    }
 }
 
 // The SP2 iteration in one launch.  Each workgroup computes 64 rows, then
@@ -692,8 +720,19 @@ __global__ __launch_bounds__(256) void k_x2_sym_step(int N, SpanRot3<T> spans, S
   }
   __syncthreads();
   if (!last_s) return;
-  // the last workgroup: every other workgroup's partials are complete
+  // the last workgroup: every other workgroup's partials are complete.  The
+  // deciding thread loads the state (unchanged since the launch began) and
+  // the norms of the products before this one under the partials' loads.
   const int t = threadIdx.x;
+  SP2State x;
+  sp2dev::SymOut o;
+  if (t == 0) {
+    x = *st;
+    for (int q = 0; q < 3; ++q) {
+      const int m = x.iter - 1 - q;
+      o.prev[q] = m >= x.phase_start ? h.eta2[m] : 0.0;
+    }
+  }
   double v[kSums];
   thread_leaves(s.part, nq, t, v);
   int32_t mx[3] = {0, 0, 0};
@@ -711,13 +750,17 @@ __global__ __launch_bounds__(256) void k_x2_sym_step(int N, SpanRot3<T> spans, S
     wsl[0][w] = sy;
     wsl[1][w] = so;
   }
-  tree_finish(v, s.out);  // (its barrier also covers wsi, wsl)
+  tree_finish(v, s.out, o.sum);  // (its barrier also covers wsi, wsl)
   if (t == 0) {
-    for (int c = 0; c < 3; ++c) s.outw[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
-    s.outn[0] = wsl[0][0] + wsl[0][1] + wsl[0][2] + wsl[0][3];
-    s.outn[1] = wsl[1][0] + wsl[1][1] + wsl[1][2] + wsl[1][3];
-    SP2State x = *st;
-    sp2dev::decide_sym(&x, cfg, h, s);
+    for (int c = 0; c < 3; ++c) {
+      o.w[c] = max(max(wsi[c][0], wsi[c][1]), max(wsi[c][2], wsi[c][3]));
+      s.outw[c] = o.w[c];
+    }
+    for (int c = 0; c < 2; ++c) {
+      o.n[c] = wsl[c][0] + wsl[c][1] + wsl[c][2] + wsl[c][3];
+      s.outn[c] = o.n[c];
+    }
+    sp2dev::decide_sym(&x, cfg, h, o);
     *st = x;
     cst(s.ticket, 0u);
     if (publish) {

@@ -116,21 +116,41 @@ __device__ inline void seed_sym(SP2State *st, const SP2Cfg &cfg, double trx, dou
 // with ST_MISPREDICT).  s.out[3], s.out[4]: Tr X', Tr X'^2 of the written
 // iterate, which fix the next branch.  s.outw: widest pruned X^2 row, widest
 // iterate row, longest iterate interval; s.outn: entries of the pruned X^2
-// and of the iterate.
-__device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const StepScratch &s)
+// and of the iterate.  The deciding thread holds them in registers (SymOut),
+// with the norms of the three products before this one, loaded ahead for the
+// stall rule.
+struct SymOut {
+  double sum[5];    // Tr X, Tr X^2 (unpruned), eta^2, Tr X', Tr X'^2
+  int32_t w[3];     // widest pruned X^2 row, widest iterate row, longest iterate interval
+  int64_t n[2];     // entries of the pruned X^2 and of the iterate
+  double prev[3];   // eta^2 of products n - 1, n - 2, n - 3 (when within the phase)
+};
+
+// stalled() with the current norm and the three before it from registers;
+// m = products of the phase before this one
+__device__ inline bool stalled_sym(const SymOut &o, int m)
+{
+  if (m < 3) return false;
+  if (!(o.prev[2] < 1e-4)) return false;
+  const double now = o.sum[2] < o.prev[0] ? o.sum[2] : o.prev[0];
+  const double before = o.prev[1] < o.prev[2] ? o.prev[1] : o.prev[2];
+  return now >= before;
+}
+
+__device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h, const SymOut &o)
 {
   const int n = st->iter;
-  const double trx = s.out[0], trx2 = s.out[1], eta2 = s.out[2];
+  const double trx = o.sum[0], trx2 = o.sum[1], eta2 = o.sum[2];
   if (!same_bits(trx, st->ptrx) || !same_bits(trx2, st->ptrx2)) {
     // the product's own traces are recorded; D keeps X_n
     h.trx[n] = trx;
     h.trx2[n] = trx2;
     h.eta2[n] = eta2;
-    h.maxw[n] = s.outw[0];
+    h.maxw[n] = o.w[0];
     h.prec[n] = (int8_t)st->phase32;
     h.up[n] = -1;
     h.nnzx[n] = st->nnz_cur;
-    h.nnzy[n] = s.outn[0];
+    h.nnzy[n] = o.n[0];
     st->trx = trx;
     st->trx2 = trx2;
     st->eta2 = eta2;
@@ -142,17 +162,17 @@ __device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist
   st->trx = trx;
   st->trx2 = trx2;
   st->eta2 = eta2;
-  st->wy_max = s.outw[0];
-  st->wu_max = s.outw[1];
+  st->wy_max = o.w[0];
+  st->wu_max = o.w[1];
   h.trx[n] = trx;
   h.trx2[n] = trx2;
   h.eta2[n] = eta2;
-  h.maxw[n] = s.outw[0];
+  h.maxw[n] = o.w[0];
   h.prec[n] = (int8_t)st->phase32;
   h.up[n] = -1;
   h.nnzx[n] = st->nnz_cur;
-  h.nnzy[n] = s.outn[0];
-  const bool stall = cfg.stall && stalled(h.eta2 + st->phase_start, n - st->phase_start);
+  h.nnzy[n] = o.n[0];
+  const bool stall = cfg.stall && stalled_sym(o, n - st->phase_start);
   if (st->phase32) {
     if (eta2 < cfg.switch2 || stall) {
       st->phase_start = n + 1;
@@ -182,9 +202,9 @@ __device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist
     return;
   }
   const bool up = st->up_next != 0;
-  if (s.outw[2] > st->sw) {
+  if (o.w[2] > st->sw) {
     st->status = ELL_EOVERFLOW;
-    st->need_width = s.outw[2];
+    st->need_width = o.w[2];
     st->stop = 1;
     return;
   }
@@ -192,9 +212,9 @@ __device__ inline void decide_sym(SP2State *st, const SP2Cfg &cfg, const SP2Hist
   const int c = st->cur;
   st->cur = up ? (c == 0 ? 2 : c - 1) : (c == 2 ? 0 : c + 1);
   if (!st->phase32) st->fp64_updates += 1;
-  st->nnz_cur = s.outn[1];
+  st->nnz_cur = o.n[1];
   st->iter = n + 1;
-  seed_sym(st, cfg, s.out[3], s.out[4]);
+  seed_sym(st, cfg, o.sum[3], o.sum[4]);
 }
 
 }  // namespace sp2dev
