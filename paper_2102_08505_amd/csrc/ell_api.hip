@@ -1652,6 +1652,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   int graph_iters = 0;
   int kernel = 0;            // step kernel: 0 matrix cores, 1 register-tiled VALU (same results)
+  bool sym = false;          // every instance's H is bitwise symmetric (so is each iterate)
   int graph_kernel = 0;      // the kernel the graph was captured with
   ~Batch()
   {
@@ -1695,10 +1696,10 @@ struct Batch {
     if (any32)
       HIP_TRY(launch_x2_band_batch<float>(ngroups, A32.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
                                           inst_rows.as<int32_t>(), stp, 1, taus32.as<float>(),
-                                          ss.as<StepScratch>(), flags.as<int32_t>(), st, kernel == 0));
+                                          ss.as<StepScratch>(), flags.as<int32_t>(), st, kernel == 0, sym));
     HIP_TRY(launch_x2_band_batch<double>(ngroups, A64.rot(), grp_inst.as<int32_t>(), inst_r0.as<int32_t>(),
                                          inst_rows.as<int32_t>(), stp, 0, taus64.as<double>(), ss.as<StepScratch>(),
-                                         flags.as<int32_t>(), st, kernel == 0));
+                                         flags.as<int32_t>(), st, kernel == 0, sym));
     HIP_TRY(launch_reduce_batch(nblocks, blk_inst.as<int32_t>(), blk_local.as<int32_t>(), inst_rows.as<int32_t>(),
                                 ss.as<StepScratch>(), stp, st));
     HIP_TRY(launch_decide_batch(n, states.as<SP2State>(), cfgs.as<SP2Cfg>(), hists.as<SP2Hist>(),
@@ -1908,6 +1909,21 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
       if (r) r[q].status = early[q];
     }
   if (B.n == 0) return worst;
+
+  // ---- bitwise symmetry of every H: if all are, so is every iterate, and the
+  // matrix-core step reads its A operand through the symmetry ----
+  {
+    DevMem asym;
+    HIP_TRY(asym.alloc(sizeof(int32_t) * B.n));
+    HIP_TRY(launch_zero_words(B.n, asym.as<int32_t>(), st));
+    for (int m = 0; m < B.n; ++m)
+      HIP_TRY(launch_check_symmetric(B.in[m].N, view<double>(H[B.in[m].q]), asym.as<int32_t>() + m, st));
+    std::vector<int32_t> fl(B.n);
+    HIP_TRY(hipMemcpyAsync(fl.data(), asym.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    B.sym = true;
+    for (int32_t f : fl) B.sym = B.sym && (f & 1) == 0;
+  }
 
   // ---- X0 of every instance in ELLPACK form (capacity grows until it fits) ----
   int32_t cap0 = 32;

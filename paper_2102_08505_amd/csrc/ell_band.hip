@@ -664,12 +664,13 @@ template hipError_t launch_x2_band<float>(int, SpanRot3<float>, Rot3<float>, con
 template <typename T>
 hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                 const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
-                                const StepScratch *ss, int32_t *flags, hipStream_t stream, bool matrix_cores)
+                                const StepScratch *ss, int32_t *flags, hipStream_t stream, bool matrix_cores,
+                                bool sym)
 {
   static_assert(kBatchAlign % kGroupRows == 0, "batch alignment is a whole number of row groups");
   if (matrix_cores && x2_band16_fits(ngroups * kGroupRows, spans.b[0].SW, (int)sizeof(T)))
     return launch_x2_band16_batch<T>(ngroups * kGroupRows / 16, spans, grp_inst, inst_r0, inst_rows, states, phase32,
-                                     taus, ss, flags, stream);
+                                     taus, ss, flags, sym, stream);
   const dim3 grid((ngroups + kWavesPerBlock - 1) / kWavesPerBlock), block(256);
   hipLaunchKernelGGL((k_x2_band_batch<T>), grid, block, 0, stream, ngroups, spans, grp_inst, inst_r0, inst_rows,
                      states, phase32, taus, ss, flags);
@@ -677,10 +678,10 @@ hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *g
 }
 template hipError_t launch_x2_band_batch<double>(int, SpanRot3<double>, const int32_t *, const int32_t *,
                                                  const int32_t *, const SP2State *, int32_t, const double *,
-                                                 const StepScratch *, int32_t *, hipStream_t, bool);
+                                                 const StepScratch *, int32_t *, hipStream_t, bool, bool);
 template hipError_t launch_x2_band_batch<float>(int, SpanRot3<float>, const int32_t *, const int32_t *,
                                                 const int32_t *, const SP2State *, int32_t, const float *,
-                                                const StepScratch *, int32_t *, hipStream_t, bool);
+                                                const StepScratch *, int32_t *, hipStream_t, bool, bool);
 
 template <typename T>
 hipError_t launch_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags, int32_t *maxlen,

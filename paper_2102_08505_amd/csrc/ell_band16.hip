@@ -77,17 +77,20 @@ __device__ void fill_gap(__amdgpu_buffer_rsrc_t rs, int first, int gap_lo, int c
 // Accumulate one 64-column block: acc[p] += X[i0 .. i0+15][k] X[k][p0 + 16 p ..]
 // over k = klo .. khi, four k per step (a step past khi multiplies zeros);
 // tile p takes part only in the steps that meet its own range tlo[p] .. thi[p].
-// A operand: lane (r, q) = (l % 16, l / 16) supplies X[i0 + r][k0 + q];
+// A operand: lane (r, q) = (l % 16, l / 16) supplies X[i0 + r][k0 + q] -- with
+// SYMA (X bitwise symmetric) read as X[k0 + q][i0 + r] from row k's interval,
+// four 128-byte runs per load instead of sixteen rows of 32 bytes;
 // B operand: lane (r, q) supplies X[k0 + q][p0 + 16 p + r].
 // Two operand sets alternate: the loads of step k0 + 4 are in flight while
 // the products of step k0 issue.  Every load is range-checked (rows k past
 // khi have no entry in the block's columns, and rows k past kmax have an
 // empty interval in the table), so the step after the last needs no branch.
-template <typename T, bool LDS_META>
+template <typename T, bool LDS_META, bool SYMA>
 __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_buffer_rsrc_t xr, const int2 *meta,
                                           const int kmin, const int kmax, const int klo, const int khi,
                                           const int (&tlo)[kP], const int (&thi)[kP], const int p0, const int arow,
-                                          const int bA, const int lA, typename Mfma<T>::acc (&acc)[kP])
+                                          const int bA, const int lA, const int ai,
+                                          typename Mfma<T>::acc (&acc)[kP])
 {
   const int lane = lane_id();
   const int r = lane & 15, q = lane >> 4;
@@ -106,8 +109,11 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
   };
   auto load = [&](int k0, int2 m, T &a, T (&b)[kP]) {
     const int k = k0 + q;
-    a = ld(xr, at<T>((unsigned)(k - bA) < (unsigned)lA, arow + k), T(0));
     const int brow = k * SW - m.x;
+    if (SYMA)
+      a = ld(xr, at<T>((unsigned)(ai - m.x) < (unsigned)m.y, brow + ai), T(0));
+    else
+      a = ld(xr, at<T>((unsigned)(k - bA) < (unsigned)lA, arow + k), T(0));
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
       const int col = p0 + 16 * p + r;
@@ -146,8 +152,9 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
 
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
 // `once`: 2X - X^2 and the norm take the unpruned X^2 (one pruning per
-// iteration); otherwise the pruned X^2.
-template <typename T>
+// iteration); otherwise the pruned X^2.  SYMA: X is bitwise symmetric (the A
+// operand is read through the symmetry).
+template <typename T, bool SYMA = false>
 __device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
                        const SpanView<T> SU, const T tau, const bool once, const StepScratch &s, double *stk,
                        double *sq, int2 *meta, [[maybe_unused]] int32_t *fallback)
@@ -296,8 +303,8 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
 #pragma unroll
     for (int p = 0; p < kP; ++p) acc[p] = typename Mfma<T>::acc{T(0), T(0), T(0), T(0)};
     if (klo <= khi) {
-      if (kfit) mma_block<T, true>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, acc);
-      else mma_block<T, false>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, acc);
+      if (kfit) mma_block<T, true, SYMA>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, i0 + r, acc);
+      else mma_block<T, false, SYMA>(X, xr, meta, kmin, kmax, klo, khi, tlo, thi, p0, arow, bA, lA, i0 + r, acc);
     }
 
     // sweep the block, row quad by row quad
@@ -589,7 +596,7 @@ __device__ __forceinline__ SpanView<T> rows_from(SpanView<T> v, int r0)
   return v;
 }
 
-template <typename T>
+template <typename T, bool SYMA>
 __global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst,
                                                          const int32_t *inst_r0, const int32_t *inst_rows,
                                                          const SP2State *states, int32_t phase32, const T *taus,
@@ -609,7 +616,7 @@ __global__ __launch_bounds__(256) void k_x2_band16_batch(int ngroups, SpanRot3<T
   const int r0 = uni(inst_r0[m]), n = uni(inst_rows[m]);
   const int i0 = grp * kR - r0;
   if (i0 >= n) return;  // alignment rows after the instance's last row
-  rows16<T>(n, i0, min(kR, n - i0), rows_from(spans.b[cur], r0), rows_from(spans.b[cy], r0),
+  rows16<T, SYMA>(n, i0, min(kR, n - i0), rows_from(spans.b[cur], r0), rows_from(spans.b[cy], r0),
             rows_from(spans.b[cu], r0), taus[m], st->once != 0, ss[m], stk_s[w], sq_s[w], meta_s[w], flags + m);
 }
 
@@ -657,19 +664,23 @@ hipError_t launch_step_final64(SP2State *st, const SP2Cfg &cfg, const SP2Hist &h
 template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                   const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
-                                  const StepScratch *ss, int32_t *flags, hipStream_t stream)
+                                  const StepScratch *ss, int32_t *flags, bool sym, hipStream_t stream)
 {
   static_assert(kR % kGroupRows == 0, "a 16-row group is a whole number of 8-row groups");
   const dim3 grid((ngroups16 + kWpb - 1) / kWpb), block(kWpb * kWave);
-  hipLaunchKernelGGL(k_x2_band16_batch<T>, grid, block, 0, stream, ngroups16, spans, grp_inst, inst_r0, inst_rows,
-                     states, phase32, taus, ss, flags);
+  if (sym)
+    hipLaunchKernelGGL((k_x2_band16_batch<T, true>), grid, block, 0, stream, ngroups16, spans, grp_inst, inst_r0,
+                       inst_rows, states, phase32, taus, ss, flags);
+  else
+    hipLaunchKernelGGL((k_x2_band16_batch<T, false>), grid, block, 0, stream, ngroups16, spans, grp_inst, inst_r0,
+                       inst_rows, states, phase32, taus, ss, flags);
   return hipGetLastError();
 }
 template hipError_t launch_x2_band16_batch<double>(int, SpanRot3<double>, const int32_t *, const int32_t *,
                                                    const int32_t *, const SP2State *, int32_t, const double *,
-                                                   const StepScratch *, int32_t *, hipStream_t);
+                                                   const StepScratch *, int32_t *, bool, hipStream_t);
 template hipError_t launch_x2_band16_batch<float>(int, SpanRot3<float>, const int32_t *, const int32_t *,
                                                   const int32_t *, const SP2State *, int32_t, const float *,
-                                                  const StepScratch *, int32_t *, hipStream_t);
+                                                  const StepScratch *, int32_t *, bool, hipStream_t);
 
 }  // namespace ellsp2

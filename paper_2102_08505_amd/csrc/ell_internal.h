@@ -202,7 +202,7 @@ hipError_t launch_sym_seed(int N, SpanRot3<T> spans, SP2State *st, const SP2Cfg 
 template <typename T>
 hipError_t launch_x2_band16_batch(int ngroups16, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                   const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
-                                  const StepScratch *ss, int32_t *flags, hipStream_t stream);
+                                  const StepScratch *ss, int32_t *flags, bool sym, hipStream_t stream);
 // Row intervals of an ELLPACK matrix: len[i] (or null), flags |= 4 when a value
 // is an exact zero; with maxlen: the longest interval, and with sums:
 // sums[0] += stored entries, sums[1] += interval lengths.
@@ -227,12 +227,14 @@ hipError_t launch_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wma
 // of them (local columns); per-instance state, drop tolerance, row-output
 // scratch view and fallback flag.  Takes the matrix-core kernel when the stack
 // fits its 2^31-byte buffer range and matrix_cores is set, else the
-// register-tiled VALU kernel (the same results).
+// register-tiled VALU kernel (the same results).  sym: every instance's X is
+// bitwise symmetric (the matrix-core kernel then reads its A operand through
+// the symmetry).
 template <typename T>
 hipError_t launch_x2_band_batch(int ngroups, SpanRot3<T> spans, const int32_t *grp_inst, const int32_t *inst_r0,
                                 const int32_t *inst_rows, const SP2State *states, int32_t phase32, const T *taus,
                                 const StepScratch *ss, int32_t *flags, hipStream_t stream,
-                                bool matrix_cores = true);
+                                bool matrix_cores = true, bool sym = false);
 constexpr int kGroupRows = 8;   // rows per wavefront of the register-tiled span step kernel
 constexpr int kBatchAlign = 16; // instance alignment in a batch: a whole number of both kernels' row groups
 template <typename TS, typename TD>

@@ -108,6 +108,32 @@ def test_batched_mixed_instances_match_the_oracle():
         assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
 
 
+def test_batched_with_an_asymmetric_instance_matches_the_oracle():
+    """One instance's H has a coupling whose two sides differ by one ulp: the
+    batch then reads every A operand directly instead of through the
+    symmetry (the path all-symmetric batches leave), and every instance still
+    equals the oracle bit for bit."""
+    specs = [(64, 4, 21), (120, 5, 22), (200, 6, 23)]
+    inst = _instances(specs)
+    N, Mh, nnz, idx, val = inst[1]
+    D = synth.ell_to_dense(N, Mh, nnz, idx, val)
+    D[7, 9] = np.nextafter(D[7, 9], np.inf)
+    assert D[7, 9] != D[9, 7]
+    nnz, idx, val, Mh = synth.dense_to_ell(D)
+    inst[1] = (N, Mh, nnz, idx, val)
+    params = [_params(N, 1e-9, 1e-8) for (N, *_r) in inst]
+    rc_b, reps_b, Db, singles, Hs = _run(inst, params)
+    for q, (N, Mh, nnz, idx, val) in enumerate(inst):
+        po = oracle.make_params(N // 4, 1e-9, 1e-8, max_iter=100, tau_fp32=1e-7, switch_eta=1e-3)
+        rc_o, Do, ro = oracle.sp2(oracle.Ell(N, Mh, nnz, idx, val), po, Mo=N)
+        assert reps_b[q]["status"] == rc_o == E.ELL_OK
+        for k in ("trx", "trx2", "eta2"):
+            assert np.array_equal(reps_b[q][k].view(np.uint64), ro[k].view(np.uint64)), k
+        assert np.array_equal(reps_b[q]["up"], ro["up"])
+        assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
+    _check(rc_b, reps_b, Db, singles)
+
+
 def test_batched_mixed_and_fp64_instances_together():
     specs = [(128, 4, 21), (256, 8, 22), (512, 16, 23), (700, 21, 24), (64, 4, 25)]
     inst = _instances(specs)
