@@ -361,6 +361,19 @@ def test_sp2_small_and_ragged_sizes():
         assert_same_trajectory(o, g)
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("N", [1000, 777])
+def test_sp2_ragged_sizes_with_pruned_window_ends(N, mixed):
+    """N not a multiple of 16 or 64 (a last wavefront of 8 or 9 rows, a last
+    workgroup with idle wavefronts) at tau = 1e-9 (FP32 steps 1e-7), where
+    the ends of a row group's column window are often blocks that keep
+    nothing and lie outside X: the whole trajectory against the oracle."""
+    o, g = sp2_both(N, 10, 1e-9, 1e-6 if mixed else 1e-7, M=64, max_iter=150, mixed=mixed, tau32=1e-7,
+                    switch_eta=1e-2)
+    assert o[0] == 0
+    assert_same_trajectory(o, g)
+
+
 def test_sp2_deterministic_and_poll_independent():
     N, b = 400, 8
     nnz, idx, val, Mh = synth.banded_hamiltonian(N, b, seed=3)
