@@ -444,10 +444,11 @@ int run_step_band16(const ellpack *X, ellpack *Y, ellpack *U, double tau, int32_
   SpanMem<T> sx, sy, su;
   HIP_TRY(sx.alloc(N, sw));
   HIP_TRY(sy.alloc(N, sw));
-  HIP_TRY(su.alloc(N, sw));
+  if (U) HIP_TRY(su.alloc(N, sw));
   HIP_TRY(launch_ell_to_span<T>(N, view<T>(X), sx.v(), X->stream));
-  const SpanRot3<T> spans{{sx.v(), sy.v(), su.v()}};  // X^2 to slot 1, 2X - X^2 to slot 2
-  HIP_TRY(launch_x2_band16<T>(N, spans, nullptr, (T)tau, m.s, m.s.flags, X->stream));
+  // X^2 to slot 1, 2X - X^2 to slot 2 (without U: X^2 alone, slot 2 untouched)
+  const SpanRot3<T> spans{{sx.v(), sy.v(), U ? su.v() : sy.v()}};
+  HIP_TRY(launch_x2_band16<T>(N, spans, nullptr, (T)tau, m.s, m.s.flags, X->stream, U != nullptr));
   HIP_TRY(launch_reduce(N, nullptr, m.s, X->stream));
   HIP_TRY(launch_final_only(m.s, X->stream));
   int32_t fb = 0, w[4];

@@ -153,8 +153,10 @@ __device__ __forceinline__ void mma_block(const SpanView<T> &X, const __amdgpu_b
 // One wave: output rows i0 .. i0 + nrows - 1 (nrows <= 16) of X^2 and 2X - X^2.
 // `once`: 2X - X^2 and the norm take the unpruned X^2 (one pruning per
 // iteration); otherwise the pruned X^2.  SYMA: X is bitwise symmetric (the A
-// operand is read through the symmetry).
-template <typename T, bool SYMA = false>
+// operand is read through the symmetry).  WITH_U false: a standalone product
+// without the 2X - X^2 output (SU is neither read nor written; its widths
+// read 0).
+template <typename T, bool SYMA = false, bool WITH_U = true>
 __device__ void rows16(const int N, const int i0, const int nrows, const SpanView<T> X, const SpanView<T> SY,
                        const SpanView<T> SU, const T tau, const bool once, const StepScratch &s, double *stk,
                        double *sq, int2 *meta, [[maybe_unused]] int32_t *fallback)
@@ -179,8 +181,10 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
       const int i = i0 + r;
       SY.base[i] = 0;
       SY.len[i] = 0;
-      SU.base[i] = 0;
-      SU.len[i] = 0;
+      if (WITH_U) {
+        SU.base[i] = 0;
+        SU.len[i] = 0;
+      }
       s.wy[i] = 0;
       s.wu[i] = 0;
       if (s.ly) s.ly[i] = 0;
@@ -324,7 +328,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
         yk[p] = ky[p] ? y : T(0);
         const T ym = once ? y : yk[p];  // the X^2 value 2X - X^2 and the norm see
         const T v = T(2) * x - ym;
-        ku[p] = act && absv(v) > tau;
+        ku[p] = WITH_U && act && absv(v) > tau;
         uk[p] = ku[p] ? v : T(0);
         const double d = (double)ym - (double)x;
         e[p] = d * d;
@@ -333,7 +337,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
 #pragma unroll
       for (int p = 0; p < kP; ++p) {
         my[p] = __ballot(ky[p]);
-        mu[p] = __ballot(ku[p]);
+        mu[p] = WITH_U ? __ballot(ku[p]) : 0;
       }
       // (a quad whose rows keep nothing of X^2, or of 2X - X^2, in this block
       // leaves that output's row state as it is and writes nothing to it)
@@ -345,7 +349,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
 #pragma unroll
         for (int p = 0; p < kP; ++p) put<T>(yr, ry[t].first, ly, p0 + 16 * p + r, i * SW, SW, act, yk[p]);
       }
-      if ((mu[0] | mu[1] | mu[2] | mu[3]) != 0) {
+      if (WITH_U && (mu[0] | mu[1] | mu[2] | mu[3]) != 0) {
         row_bits(mu, q, lo, hi);
         const int lu = ru[t].add(lo, hi, p0, gu);
 #pragma unroll
@@ -356,7 +360,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
       for (int p = 0; p < kP; ++p) sq[rr * kWave + 16 * p + r] = e[p];
       if (__ballot(gy < p0 || gu < p0)) {
         fill_gap<T>(yr, ry[t].first, gy, p0, r, i * SW, SW, act);
-        fill_gap<T>(ur, ru[t].first, gu, p0, r, i * SW, SW, act);
+        if (WITH_U) fill_gap<T>(ur, ru[t].first, gu, p0, r, i * SW, SW, act);
       }
       if (diag) {
 #pragma unroll
@@ -428,8 +432,10 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
       const int ylen = ry[t].length(), ulen = ru[t].length();
       SY.base[i] = ylen ? ry[t].first : 0;
       SY.len[i] = ylen;
-      SU.base[i] = ulen ? ru[t].first : 0;
-      SU.len[i] = ulen;
+      if (WITH_U) {
+        SU.base[i] = ulen ? ru[t].first : 0;
+        SU.len[i] = ulen;
+      }
       s.wy[i] = ry[t].count;
       s.wu[i] = ru[t].count;
       if (s.ly) s.ly[i] = ylen;
@@ -442,7 +448,7 @@ __device__ void rows16(const int N, const int i0, const int nrows, const SpanVie
   }
 }
 
-template <typename T>
+template <typename T, bool WITH_U>
 __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, StepScratch s,
                                                    int32_t *fallback)
 {
@@ -461,8 +467,8 @@ __global__ __launch_bounds__(256) void k_x2_band16(int N, SpanRot3<T> spans, con
   const int i0 = grp * kR;
   if (i0 >= N) return;
   const int cy = cur == 2 ? 0 : cur + 1, cu = cur == 0 ? 2 : cur - 1;
-  rows16<T>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, once, s, stk_s[w], sq_s[w],
-            meta_s[w], fallback);
+  rows16<T, false, WITH_U>(N, i0, min(kR, N - i0), spans.b[cur], spans.b[cy], spans.b[cu], tau, once, s, stk_s[w],
+                           sq_s[w], meta_s[w], fallback);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,17 +632,20 @@ bool x2_band16_fits(int N, int SW, int elem_bytes) { return (int64_t)N * SW * el
 
 template <typename T>
 hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
-                            int32_t *fallback, hipStream_t stream)
+                            int32_t *fallback, hipStream_t stream, bool with_u)
 {
   const int groups = (N + kR - 1) / kR;
   const dim3 grid((groups + kWpb - 1) / kWpb), block(kWpb * kWave);
-  hipLaunchKernelGGL(k_x2_band16<T>, grid, block, 0, stream, N, spans, st, tau, s, fallback);
+  if (with_u)
+    hipLaunchKernelGGL((k_x2_band16<T, true>), grid, block, 0, stream, N, spans, st, tau, s, fallback);
+  else
+    hipLaunchKernelGGL((k_x2_band16<T, false>), grid, block, 0, stream, N, spans, st, tau, s, fallback);
   return hipGetLastError();
 }
 template hipError_t launch_x2_band16<double>(int, SpanRot3<double>, const SP2State *, double, const StepScratch &,
-                                             int32_t *, hipStream_t);
+                                             int32_t *, hipStream_t, bool);
 template hipError_t launch_x2_band16<float>(int, SpanRot3<float>, const SP2State *, float, const StepScratch &,
-                                            int32_t *, hipStream_t);
+                                            int32_t *, hipStream_t, bool);
 
 template <typename T>
 hipError_t launch_x2_band16_part(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,

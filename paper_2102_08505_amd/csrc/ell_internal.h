@@ -169,11 +169,12 @@ template <typename T>
 hipError_t launch_x2_band(int N, SpanRot3<T> spans, Rot3<T> ells, const SP2State *st, bool with_u, bool out_ell,
                           T tau, const StepScratch &s, int32_t *fallback, hipStream_t stream);
 // Span-form X^2 on the matrix cores (ell_band16.hip): the kernel of the SP2
-// iteration when every matrix of the rotation fits 2^31 bytes
+// iteration when every matrix of the rotation fits 2^31 bytes; with_u false:
+// X^2 only (a standalone product without the 2X - X^2 output)
 bool x2_band16_fits(int N, int SW, int elem_bytes);
 template <typename T>
 hipError_t launch_x2_band16(int N, SpanRot3<T> spans, const SP2State *st, T tau, const StepScratch &s,
-                            int32_t *fallback, hipStream_t stream);
+                            int32_t *fallback, hipStream_t stream, bool with_u = true);
 // The SP2 iteration on the span form in two launches (ell_band16.hip): X^2,
 // the row outputs and 64-row partial sums (needs x2_band16_fits and s sized for
 // N rows: s.nq == ceil(N / 64) <= 16384); then the upper reduction levels and
