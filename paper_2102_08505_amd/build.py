@@ -24,10 +24,13 @@ HIPCC_FLAGS = [
     "-Wall",
 ]
 
-# The matrix-core band kernel keeps its accumulators in VGPRs: with the
-# compiler's AGPR choice they are copied between the two files every step.
+# The matrix-core kernels keep their accumulators in VGPRs: with the
+# compiler's AGPR choice they are copied between the two files every step (the
+# dense GEMMs: all 128 accumulator registers twice per k-slice, and the FP64
+# GEMM then needs 344 registers, one wavefront per SIMD, against 222).
 EXTRA_FLAGS = {"ell_band16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
-               "ell_sym16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+               "ell_sym16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               "dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose=False, jobs=4):
