@@ -133,6 +133,46 @@ __global__ __launch_bounds__(256) void k_transpose64(int N, DSel<double> sel, do
   }
 }
 
+// ---- tile order of the GEMMs ---------------------------------------------------------
+// Launch block b computes output tile (tr, tc) of an nt x nt grid of tiles (with
+// SYM only those on and above the diagonal, tc >= tr).  The hardware deals the
+// blocks to the chip's 8 XCDs in turn, so block b is first mapped to position
+// t = (b mod 8) (nb / 8) + b / 8 of a single order, and each XCD runs a
+// contiguous stretch of it; the order walks groups of kTileGroup tile rows
+// column by column, so the blocks an XCD runs at once share a few row and
+// column panels of the operands in its L2 instead of each reading its own.
+constexpr int kXcds = 8, kTileGroup = 8;
+__host__ __device__ inline int tile_count(int nt, bool sym) { return sym ? nt * (nt + 1) / 2 : nt * nt; }
+__host__ __device__ inline void tile_of(int b, int nb, int nt, bool sym, int &tr, int &tc)
+{
+  const int per = nb / kXcds, full = per * kXcds;
+  int t = b < full ? (b % kXcds) * per + b / kXcds : b;
+  for (int r0 = 0; r0 < nt; r0 += kTileGroup) {
+    const int rows = nt - r0 < kTileGroup ? nt - r0 : kTileGroup;
+    const int tri = sym ? rows * (rows + 1) / 2 : 0;  // the group's tiles in its diagonal block (SYM)
+    const int cnt = sym ? tri + rows * (nt - r0 - rows) : rows * nt;
+    if (t >= cnt) {
+      t -= cnt;
+      continue;
+    }
+    if (!sym) {
+      tc = t / rows;
+      tr = r0 + t % rows;
+    } else if (t < tri) {  // column r0 + m holds rows r0 .. r0 + m
+      int m = 0;
+      while ((m + 1) * (m + 2) / 2 <= t) ++m;
+      tc = r0 + m;
+      tr = r0 + (t - m * (m + 1) / 2);
+    } else {
+      t -= tri;
+      tc = r0 + rows + t / rows;
+      tr = r0 + t % rows;
+    }
+    return;
+  }
+  tr = tc = 0;  // (b < nb: not reached)
+}
+
 // ---- BF16x3 GEMM: C = hi.hi + hi.lo + lo.hi, 128 x 128 tile per block ----------------
 // LDS holds 64 k-values per row (A tiles) and per column (B tiles, read from the
 // transposed copies); the next 64-value slice is loaded into registers while
@@ -195,7 +235,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
                                                      const uint16_t *__restrict__ loT, DSel<float> sel)
 {
   __shared__ __attribute__((aligned(16))) uint16_t T4[4][kBM][kLdsK];  // A hi, A lo, B hi, B lo
-  if (SYM && blockIdx.y > blockIdx.x) return;
+  int tr, tc;
+  tile_of(blockIdx.x, gridDim.x, (N + kBM - 1) / kBM, SYM, tr, tc);
   const float *unused;
   float *C;
   if (!resolve(sel, unused, C)) return;
@@ -205,7 +246,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int N, const uint16_t *__re
   }
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int row0 = blockIdx.y * kBM, col0 = blockIdx.x * kBM;
+  const int row0 = tr * kBM, col0 = tc * kBM;
   const uint16_t *const src[4] = {hi, lo, hiT, loT};
   const uint32_t bytes = (uint32_t)((size_t)N * N * 2 > 0xfffffff0u ? 0xfffffff0u : (size_t)N * N * 2);
   const __amdgpu_buffer_rsrc_t rs[4] = {
@@ -306,14 +347,15 @@ template <bool VEC, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_f64(int N, const double *__restrict__ AT, DSel<double> sel)
 {
   __shared__ double As[kDM][kDK + 1], Bs[kDM][kDK + 1];
-  if (SYM && blockIdx.y > blockIdx.x) return;
+  int tr, tc;
+  tile_of(blockIdx.x, gridDim.x, (N + kDM - 1) / kDM, SYM, tr, tc);
   const double *A;
   double *C;
   if (!resolve(sel, A, C)) return;
   if (SYM) AT = A;
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int row0 = blockIdx.y * kDM, col0 = blockIdx.x * kDM;
+  const int row0 = tr * kDM, col0 = tc * kDM;
   const size_t nbytes = (size_t)N * N * 8;
   const uint32_t bytes = (uint32_t)(nbytes > 0xfffffff0u ? 0xfffffff0u : nbytes);
   const __amdgpu_buffer_rsrc_t ra =
@@ -499,7 +541,7 @@ hipError_t product_f32(int N, DSel<float> sel, uint16_t *hi, uint16_t *lo, uint1
 {
   const dim3 tb((N + 31) / 32, (N + 31) / 32);
   hipLaunchKernelGGL(k_split, tb, dim3(256), 0, s, N, sel, hi, lo, sym ? nullptr : hiT, sym ? nullptr : loT);
-  const dim3 gb((N + kBM - 1) / kBM, (N + kBM - 1) / kBM);
+  const dim3 gb(tile_count((N + kBM - 1) / kBM, sym));
   if (N % 8 == 0) {
     if (sym) hipLaunchKernelGGL((k_gemm_bf16x3<true, true>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
     else hipLaunchKernelGGL((k_gemm_bf16x3<true, false>), gb, dim3(256), 0, s, N, hi, lo, hiT, loT, sel);
@@ -515,7 +557,7 @@ hipError_t product_f64(int N, DSel<double> sel, double *XT, hipStream_t s, bool 
 {
   const dim3 tb((N + 31) / 32, (N + 31) / 32);
   if (!sym) hipLaunchKernelGGL(k_transpose64, tb, dim3(256), 0, s, N, sel, XT);
-  const dim3 gb((N + kDM - 1) / kDM, (N + kDM - 1) / kDM);
+  const dim3 gb(tile_count((N + kDM - 1) / kDM, sym));
   if (N % 2 == 0) {
     if (sym) hipLaunchKernelGGL((k_gemm_f64<true, true>), gb, dim3(256), 0, s, N, XT, sel);
     else hipLaunchKernelGGL((k_gemm_f64<true, false>), gb, dim3(256), 0, s, N, XT, sel);
