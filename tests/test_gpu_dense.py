@@ -133,6 +133,23 @@ def test_dense_sp2_f64_matches_oracle(N, b):
     assert np.linalg.norm(D - P) < 1e-6
 
 
+def test_dense_sp2_f64_several_tile_groups():
+    """N = 1100: 9 x 9 output tiles of 128, so the symmetric products' tile
+    order spans two groups of tile rows (8 and 1) and the XCD stretches cut
+    through them; three products against the oracle, bit for bit."""
+    N = 1100
+    H = synth.dense_hamiltonian(N, 12, seed=11)
+    n_occ = N // 4
+    rc, D, rep = _solve(H, E.DENSE_F64, 1e-10, n_occ, max_iter=3)
+    orc, Do, ro = oracle.dense_sp2(H, oracle.DENSE_F64, _oracle_params(n_occ, 1e-10, max_iter=3))
+    assert rc == orc == E.ELL_ENOCONV
+    assert rep["iterations"] == ro["iterations"] == 3
+    assert np.array_equal(rep["up"], ro["up"])
+    for k in ("trx", "trx2", "eta2"):
+        assert np.array_equal(rep[k].view(np.uint64), ro[k].view(np.uint64)), k
+    assert np.array_equal(D.view(np.uint64), Do.view(np.uint64))
+
+
 def test_dense_sp2_f64_hamiltonian_not_bitwise_symmetric():
     """One coupling's two sides one ulp apart: the solve takes the full
     product (a transposed copy, every tile) instead of the mirrored upper
