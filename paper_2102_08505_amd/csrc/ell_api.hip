@@ -66,7 +66,9 @@ int32_t roundup32(int64_t x) { return (int32_t)((x + 31) / 32 * 32); }
 // release; a new owner on another stream waits for that event first, so reuse
 // is ordered after every earlier use.  The cache holds at most kCacheBytes
 // (oldest blocks are freed beyond that).  Without a scope, allocations are
-// plain hipMalloc / hipFree.
+// plain hipMalloc / hipFree; a scope opened with cache = false keeps them so
+// but still names the stream their fills are queued on (a call whose work runs
+// on a non-blocking stream, which does not wait for the null stream).
 thread_local bool g_cache_alloc = false;
 thread_local hipStream_t g_cache_stream = nullptr;
 
@@ -91,9 +93,9 @@ size_t size_class(size_t bytes)
 struct AllocScope {
   bool prev_on;
   hipStream_t prev_stream;
-  explicit AllocScope(hipStream_t s) : prev_on(g_cache_alloc), prev_stream(g_cache_stream)
+  explicit AllocScope(hipStream_t s, bool cache = true) : prev_on(g_cache_alloc), prev_stream(g_cache_stream)
   {
-    g_cache_alloc = true;
+    g_cache_alloc = cache;
     g_cache_stream = s;
   }
   ~AllocScope()
@@ -174,8 +176,10 @@ struct DevMem {
   }
   template <typename T>
   T *as() const { return static_cast<T *>(p); }
+  // fills are queued on the scope's stream (or, outside any scope, are plain hipMemset)
+  bool ordered() const { return cached || stream; }
   // zero the first `n` bytes, ordered like the allocation
-  hipError_t zero(size_t n) const { return cached ? hipMemsetAsync(p, 0, n, stream) : hipMemset(p, 0, n); }
+  hipError_t zero(size_t n) const { return ordered() ? hipMemsetAsync(p, 0, n, stream) : hipMemset(p, 0, n); }
 };
 
 void swap_mem(DevMem &a, DevMem &b)
@@ -294,7 +298,7 @@ int ensure_valid(const ellpack *A)
 
 // Scratch of one fused step for N rows.
 struct StepMem {
-  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags, ticket;
+  DevMem d1, d2, e, wy, wu, ly, lu, part, partw, partn, out, outw, outn, flags;  // flags: the flag, then the ticket
   StepScratch s{};
   hipError_t alloc(int N)
   {
@@ -309,10 +313,9 @@ struct StepMem {
         (err = lu.alloc(sizeof(int32_t) * N)) || (err = part.alloc(sizeof(double) * (5 * nq + 256 * lq))) ||
         (err = partw.alloc(sizeof(int32_t) * 4 * nq)) || (err = partn.alloc(sizeof(int64_t) * 2 * nq)) ||
         (err = out.alloc(sizeof(double) * 5)) || (err = outw.alloc(sizeof(int32_t) * 4)) ||
-        (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(sizeof(int32_t))) ||
-        (err = ticket.alloc(sizeof(uint32_t))))
+        (err = outn.alloc(sizeof(int64_t) * 2)) || (err = flags.alloc(2 * sizeof(int32_t))))
       return err;
-    if ((err = flags.zero(sizeof(int32_t))) || (err = ticket.zero(sizeof(uint32_t)))) return err;
+    if ((err = flags.zero(2 * sizeof(int32_t)))) return err;  // the fallback flag, then the ticket
     s.d1 = d1.as<double>();
     s.d2 = d2.as<double>();
     s.e = e.as<double>();
@@ -321,7 +324,7 @@ struct StepMem {
     s.ly = ly.as<int32_t>();
     s.lu = lu.as<int32_t>();
     s.flags = flags.as<int32_t>();
-    s.ticket = ticket.as<uint32_t>();
+    s.ticket = reinterpret_cast<uint32_t *>(flags.as<int32_t>() + 1);
     s.part = part.as<double>();
     s.partw = partw.as<int32_t>();
     s.partn = partn.as<int64_t>();
@@ -354,7 +357,8 @@ struct SpanMem {
   int32_t SW = 0;
   // zero_values: false when only the symmetric iteration reads the matrices
   // (its reads stay inside the row intervals, which every writer fills)
-  hipError_t alloc(int N, int32_t sw, bool zero_values = true)
+  // zero_intervals false: the caller clears base and len (several matrices' in one launch)
+  hipError_t alloc(int N, int32_t sw, bool zero_values = true, bool zero_intervals = true)
   {
     SW = sw;
     hipError_t e;
@@ -363,8 +367,10 @@ struct SpanMem {
         (e = len.alloc(sizeof(int32_t) * ((size_t)N + kSpanPadRows))))
       return e;
     // rows past N read as empty by the band kernel's batched interval loads
-    if ((e = base.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
-    if ((e = len.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    if (zero_intervals) {
+      if ((e = base.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+      if ((e = len.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows)))) return e;
+    }
     // the guard bands are read (and masked) by the band kernel: keep them finite
     return zero_values ? val.zero(sizeof(T) * ((size_t)N * sw + 2 * kSpanGuard)) : hipSuccess;
   }
@@ -931,9 +937,26 @@ struct SpanSet {
   hipError_t alloc(int N, int32_t sw, bool zero_values = true)
   {
     SW = sw;
+    // the six interval arrays in one launch on the blocks' stream (outside an
+    // allocation scope that names a stream, each with its own hipMemset)
+    ZeroList z{};
+    bool one = true;
     for (int b = 0; b < 3; ++b) {
-      hipError_t e = m[b].alloc(N, sw, zero_values);
+      hipError_t e = m[b].alloc(N, sw, zero_values, false);
       if (e) return e;
+      one = one && m[b].base.ordered() && m[b].len.ordered() && m[b].base.stream == m[0].base.stream &&
+            m[b].len.stream == m[0].base.stream;
+      z.p[z.count] = m[b].base.template as<int32_t>();
+      z.n[z.count++] = N + kSpanPadRows;
+      z.p[z.count] = m[b].len.template as<int32_t>();
+      z.n[z.count++] = N + kSpanPadRows;
+    }
+    if (one) return launch_zero_list(z, m[0].base.stream);
+    for (int b = 0; b < 3; ++b) {
+      hipError_t e;
+      if ((e = m[b].base.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows))) ||
+          (e = m[b].len.zero(sizeof(int32_t) * ((size_t)N + kSpanPadRows))))
+        return e;
     }
     return hipSuccess;
   }
@@ -1159,7 +1182,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   S.mi = (size_t)p->max_iter;
   HIP_TRY(S.hist.alloc(kHistBytesPerIter * S.mi));
   HIP_TRY(S.init.alloc(sizeof(InitBlock)));
-  const int gb = init_blocks(N);  // Gershgorin partials, one per workgroup
+  const int gb = gersh_blocks(N);  // Gershgorin partials, one per workgroup
   HIP_TRY(S.glo.alloc(sizeof(double) * gb));
   HIP_TRY(S.ghi.alloc(sizeof(double) * gb));
   HIP_TRY(S.wmax.alloc(sizeof(int32_t)));
@@ -1829,6 +1852,9 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   Batch B;
   HIP_TRY(hipStreamCreateWithFlags(&B.st, hipStreamNonBlocking));
   hipStream_t st = B.st;
+  // the batch's buffers are plain allocations whose fills are queued on st,
+  // ahead of the kernels that write them
+  AllocScope fills_on_st(st, false);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   struct Ev {
     hipEvent_t &a, &b;
@@ -1846,8 +1872,8 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   int maxN = 0;
   for (int32_t q = 0; q < n; ++q) maxN = std::max(maxN, H[q]->N);
   DevMem glo, ghi, gout, gflags;
-  HIP_TRY(glo.alloc(sizeof(double) * init_blocks(maxN)));
-  HIP_TRY(ghi.alloc(sizeof(double) * init_blocks(maxN)));
+  HIP_TRY(glo.alloc(sizeof(double) * gersh_blocks(maxN)));
+  HIP_TRY(ghi.alloc(sizeof(double) * gersh_blocks(maxN)));
   HIP_TRY(gout.alloc(sizeof(double) * 2 * n));
   HIP_TRY(gflags.alloc(sizeof(int32_t) * n));
   HIP_TRY(hipMemsetAsync(gflags.p, 0, sizeof(int32_t) * n, st));

@@ -2,6 +2,7 @@
 // control block, and the kernel launchers.  Not part of the public ABI.
 #pragma once
 
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -138,7 +139,10 @@ hipError_t launch_decide_batch(int n, SP2State *states, const SP2Cfg *cfgs, cons
 // workgroup, rows strided over at most kInitBlocks workgroups).
 constexpr int kInitBlocks = 1024;
 inline int init_blocks(int N) { return N < 4 * kInitBlocks ? (N + 3) / 4 : kInitBlocks; }
-// Gershgorin bounds of H into emin_emax[0..1] (rowlo, rowhi: init_blocks(N)
+// Workgroups of the Gershgorin kernel: one wavefront per kGershRows rows.
+constexpr int kGershRows = 16, kGershMaxBlocks = 8192;
+inline int gersh_blocks(int N) { return std::min((N + kGershRows - 1) / kGershRows, kGershMaxBlocks); }
+// Gershgorin bounds of H into emin_emax[0..1] (rowlo, rowhi: gersh_blocks(N)
 // doubles of per-workgroup partials); flags |= 2 if H holds a non-finite value
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi,
                              double *emin_emax, int32_t *flags, hipStream_t stream);
@@ -155,6 +159,14 @@ hipError_t launch_copy(int N, EllView<TS> src, EllView<TD> dst, hipStream_t stre
 template <typename T>
 hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stream);
 hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream);
+// up to eight int32 arrays cleared by one launch (the setup's interval arrays,
+// which separate fills would each pay a host call and a device idle for)
+struct ZeroList {
+  int32_t *p[8];
+  int n[8];
+  int count;
+};
+hipError_t launch_zero_list(const ZeroList &z, hipStream_t stream);
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
 // *flag |= 1 unless every stored H_ij has a stored H_ji with the same bits

@@ -19,6 +19,7 @@
 // Row spans wider than the window are processed in several passes over
 // consecutive column windows; every pass re-reads the rows k and keeps only
 // the entries of its window, so the result does not depend on the window.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -830,66 +831,73 @@ __global__ __launch_bounds__(256) void k_step_final_batch(SP2State *states, cons
 // --------------------------------------------------------------------------
 // initialisation: Gershgorin bounds and X0
 // --------------------------------------------------------------------------
-// value v of lane u (u the same for the whole wavefront)
-__device__ __forceinline__ double lane_value(double v, int u)
-{
-  const long long b = __double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, u);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), u);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
 
-// One wavefront per row, rows strided over a grid of at most kInitBlocks
-// workgroups: the row's entries are loaded 64 at a time, coalesced, and passed
-// in ascending j to one running sum r = r + |H_ij| (j != i; the diagonal adds
-// +0, which leaves r unchanged since r >= +0); each workgroup writes the min /
-// max of its rows' H_ii - r_i and H_ii + r_i.
-__global__ __launch_bounds__(256) void k_gersh_rows(int N, EllView<double> H, double *plo, double *phi,
-                                                    int32_t *flags)
+// One wavefront per kGershRows consecutive rows (rows strided over the grid).
+// The rows' entries are staged through LDS kGershCols columns at a time, loaded
+// coalesced (consecutive rows are contiguous in the ELLPACK arrays) and all in
+// flight together before the first is stored; then lane
+// t < kGershRows passes row i0 + t's staged entries in ascending j to one
+// running sum r = r + |H_ij| (j != i), so the rows' serial sums run side by
+// side.  Each workgroup writes the min / max of its rows' H_ii - r_i and
+// H_ii + r_i (min and max are exact in any order).
+constexpr int kGershCols = 136;  // 26 KiB of LDS; a 129-entry band row in one pass
+constexpr int kGershStride = kGershCols + 1;  // LDS row stride: the summing lanes hit distinct banks
+constexpr int kGershLoads = kGershRows * kGershCols / kWave;  // staged entries per lane and pass
+static_assert(kGershRows * kGershCols % kWave == 0, "whole loads per lane");
+__global__ __launch_bounds__(kWave) void k_gersh_rows(int N, EllView<double> H, double *plo, double *phi,
+                                                      int32_t *flags)
 {
-  __shared__ double slo[kWavesPerBlock], shi[kWavesPerBlock];
-  const int w = threadIdx.x >> 6, lane = lane_id();
+  __shared__ double sv[kGershRows * kGershStride];
+  __shared__ int32_t sj[kGershRows * kGershStride];
+  const int lane = threadIdx.x;
   double lo = INFINITY, hi = -INFINITY;
   bool bad = false;
-  for (int i = uniform_i(blockIdx.x * kWavesPerBlock + w); i < N; i += gridDim.x * kWavesPerBlock) {
-    const int n = uniform_i(H.nnz[i]);
+  for (int i0 = blockIdx.x * kGershRows; i0 < N; i0 += gridDim.x * kGershRows) {
+    const int rows = min(kGershRows, N - i0);
+    const int i = i0 + lane;
+    const int n = lane < rows ? H.nnz[i] : 0;
+    int nmax = n;
+    for (int o = kWave / 2; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
     double r = 0.0, hii = 0.0;
-    for (int q1 = 0; q1 < n; q1 += 4 * kWave) {
-      // up to four 64-entry chunks loaded together, then summed in order
-      int j[4];
-      double h[4];
+    for (int q0 = 0; q0 < nmax; q0 += kGershCols) {
+      int jj[kGershLoads];
+      double hh[kGershLoads];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int q = q1 + c * kWave + lane;
-        const bool in = q < n;
-        j[c] = in ? H.idx[(size_t)i * H.M + q] : -1;
-        h[c] = in ? H.val[(size_t)i * H.M + q] : 0.0;
+      for (int k = 0; k < kGershLoads; ++k) {
+        const int e = k * kWave + lane, t = e / kGershCols, q = q0 + e % kGershCols;
+        const bool in = t < rows && q < __shfl(n, t, kWave);  // a stored entry of row i0 + t
+        jj[k] = in ? H.idx[(size_t)(i0 + t) * H.M + q] : 0;
+        hh[k] = in ? H.val[(size_t)(i0 + t) * H.M + q] : 0.0;
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int q0 = q1 + c * kWave;
-        if (q0 >= n) break;  // the same for the whole wavefront
-        const bool in = q0 + lane < n;
-        bad = bad || (in && !isfinite(h[c]));
-        const uint64_t dm = __ballot(j[c] == i);
-        if (dm) hii = lane_value(h[c], __builtin_ctzll(dm));
-        const double a = (in && j[c] != i) ? fabs(h[c]) : 0.0;
-        const int cnt = min(kWave, n - q0);
-        for (int u = 0; u < cnt; ++u) r = r + lane_value(a, u);
+      for (int k = 0; k < kGershLoads; ++k) {
+        const int e = k * kWave + lane, t = e / kGershCols;
+        sj[t * kGershStride + e % kGershCols] = jj[k];
+        sv[t * kGershStride + e % kGershCols] = hh[k];
       }
+      __syncthreads();
+      const int cnt = min(kGershCols, n - q0);  // <= 0 past the row's end and for lanes >= rows
+      for (int c = 0; c < cnt; ++c) {
+        const double h = sv[lane * kGershStride + c];
+        bad = bad || !isfinite(h);
+        if (sj[lane * kGershStride + c] == i) hii = h;
+        else r = r + fabs(h);
+      }
+      __syncthreads();
     }
-    lo = fmin(lo, hii - r);
-    hi = fmax(hi, hii + r);
+    if (lane < rows) {
+      lo = fmin(lo, hii - r);
+      hi = fmax(hi, hii + r);
+    }
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, kWave));
+    hi = fmax(hi, __shfl_xor(hi, o, kWave));
   }
   if (__ballot(bad) && lane == 0) atomicOr(flags, 2);
   if (lane == 0) {
-    slo[w] = lo;
-    shi[w] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    plo[blockIdx.x] = fmin(fmin(slo[0], slo[1]), fmin(slo[2], slo[3]));
-    phi[blockIdx.x] = fmax(fmax(shi[0], shi[1]), fmax(shi[2], shi[3]));
+    plo[blockIdx.x] = lo;
+    phi[blockIdx.x] = hi;
   }
 }
 
@@ -1082,6 +1090,13 @@ __global__ __launch_bounds__(256) void k_zero_words(int n, int32_t *p)
   if (i < n) p[i] = 0;
 }
 
+// every array of the list, in one launch (grid-stride over each)
+__global__ __launch_bounds__(256) void k_zero_list(ZeroList z)
+{
+  for (int a = 0; a < z.count; ++a)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < z.n[a]; i += gridDim.x * 256) z.p[a][i] = 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_trace_rows(int N, EllView<T> A, double *d)
 {
@@ -1218,8 +1233,8 @@ hipError_t launch_final_only(const StepScratch &s, hipStream_t stream)
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi, double *emin_emax,
                              int32_t *flags, hipStream_t stream)
 {
-  const int nb = init_blocks(N);
-  hipLaunchKernelGGL(k_gersh_rows, dim3(nb), dim3(256), 0, stream, N, H, rowlo, rowhi, flags);
+  const int nb = gersh_blocks(N);
+  hipLaunchKernelGGL(k_gersh_rows, dim3(nb), dim3(kWave), 0, stream, N, H, rowlo, rowhi, flags);
   hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(256), 0, stream, nb, rowlo, rowhi, emin_emax);
   return hipGetLastError();
 }
@@ -1279,6 +1294,15 @@ hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream)
 {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, stream, n, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_list(const ZeroList &z, hipStream_t stream)
+{
+  int most = 0;
+  for (int a = 0; a < z.count; ++a) most = std::max(most, z.n[a]);
+  if (most <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_list, dim3(std::min((most + 255) / 256, 1024)), dim3(256), 0, stream, z);
   return hipGetLastError();
 }
 

@@ -111,3 +111,20 @@ def test_semiconductor_x2_at_32000_orbitals_sampled_rows():
         assert np.array_equal(gi[i, :nz[q]], ix[q, :nz[q]]), i
         assert np.array_equal(gv[i, :nz[q]].view(np.uint64), vl[q, :nz[q]].view(np.uint64)), i
     assert w == int(G.nnz.max())
+
+
+@pytest.mark.parametrize("N,per_row", [(3001, 200), (1000, 250)])
+def test_gershgorin_bounds_of_rows_spanning_several_chunks(N, per_row):
+    """Rows of several hundred entries (more than one pass of the bounds
+    kernel's staged columns) and a last group of rows cut short by N: the
+    solve's reported emin / emax equal the oracle's Gershgorin bounds, bit
+    for bit (the solve is cut after one product)."""
+    H = scattered_symmetric(N, per_row, seed=34)
+    assert int(H.nnz.max()) > 272
+    rc, lo, hi = oracle.gershgorin(H)
+    assert rc == 0
+    Hd = dev_from_oracle(H)
+    Dd = E.DeviceEll(H.N, H.M + 1)
+    rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(H.N // 4, 1e-6, 1e-6, max_iter=1))
+    assert rc == E.ELL_ENOCONV, E.ellpack_strerror(rc)
+    assert same_float(rep["emin"], lo) and same_float(rep["emax"], hi)
