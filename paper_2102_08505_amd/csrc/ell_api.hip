@@ -972,13 +972,15 @@ struct SpanSet {
 // Results of the initialisation kernels, read by the host with one copy and
 // one synchronisation.
 struct InitBlock {
-  double emin, emax;          // Gershgorin bounds
-  int32_t flags;              // bit 1: H holds a non-finite value
-  int32_t wmax;               // widest row of X0
-  unsigned long long total;   // entries of X0
-  int32_t maxlen;             // longest row interval of X0
-  int32_t xflags;             // bit 2: X0 stores an exact zero
-  int32_t asym;               // bit 0: H is not bitwise symmetric
+  double emin, emax;            // Gershgorin bounds
+  int32_t flags;                // bit 1: H holds a non-finite value
+  int32_t asym;                 // bit 0: an entry above the diagonal has no equal mirror
+  unsigned long long balance;   // entries above minus below the diagonal (H symmetric iff 0 and asym 0)
+  // the X0 results (from wmax on: cleared when X0 is formed again)
+  int32_t wmax;                 // widest row of X0
+  unsigned long long total;     // entries of X0
+  int32_t maxlen;               // longest row interval of X0
+  int32_t xflags;               // bit 2: X0 stores an exact zero
 };
 
 // Per-iteration history, one block of arrays of max_iter entries each (device,
@@ -1210,7 +1212,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
   InitBlock &hi = *S.init_host();
   HIP_TRY(hipMemsetAsync(ib, 0, sizeof(InitBlock), st));
   HIP_TRY(launch_gershgorin(N, view<double>(H), S.glo.as<double>(), S.ghi.as<double>(), &ib->emin, &ib->flags, st));
-  HIP_TRY(launch_check_symmetric(N, view<double>(H), &ib->asym, st));
+  HIP_TRY(launch_check_symmetric(N, view<double>(H), &ib->asym, &ib->balance, st));
   bool first = true;
   for (;;) {
     if (!first) {  // X0 again, wider: clear the X0 results
@@ -1251,7 +1253,7 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     const bool zeros = (hi.xflags & 4) != 0;
     // a bitwise symmetric H gives bitwise symmetric iterates: their rows are
     // read through the symmetry, in runs of kSymAlign columns
-    S.sym = (hi.asym & 1) == 0;
+    S.sym = (hi.asym & 1) == 0 && hi.balance == 0;
     const int32_t pad = S.sym ? 2 * (kSymAlign - 1) : 0;
     const int32_t sw = std::min(std::max(256, roundup64(maxlen + pad)), std::max(64, roundup64(N)));
     // (X0's fill of its intervals does not decide here: the iterates fill them)
@@ -1940,16 +1942,19 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   // ---- bitwise symmetry of every H: if all are, so is every iterate, and the
   // matrix-core step reads its A operand through the symmetry ----
   {
+    // per instance: the flag word, a pad word, then the balance
     DevMem asym;
-    HIP_TRY(asym.alloc(sizeof(int32_t) * B.n));
-    HIP_TRY(launch_zero_words(B.n, asym.as<int32_t>(), st));
+    HIP_TRY(asym.alloc(sizeof(int32_t) * 4 * B.n));
+    HIP_TRY(launch_zero_words(4 * B.n, asym.as<int32_t>(), st));
     for (int m = 0; m < B.n; ++m)
-      HIP_TRY(launch_check_symmetric(B.in[m].N, view<double>(H[B.in[m].q]), asym.as<int32_t>() + m, st));
-    std::vector<int32_t> fl(B.n);
-    HIP_TRY(hipMemcpyAsync(fl.data(), asym.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(launch_check_symmetric(B.in[m].N, view<double>(H[B.in[m].q]), asym.as<int32_t>() + 4 * m,
+                                     reinterpret_cast<unsigned long long *>(asym.as<int32_t>() + 4 * m + 2), st));
+    std::vector<int32_t> fl(4 * (size_t)B.n);
+    HIP_TRY(hipMemcpyAsync(fl.data(), asym.p, sizeof(int32_t) * 4 * B.n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     B.sym = true;
-    for (int32_t f : fl) B.sym = B.sym && (f & 1) == 0;
+    for (int m = 0; m < B.n; ++m)
+      B.sym = B.sym && (fl[4 * m] & 1) == 0 && fl[4 * m + 2] == 0 && fl[4 * m + 3] == 0;
   }
 
   // ---- X0 of every instance in ELLPACK form (capacity grows until it fits) ----

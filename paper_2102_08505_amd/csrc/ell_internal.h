@@ -169,8 +169,12 @@ struct ZeroList {
 hipError_t launch_zero_list(const ZeroList &z, hipStream_t stream);
 template <typename T>
 hipError_t launch_trace_rows(int N, EllView<T> A, double *d, hipStream_t stream);
-// *flag |= 1 unless every stored H_ij has a stored H_ji with the same bits
-hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, hipStream_t stream);
+// Bitwise symmetry of H: *flag |= 1 when a stored H_ij above the diagonal has
+// no stored H_ji with the same bits, and *balance (both zeroed by the caller)
+// gains the entries above the diagonal minus those below it.  H is bitwise
+// symmetric iff neither is nonzero afterwards.
+hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, unsigned long long *balance,
+                                  hipStream_t stream);
 hipError_t launch_tree_sum(int n, const double *d, double *part, double *out, hipStream_t stream);
 // row terms of Tr(AB): d[i] = ascending-j fma chain of A_ij * B_ji
 template <typename TA, typename TB>

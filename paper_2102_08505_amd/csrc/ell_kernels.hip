@@ -1043,17 +1043,28 @@ __global__ __launch_bounds__(256) void k_validate(int N, EllView<T> A, int32_t *
   if (nonfinite) atomicOr(flags, 2);
 }
 
-// Bitwise symmetry of an ELLPACK matrix: one wavefront per row, rows strided
-// over the grid; each lane takes one stored (i, j) and looks it up in row j by
-// bisection.
-__global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag)
+// Bitwise symmetry of an ELLPACK matrix, one wavefront per row (rows strided
+// over the grid).  Each stored (i, j) above the diagonal (j > i) is looked up
+// in row j -- first at the mirror slot, then by bisection -- and *flag |= 1
+// when (j, i) is absent or holds other bits; *balance gains the number of
+// entries above the diagonal minus the number below it.  The mirrors found
+// are distinct entries below the diagonal (one per entry above it), so with a
+// zero balance they are all of them: H is bitwise symmetric iff the flag stays
+// clear and the balance is zero.  (Half the lookups of checking both sides.)
+__global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag,
+                                                         unsigned long long *balance)
 {
-  const int lane = lane_id();
+  __shared__ long long sb[kWavesPerBlock];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
   bool bad = false;
-  for (int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += gridDim.x * kWavesPerBlock) {
+  long long bal = 0;  // this lane's entries above minus below the diagonal
+  for (int i = blockIdx.x * kWavesPerBlock + w; i < N; i += gridDim.x * kWavesPerBlock) {
     const int n = H.nnz[i];
     for (int s = lane; s < n; s += kWave) {
       const int j = H.idx[(size_t)i * H.M + s];
+      if (j < i) --bal;
+      if (j <= i) continue;
+      ++bal;
       const double v = H.val[(size_t)i * H.M + s];
       const int32_t *cj = H.idx + (size_t)j * H.M;
       // first the mirror slot, where (j, i) sits when rows i and j are bands of
@@ -1080,6 +1091,13 @@ __global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> 
     }
   }
   if (__ballot(bad) && lane == 0) atomicOr(flag, 1);
+  for (int o = kWave / 2; o > 0; o >>= 1) bal += __shfl_xor(bal, o, kWave);
+  if (lane == 0) sb[w] = bal;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long t = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    if (t != 0) atomicAdd(balance, (unsigned long long)t);  // (two's complement: a sum of signed counts)
+  }
 }
 
 // n words set to zero (a kernel rather than a memset node, so that a caller
@@ -1284,9 +1302,10 @@ hipError_t launch_validate(int N, EllView<T> A, int32_t *flags, hipStream_t stre
 template hipError_t launch_validate<double>(int, EllView<double>, int32_t *, hipStream_t);
 template hipError_t launch_validate<float>(int, EllView<float>, int32_t *, hipStream_t);
 
-hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, hipStream_t stream)
+hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, unsigned long long *balance,
+                                  hipStream_t stream)
 {
-  hipLaunchKernelGGL(k_check_symmetric, dim3(init_blocks(N)), dim3(256), 0, stream, N, H, flag);
+  hipLaunchKernelGGL(k_check_symmetric, dim3(init_blocks(N)), dim3(256), 0, stream, N, H, flag, balance);
   return hipGetLastError();
 }
 

@@ -108,17 +108,23 @@ def test_batched_mixed_instances_match_the_oracle():
         assert_same_rows(oracle_from_dev(Db[q]), Do, f"D[{q}]")
 
 
-def test_batched_with_an_asymmetric_instance_matches_the_oracle():
-    """One instance's H has a coupling whose two sides differ by one ulp: the
-    batch then reads every A operand directly instead of through the
-    symmetry (the path all-symmetric batches leave), and every instance still
-    equals the oracle bit for bit."""
+@pytest.mark.parametrize("kind", ["ulp", "below", "above"])
+def test_batched_with_an_asymmetric_instance_matches_the_oracle(kind):
+    """One instance's H is not bitwise symmetric: a coupling whose two sides
+    differ by one ulp, or an entry below (above) the diagonal with no partner
+    above (below) it.  The batch then reads every A operand directly instead
+    of through the symmetry (the path all-symmetric batches leave), and every
+    instance still equals the oracle bit for bit."""
     specs = [(64, 4, 21), (120, 5, 22), (200, 6, 23)]
     inst = _instances(specs)
     N, Mh, nnz, idx, val = inst[1]
     D = synth.ell_to_dense(N, Mh, nnz, idx, val)
-    D[7, 9] = np.nextafter(D[7, 9], np.inf)
-    assert D[7, 9] != D[9, 7]
+    if kind == "ulp":
+        D[7, 9] = np.nextafter(D[7, 9], np.inf)
+        assert D[7, 9] != D[9, 7]
+    else:
+        assert D[9, 2] == 0.0 and D[2, 9] == 0.0  # outside the band
+        D[(9, 2) if kind == "below" else (2, 9)] = 0.01
     nnz, idx, val, Mh = synth.dense_to_ell(D)
     inst[1] = (N, Mh, nnz, idx, val)
     params = [_params(N, 1e-9, 1e-8) for (N, *_r) in inst]

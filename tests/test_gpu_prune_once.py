@@ -42,6 +42,18 @@ def asymmetric(N, b, seed):
     return (N, *_ell(D))
 
 
+def pattern_asymmetric(N, b, seed, below):
+    """A banded Hamiltonian plus one entry outside the band with no partner:
+    below the diagonal (found only by counting the entries on each side) or
+    above it (found by looking up its mirror)."""
+    nnz, idx, val, M = synth.banded_hamiltonian(N, b, seed=seed)
+    D = synth.ell_to_dense(N, M, nnz, idx, val)
+    i, j = (300, 10) if below else (10, 300)
+    assert D[i, j] == 0.0 and D[j, i] == 0.0
+    D[i, j] = 0.02
+    return (N, *_ell(D))
+
+
 def _ell(D):
     nnz, idx, val, M = synth.dense_to_ell(D)
     return M, nnz, idx, val
@@ -64,6 +76,14 @@ def test_two_output_iteration_for_a_hamiltonian_not_bitwise_symmetric(once, mixe
     o, g = both(N, M, nnz, idx, val, 1e-9, 1e-6 if mixed else 1e-7, once, mixed=mixed)
     assert_same_trajectory(o, g)
     assert g[0] == E.ELL_OK
+
+
+@pytest.mark.parametrize("below", [True, False])
+def test_two_output_iteration_for_a_hamiltonian_with_an_unpaired_entry(below):
+    N, M, nnz, idx, val = pattern_asymmetric(512, 16, seed=3, below=below)
+    o, g = both(N, M, nnz, idx, val, 1e-9, 1e-7, 0)
+    assert_same_trajectory(o, g)
+    assert g[0] == o[0]
 
 
 def test_prune_once_changes_the_trajectory():
