@@ -978,7 +978,8 @@ struct InitBlock {
   unsigned long long balance;   // entries above minus below the diagonal (H symmetric iff 0 and asym 0)
   // the X0 results (from wmax on: cleared when X0 is formed again)
   int32_t wmax;                 // widest row of X0
-  unsigned long long total;     // entries of X0
+  unsigned long long total;     // entries of X0 (the extent kernel's sums: then
+  unsigned long long lensum;    //   the summed row interval lengths)
   int32_t maxlen;               // longest row interval of X0
   int32_t xflags;               // bit 2: X0 stores an exact zero
 };
@@ -1220,13 +1221,13 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
     }
     if (mixed) {
       HIP_TRY(W32.alloc(N, cap));
-      HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), &ib->emin, (float)p->tau_fp32, &ib->wmax, &ib->total,
+      HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), &ib->emin, (float)p->tau_fp32, &ib->wmax, nullptr,
                                st));
-      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, nullptr, st));
+      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, &ib->total, st));
     } else {
       HIP_TRY(W64.alloc(N, cap));
-      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), &ib->emin, p->tau, &ib->wmax, &ib->total, st));
-      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, nullptr, st));
+      HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), &ib->emin, p->tau, &ib->wmax, nullptr, st));
+      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, &ib->total, st));
     }
     HIP_TRY(hipMemcpyAsync(&hi, ib, sizeof(InitBlock), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

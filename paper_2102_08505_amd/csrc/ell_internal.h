@@ -146,6 +146,8 @@ inline int gersh_blocks(int N) { return std::min((N + kGershRows - 1) / kGershRo
 // doubles of per-workgroup partials); flags |= 2 if H holds a non-finite value
 hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *rowhi,
                              double *emin_emax, int32_t *flags, hipStream_t stream);
+// X0 of H into X: *wmax (zeroed by the caller) gets the widest row's count
+// of kept entries, *total (zeroed, or null) their sum
 template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau,
                      int32_t *wmax, unsigned long long *total, hipStream_t stream);

@@ -928,8 +928,10 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
 // X0 = (emax I - H) inv, pruned, one wavefront per row (rows strided over at
 // most kInitBlocks workgroups): the entries of row i in ascending column order,
 // with the diagonal entry (emax - 0) inv put in its place when H stores none;
-// kept values are compacted in order by ballot prefix counts, in one pass.  One atomic max
-// and one atomic add per workgroup report the widest row and the total count.
+// kept values are compacted in order by ballot prefix counts, in one pass.  Per
+// workgroup, an atomic max reports the widest row (skipped when the maximum
+// already stored is as wide: after the first workgroups, nearly always) and,
+// when `total` is given, an atomic add the count of kept entries.
 template <typename T>
 __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, const double *ee, double emax,
                                             double inv, T tau, int32_t *wmax, unsigned long long *total)
@@ -1001,8 +1003,9 @@ __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T>
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicMax(wmax, max(max(smax[0], smax[1]), max(smax[2], smax[3])));
-    atomicAdd(total, ssum[0] + ssum[1] + ssum[2] + ssum[3]);
+    const int m = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+    if (m > __hip_atomic_load(wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(wmax, m);
+    if (total) atomicAdd(total, ssum[0] + ssum[1] + ssum[2] + ssum[3]);
   }
 }
 
@@ -1257,11 +1260,14 @@ hipError_t launch_gershgorin(int N, EllView<double> H, double *rowlo, double *ro
   return hipGetLastError();
 }
 
+// X0's workgroups: one wavefront per row up to 32768 rows
+static int x0_blocks(int N) { return std::min((N + kWavesPerBlock - 1) / kWavesPerBlock, 8192); }
+
 template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, double emax, double inv, T tau, int32_t *wmax,
                      unsigned long long *total, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, (const double *)nullptr, emax,
+  hipLaunchKernelGGL((k_x0<T>), dim3(x0_blocks(N)), dim3(256), 0, stream, N, H, X, (const double *)nullptr, emax,
                      inv, tau, wmax, total);
   return hipGetLastError();
 }
@@ -1269,7 +1275,7 @@ template <typename T>
 hipError_t launch_x0(int N, EllView<double> H, EllView<T> X, const double *emin_emax, T tau, int32_t *wmax,
                      unsigned long long *total, hipStream_t stream)
 {
-  hipLaunchKernelGGL((k_x0<T>), dim3(init_blocks(N)), dim3(256), 0, stream, N, H, X, emin_emax, 0.0, 0.0, tau, wmax,
+  hipLaunchKernelGGL((k_x0<T>), dim3(x0_blocks(N)), dim3(256), 0, stream, N, H, X, emin_emax, 0.0, 0.0, tau, wmax,
                      total);
   return hipGetLastError();
 }

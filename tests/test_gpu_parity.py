@@ -501,6 +501,14 @@ def test_sp2_report_per_iteration_bytes_and_times():
     rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-8, 1e-7))
     assert rc == E.ELL_OK and rep["x2_launches"] == 0 and rep["x2_seconds"] == 0.0
     assert rep["x2_bytes"] == int(rep["x2_bytes_each"].sum()) > 0
+    # the first product's bytes: X0's entries and those of the pruned X0^2
+    # (12 bytes each in FP64) plus one 4-byte row count per row of each
+    H = oracle.Ell(N, Mh, nnz, idx, val)
+    _, lo, hi = oracle.gershgorin(H)
+    rc0, X0, _ = oracle.x0(H, lo, hi, 1e-8)
+    rc1, Y, _, _, _ = oracle.x2(X0, 1e-8, M2=N)
+    assert rc0 == rc1 == 0
+    assert rep["x2_bytes_each"][0] == 12 * int(X0.nnz.sum()) + 12 * int(Y.nnz.sum()) + 8 * N
     rc, rep = E.sp2_solve(Hd.h, Dd.h, E.sp2_params(N // 4, 1e-8, 1e-7, profile=1))
     assert rc == E.ELL_OK and rep["x2_launches"] == rep["iterations"]
     each = rep["x2_seconds_each"]
