@@ -1871,18 +1871,30 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   HIP_TRY(hipEventCreate(&t1));
   HIP_TRY(hipEventRecord(t0, st));
 
-  // ---- Gershgorin bounds of every instance (one synchronisation) ----
-  int maxN = 0;
-  for (int32_t q = 0; q < n; ++q) maxN = std::max(maxN, H[q]->N);
-  DevMem glo, ghi, gout, gflags;
-  HIP_TRY(glo.alloc(sizeof(double) * gersh_blocks(maxN)));
-  HIP_TRY(ghi.alloc(sizeof(double) * gersh_blocks(maxN)));
+  // ---- Gershgorin bounds of every instance (one launch, one synchronisation) ----
+  std::vector<InitInst> gin_h(n);
+  std::vector<int32_t> gw(n);
+  int gwork = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    gin_h[q] = InitInst{};
+    gin_h[q].H = view<double>(H[q]);
+    gin_h[q].N = H[q]->N;
+    gin_h[q].w0 = gw[q] = gwork;
+    gin_h[q].nw = gersh_blocks(H[q]->N);
+    gwork += gin_h[q].nw;
+  }
+  DevMem gin, gws, glo, ghi, gout, gflags;
+  HIP_TRY(gin.alloc(sizeof(InitInst) * n));
+  HIP_TRY(gws.alloc(sizeof(int32_t) * n));
+  HIP_TRY(glo.alloc(sizeof(double) * gwork));
+  HIP_TRY(ghi.alloc(sizeof(double) * gwork));
   HIP_TRY(gout.alloc(sizeof(double) * 2 * n));
   HIP_TRY(gflags.alloc(sizeof(int32_t) * n));
+  HIP_TRY(hipMemcpyAsync(gin.p, gin_h.data(), sizeof(InitInst) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(gws.p, gw.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(gflags.p, 0, sizeof(int32_t) * n, st));
-  for (int32_t q = 0; q < n; ++q)
-    HIP_TRY(launch_gershgorin(H[q]->N, view<double>(H[q]), glo.as<double>(), ghi.as<double>(),
-                              gout.as<double>() + 2 * q, gflags.as<int32_t>() + q, st));
+  HIP_TRY(launch_gershgorin_multi(gin.as<InitInst>(), gws.as<int32_t>(), n, gwork, glo.as<double>(),
+                                  ghi.as<double>(), gout.as<double>(), gflags.as<int32_t>(), st));
   std::vector<double> ee(2 * (size_t)n);
   std::vector<int32_t> gf(n);
   HIP_TRY(hipMemcpyAsync(ee.data(), gout.p, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st));
@@ -1944,12 +1956,25 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   // matrix-core step reads its A operand through the symmetry ----
   {
     // per instance: the flag word, a pad word, then the balance
-    DevMem asym;
+    std::vector<InitInst> ci(B.n);
+    std::vector<int32_t> cw(B.n);
+    int cwork = 0;
+    for (int m = 0; m < B.n; ++m) {
+      ci[m] = InitInst{};
+      ci[m].H = view<double>(H[B.in[m].q]);
+      ci[m].N = B.in[m].N;
+      ci[m].w0 = cw[m] = cwork;
+      ci[m].nw = sym_blocks(B.in[m].N);
+      cwork += ci[m].nw;
+    }
+    DevMem asym, cin, cws;
     HIP_TRY(asym.alloc(sizeof(int32_t) * 4 * B.n));
+    HIP_TRY(cin.alloc(sizeof(InitInst) * B.n));
+    HIP_TRY(cws.alloc(sizeof(int32_t) * B.n));
+    HIP_TRY(hipMemcpyAsync(cin.p, ci.data(), sizeof(InitInst) * B.n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(cws.p, cw.data(), sizeof(int32_t) * B.n, hipMemcpyHostToDevice, st));
     HIP_TRY(launch_zero_words(4 * B.n, asym.as<int32_t>(), st));
-    for (int m = 0; m < B.n; ++m)
-      HIP_TRY(launch_check_symmetric(B.in[m].N, view<double>(H[B.in[m].q]), asym.as<int32_t>() + 4 * m,
-                                     reinterpret_cast<unsigned long long *>(asym.as<int32_t>() + 4 * m + 2), st));
+    HIP_TRY(launch_check_symmetric_multi(cin.as<InitInst>(), cws.as<int32_t>(), B.n, cwork, asym.as<int32_t>(), st));
     std::vector<int32_t> fl(4 * (size_t)B.n);
     HIP_TRY(hipMemcpyAsync(fl.data(), asym.p, sizeof(int32_t) * 4 * B.n, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1959,56 +1984,72 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   }
 
   // ---- X0 of every instance in ELLPACK form (capacity grows until it fits) ----
+  // One launch per precision over the packed rows.  Rows that hold no X0 of a
+  // precision (other instances, the padding between instances) keep 0 entries
+  // in its buffer, so that the whole-buffer launches below leave them empty.
   int32_t cap0 = 32;
   for (const BatchInst &I : B.in)
     cap0 = std::max(cap0, std::min(roundup32(std::min<int64_t>((int64_t)H[I.q]->M + 1, I.N)), kMaxCap));
+  std::vector<InitInst> xi(B.n);
+  std::vector<int32_t> xr(B.n);
+  for (int m = 0; m < B.n; ++m) {
+    const BatchInst &I = B.in[m];
+    xi[m] = InitInst{};
+    xi[m].H = view<double>(H[I.q]);
+    xi[m].N = I.N;
+    xi[m].r0 = xr[m] = I.r0;  // (ascending in m)
+    xi[m].f32 = I.mixed ? 1 : 0;
+    xi[m].emax = I.emax;
+    xi[m].inv = 1.0 / (I.emax - I.emin);
+    xi[m].tau = I.mixed ? p[I.q].tau_fp32 : p[I.q].tau;
+  }
   WorkSet<double> X64;
   WorkSet<float> X32;
-  DevMem wmax, total, lens, xflags;
-  HIP_TRY(wmax.alloc(sizeof(int32_t) * B.n));
-  HIP_TRY(total.alloc(sizeof(unsigned long long) * B.n));
-  HIP_TRY(lens.alloc(sizeof(int32_t) * B.NT));
-  HIP_TRY(xflags.alloc(sizeof(int32_t) * B.n));
-  std::vector<int32_t> w0(B.n);
+  DevMem xin, xrs, rowc, lens64, lens32, xflags;
+  HIP_TRY(xin.alloc(sizeof(InitInst) * B.n));
+  HIP_TRY(xrs.alloc(sizeof(int32_t) * B.n));
+  HIP_TRY(rowc.alloc(sizeof(int32_t) * B.NT));
+  HIP_TRY(lens64.alloc(sizeof(int32_t) * B.NT));
+  if (B.any32) HIP_TRY(lens32.alloc(sizeof(int32_t) * B.NT));
+  HIP_TRY(xflags.alloc(sizeof(int32_t) * 2));
+  HIP_TRY(hipMemcpyAsync(xin.p, xi.data(), sizeof(InitInst) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(xrs.p, xr.data(), sizeof(int32_t) * B.n, hipMemcpyHostToDevice, st));
+  HIP_TRY(rowc.zero(sizeof(int32_t) * B.NT));
+  std::vector<int32_t> hc(B.NT), w0(B.n);
   std::vector<unsigned long long> nz0(B.n);
   for (;;) {
-    HIP_TRY(hipMemsetAsync(wmax.p, 0, sizeof(int32_t) * B.n, st));
-    HIP_TRY(hipMemsetAsync(total.p, 0, sizeof(unsigned long long) * B.n, st));
     X64.release();
     X32.release();
     // one temporary slot set of each precision in use (only buffer 0 is used)
     HIP_TRY(X64.nnz[0].alloc(sizeof(int32_t) * B.NT));
     HIP_TRY(X64.idx[0].alloc(sizeof(int32_t) * (size_t)B.NT * cap0));
     HIP_TRY(X64.val[0].alloc(sizeof(double) * (size_t)B.NT * cap0));
+    HIP_TRY(X64.nnz[0].zero(sizeof(int32_t) * B.NT));
     X64.cap = cap0;
+    HIP_TRY(launch_x0_multi<double>(xin.as<InitInst>(), xrs.as<int32_t>(), B.n, B.NT, X64.v(0), rowc.as<int32_t>(),
+                                    st));
     if (B.any32) {
       HIP_TRY(X32.nnz[0].alloc(sizeof(int32_t) * B.NT));
       HIP_TRY(X32.idx[0].alloc(sizeof(int32_t) * (size_t)B.NT * cap0));
       HIP_TRY(X32.val[0].alloc(sizeof(float) * (size_t)B.NT * cap0));
+      HIP_TRY(X32.nnz[0].zero(sizeof(int32_t) * B.NT));
       X32.cap = cap0;
+      HIP_TRY(launch_x0_multi<float>(xin.as<InitInst>(), xrs.as<int32_t>(), B.n, B.NT, X32.v(0), rowc.as<int32_t>(),
+                                     st));
     }
-    for (int m = 0; m < B.n; ++m) {
-      const BatchInst &I = B.in[m];
-      const double inv = 1.0 / (I.emax - I.emin);
-      if (I.mixed) {
-        EllView<float> v = X32.v(0);
-        v.nnz += I.r0;
-        v.idx += (size_t)I.r0 * cap0;
-        v.val += (size_t)I.r0 * cap0;
-        HIP_TRY(launch_x0<float>(I.N, view<double>(H[I.q]), v, I.emax, inv, (float)p[I.q].tau_fp32,
-                                 wmax.as<int32_t>() + m, total.as<unsigned long long>() + m, st));
-      } else {
-        EllView<double> v = X64.v(0);
-        v.nnz += I.r0;
-        v.idx += (size_t)I.r0 * cap0;
-        v.val += (size_t)I.r0 * cap0;
-        HIP_TRY(launch_x0<double>(I.N, view<double>(H[I.q]), v, I.emax, inv, p[I.q].tau, wmax.as<int32_t>() + m,
-                                  total.as<unsigned long long>() + m, st));
-      }
-    }
-    HIP_TRY(hipMemcpyAsync(w0.data(), wmax.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(nz0.data(), total.p, sizeof(unsigned long long) * B.n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hc.data(), rowc.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    for (int m = 0; m < B.n; ++m) {  // widest row and entries of each X0 (before the capacity cut)
+      const BatchInst &I = B.in[m];
+      int32_t w = 0;
+      unsigned long long t = 0;
+      for (int i = 0; i < I.N; ++i) {
+        w = std::max(w, hc[I.r0 + i]);
+        t += (unsigned long long)hc[I.r0 + i];
+      }
+      w0[m] = w;
+      nz0[m] = t;
+    }
     int32_t wide = 0;
     for (int32_t w : w0) wide = std::max(wide, w);
     if (wide <= cap0) break;
@@ -2030,35 +2071,27 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     }
     cap0 = roundup32(wide);
   }
-  // ---- interval extents; instances the span form cannot hold run on their own ----
-  HIP_TRY(hipMemsetAsync(xflags.p, 0, sizeof(int32_t) * B.n, st));
-  for (int m = 0; m < B.n; ++m) {
-    const BatchInst &I = B.in[m];
-    if (I.solo) continue;
-    if (I.mixed) {
-      EllView<float> v = X32.v(0);
-      v.nnz += I.r0;
-      v.idx += (size_t)I.r0 * cap0;
-      v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<float>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, nullptr, st));
-    } else {
-      EllView<double> v = X64.v(0);
-      v.nnz += I.r0;
-      v.idx += (size_t)I.r0 * cap0;
-      v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_extent<double>(I.N, v, lens.as<int32_t>() + I.r0, xflags.as<int32_t>() + m, nullptr, nullptr, st));
-    }
-  }
-  std::vector<int32_t> hl(B.NT), xf(B.n);
-  HIP_TRY(hipMemcpyAsync(hl.data(), lens.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(xf.data(), xflags.p, sizeof(int32_t) * B.n, hipMemcpyDeviceToHost, st));
+  // ---- interval extents (one launch per precision over the packed rows);
+  // instances the span form cannot hold run on their own ----
+  HIP_TRY(hipMemsetAsync(xflags.p, 0, sizeof(int32_t) * 2, st));
+  HIP_TRY(launch_ell_extent<double>(B.NT, X64.v(0), lens64.as<int32_t>(), xflags.as<int32_t>(), nullptr, nullptr, st));
+  if (B.any32)
+    HIP_TRY(launch_ell_extent<float>(B.NT, X32.v(0), lens32.as<int32_t>(), xflags.as<int32_t>() + 1, nullptr, nullptr,
+                                     st));
+  std::vector<int32_t> hl64(B.NT), hl32(B.any32 ? B.NT : 0), xf(2);
+  HIP_TRY(hipMemcpyAsync(hl64.data(), lens64.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
+  if (B.any32) HIP_TRY(hipMemcpyAsync(hl32.data(), lens32.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(xf.data(), xflags.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   int32_t sw = 64;
   for (int m = 0; m < B.n; ++m) {
     BatchInst &I = B.in[m];
     if (I.solo) continue;
+    const std::vector<int32_t> &hl = I.mixed ? hl32 : hl64;
     for (int i = 0; i < I.N; ++i) I.maxlen = std::max(I.maxlen, hl[I.r0 + i]);
-    I.zeros = (xf[m] & 4) != 0;
+    // (an exact zero in any X0 of a precision sends all its instances to run
+    // on their own: with tau >= 0 an X0 keeps none)
+    I.zeros = (xf[I.mixed ? 1 : 0] & 4) != 0;
     if (I.zeros || I.maxlen > kMaxCap) {
       I.solo = true;
       continue;
@@ -2069,23 +2102,16 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   B.SW = sw;
   HIP_TRY(B.A64.alloc(B.NT, sw));
   if (B.any32) HIP_TRY(B.A32.alloc(B.NT, sw));
+  // rows of the instances that run on their own stay empty in span form (their
+  // intervals may not fit the span width)
   for (int m = 0; m < B.n; ++m) {
     const BatchInst &I = B.in[m];
-    if (I.solo) continue;
-    if (I.mixed) {
-      EllView<float> v = X32.v(0);
-      v.nnz += I.r0;
-      v.idx += (size_t)I.r0 * cap0;
-      v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_to_span<float>(I.N, v, B.rows(B.A32, 0, I), st));
-    } else {
-      EllView<double> v = X64.v(0);
-      v.nnz += I.r0;
-      v.idx += (size_t)I.r0 * cap0;
-      v.val += (size_t)I.r0 * cap0;
-      HIP_TRY(launch_ell_to_span<double>(I.N, v, B.rows(B.A64, 0, I), st));
-    }
+    if (!I.solo) continue;
+    int32_t *nz = I.mixed ? X32.nnz[0].as<int32_t>() : X64.nnz[0].as<int32_t>();
+    HIP_TRY(hipMemsetAsync(nz + I.r0, 0, sizeof(int32_t) * I.N, st));
   }
+  HIP_TRY(launch_ell_to_span<double>(B.NT, X64.v(0), B.A64.v(0), st));
+  if (B.any32) HIP_TRY(launch_ell_to_span<float>(B.NT, X32.v(0), B.A32.v(0), st));
   HIP_TRY(hipStreamSynchronize(st));
   X64.release();
   X32.release();

@@ -139,6 +139,37 @@ hipError_t launch_decide_batch(int n, SP2State *states, const SP2Cfg *cfgs, cons
 // workgroup, rows strided over at most kInitBlocks workgroups).
 constexpr int kInitBlocks = 1024;
 inline int init_blocks(int N) { return N < 4 * kInitBlocks ? (N + 3) / 4 : kInitBlocks; }
+// One instance of a multi-instance initialisation launch (the batched solve's
+// Gershgorin bounds, symmetry checks and X0s, one launch each for all).
+struct InitInst {
+  EllView<double> H;  // its Hamiltonian
+  int32_t N;
+  int32_t w0, nw;     // its workgroups in the launch: w0 .. w0 + nw - 1
+  int32_t r0;         // its first row in the packed X0 buffers
+  int32_t f32;        // 1: its X0 is FP32
+  double emax, inv;   // X0 = (emax I - H) inv
+  double tau;         // X0's drop tolerance (rounded to its precision by the kernel)
+};
+// Gershgorin bounds of every instance (workgroups w0 = sum of gersh_blocks(N)
+// of the instances before, nw = gersh_blocks(N); ws: their w0): out[2m],
+// out[2m + 1] = emin, emax of instance m, flags[m] |= 2 if its H holds a
+// non-finite value; plo, phi: the launch's per-workgroup partials.
+hipError_t launch_gershgorin_multi(const InitInst *in, const int32_t *ws, int n, int nwork, double *plo,
+                                   double *phi, double *out, int32_t *flags, hipStream_t stream);
+// Bitwise symmetry of every instance (w0 = sum of sym_blocks(N) of the
+// instances before, nw = sym_blocks(N)): flag[4m] |= 1 and the balance at
+// flag + 4m + 2 (64 bits) as launch_check_symmetric's, all zeroed by the caller.
+inline int sym_blocks(int N) { return (N + 3) / 4; }
+hipError_t launch_check_symmetric_multi(const InitInst *in, const int32_t *ws, int n, int nwork, int32_t *flag,
+                                        hipStream_t stream);
+// X0 of every instance whose precision is T's into the packed rows X[r0 ..
+// r0 + N) (rows: the packed rows; rs: the instances' r0, ascending); rowc[r]
+// = the kept count of packed row r before the capacity cut (rows of other
+// instances untouched).
+template <typename T>
+hipError_t launch_x0_multi(const InitInst *in, const int32_t *rs, int n, int rows, EllView<T> X, int32_t *rowc,
+                           hipStream_t stream);
+
 // Workgroups of the Gershgorin kernel: one wavefront per kGershRows rows.
 constexpr int kGershRows = 16, kGershMaxBlocks = 8192;
 inline int gersh_blocks(int N) { return std::min((N + kGershRows - 1) / kGershRows, kGershMaxBlocks); }

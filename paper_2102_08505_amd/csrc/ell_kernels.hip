@@ -844,60 +844,132 @@ constexpr int kGershCols = 136;  // 26 KiB of LDS; a 129-entry band row in one p
 constexpr int kGershStride = kGershCols + 1;  // LDS row stride: the summing lanes hit distinct banks
 constexpr int kGershLoads = kGershRows * kGershCols / kWave;  // staged entries per lane and pass
 static_assert(kGershRows * kGershCols % kWave == 0, "whole loads per lane");
+// One group of rows i0 .. i0 + kGershRows - 1 (cut at N): lo / hi take the
+// min / max of H_ii - r_i and H_ii + r_i, bad whether a stored value is not
+// finite.  sv, sj: the wavefront's LDS staging.
+__device__ __forceinline__ void gersh_group(int N, const EllView<double> &H, int i0, double *sv, int32_t *sj,
+                                            double &lo, double &hi, bool &bad)
+{
+  const int lane = threadIdx.x;
+  const int rows = min(kGershRows, N - i0);
+  const int i = i0 + lane;
+  const int n = lane < rows ? H.nnz[i] : 0;
+  int nmax = n;
+  for (int o = kWave / 2; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+  double r = 0.0, hii = 0.0;
+  for (int q0 = 0; q0 < nmax; q0 += kGershCols) {
+    int jj[kGershLoads];
+    double hh[kGershLoads];
+#pragma unroll
+    for (int k = 0; k < kGershLoads; ++k) {
+      const int e = k * kWave + lane, t = e / kGershCols, q = q0 + e % kGershCols;
+      const bool in = t < rows && q < __shfl(n, t, kWave);  // a stored entry of row i0 + t
+      jj[k] = in ? H.idx[(size_t)(i0 + t) * H.M + q] : 0;
+      hh[k] = in ? H.val[(size_t)(i0 + t) * H.M + q] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kGershLoads; ++k) {
+      const int e = k * kWave + lane, t = e / kGershCols;
+      sj[t * kGershStride + e % kGershCols] = jj[k];
+      sv[t * kGershStride + e % kGershCols] = hh[k];
+    }
+    __syncthreads();
+    const int cnt = min(kGershCols, n - q0);  // <= 0 past the row's end and for lanes >= rows
+    for (int c = 0; c < cnt; ++c) {
+      const double h = sv[lane * kGershStride + c];
+      bad = bad || !isfinite(h);
+      if (sj[lane * kGershStride + c] == i) hii = h;
+      else r = r + fabs(h);
+    }
+    __syncthreads();
+  }
+  if (lane < rows) {
+    lo = fmin(lo, hii - r);
+    hi = fmax(hi, hii + r);
+  }
+}
+
+// the wavefront's min / max to out_lo / out_hi, and flags |= 2 if bad
+__device__ __forceinline__ void gersh_out(double lo, double hi, bool bad, double *out_lo, double *out_hi,
+                                          int32_t *flags)
+{
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, kWave));
+    hi = fmax(hi, __shfl_xor(hi, o, kWave));
+  }
+  if (__ballot(bad) && threadIdx.x == 0) atomicOr(flags, 2);
+  if (threadIdx.x == 0) {
+    *out_lo = lo;
+    *out_hi = hi;
+  }
+}
+
 __global__ __launch_bounds__(kWave) void k_gersh_rows(int N, EllView<double> H, double *plo, double *phi,
                                                       int32_t *flags)
 {
   __shared__ double sv[kGershRows * kGershStride];
   __shared__ int32_t sj[kGershRows * kGershStride];
-  const int lane = threadIdx.x;
   double lo = INFINITY, hi = -INFINITY;
   bool bad = false;
-  for (int i0 = blockIdx.x * kGershRows; i0 < N; i0 += gridDim.x * kGershRows) {
-    const int rows = min(kGershRows, N - i0);
-    const int i = i0 + lane;
-    const int n = lane < rows ? H.nnz[i] : 0;
-    int nmax = n;
-    for (int o = kWave / 2; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
-    double r = 0.0, hii = 0.0;
-    for (int q0 = 0; q0 < nmax; q0 += kGershCols) {
-      int jj[kGershLoads];
-      double hh[kGershLoads];
-#pragma unroll
-      for (int k = 0; k < kGershLoads; ++k) {
-        const int e = k * kWave + lane, t = e / kGershCols, q = q0 + e % kGershCols;
-        const bool in = t < rows && q < __shfl(n, t, kWave);  // a stored entry of row i0 + t
-        jj[k] = in ? H.idx[(size_t)(i0 + t) * H.M + q] : 0;
-        hh[k] = in ? H.val[(size_t)(i0 + t) * H.M + q] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kGershLoads; ++k) {
-        const int e = k * kWave + lane, t = e / kGershCols;
-        sj[t * kGershStride + e % kGershCols] = jj[k];
-        sv[t * kGershStride + e % kGershCols] = hh[k];
-      }
-      __syncthreads();
-      const int cnt = min(kGershCols, n - q0);  // <= 0 past the row's end and for lanes >= rows
-      for (int c = 0; c < cnt; ++c) {
-        const double h = sv[lane * kGershStride + c];
-        bad = bad || !isfinite(h);
-        if (sj[lane * kGershStride + c] == i) hii = h;
-        else r = r + fabs(h);
-      }
-      __syncthreads();
-    }
-    if (lane < rows) {
-      lo = fmin(lo, hii - r);
-      hi = fmax(hi, hii + r);
-    }
+  for (int i0 = blockIdx.x * kGershRows; i0 < N; i0 += gridDim.x * kGershRows) gersh_group(N, H, i0, sv, sj, lo, hi, bad);
+  gersh_out(lo, hi, bad, plo + blockIdx.x, phi + blockIdx.x, flags);
+}
+
+// Instance of a multi-instance launch whose workgroups start at w0 (the
+// instances in ascending w0; ws: their w0 in a separate array for the search).
+__device__ __forceinline__ int inst_of(const int32_t *ws, int n, int w)
+{
+  int lo = 0, hi = n - 1;  // the last instance with ws[m] <= w
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ws[mid] <= w) lo = mid;
+    else hi = mid - 1;
   }
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o, kWave));
-    hi = fmax(hi, __shfl_xor(hi, o, kWave));
+  return lo;
+}
+
+// Gershgorin over many matrices in one launch: one wavefront per group of
+// kGershRows rows of one of them (workgroup b of instance m: rows 16 (b -
+// w0[m]) .., strided by 16 nw[m] as in the single launch); the partial of
+// workgroup b goes to plo[b], phi[b].
+__global__ __launch_bounds__(kWave) void k_gersh_multi(const InitInst *in, const int32_t *ws, int n, double *plo,
+                                                       double *phi, int32_t *flags)
+{
+  __shared__ double sv[kGershRows * kGershStride];
+  __shared__ int32_t sj[kGershRows * kGershStride];
+  const int m = inst_of(ws, n, blockIdx.x);
+  const InitInst I = in[m];
+  double lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
+  for (int i0 = (blockIdx.x - I.w0) * kGershRows; i0 < I.N; i0 += I.nw * kGershRows)
+    gersh_group(I.N, I.H, i0, sv, sj, lo, hi, bad);
+  gersh_out(lo, hi, bad, plo + blockIdx.x, phi + blockIdx.x, flags + m);
+}
+
+// one workgroup per instance: min / max over its partials [w0, w0 + nw)
+__global__ __launch_bounds__(256) void k_gersh_final_multi(const InitInst *in, const double *plo, const double *phi,
+                                                           double *out)
+{
+  __shared__ double slo[256], shi[256];
+  const InitInst I = in[blockIdx.x];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int b = threadIdx.x; b < I.nw; b += 256) {
+    lo = fmin(lo, plo[I.w0 + b]);
+    hi = fmax(hi, phi[I.w0 + b]);
   }
-  if (__ballot(bad) && lane == 0) atomicOr(flags, 2);
-  if (lane == 0) {
-    plo[blockIdx.x] = lo;
-    phi[blockIdx.x] = hi;
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + o]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = slo[0];
+    out[2 * blockIdx.x + 1] = shi[0];
   }
 }
 
@@ -932,6 +1004,64 @@ __global__ __launch_bounds__(256) void k_gersh_final(int nb, const double *plo, 
 // workgroup, an atomic max reports the widest row (skipped when the maximum
 // already stored is as wide: after the first workgroups, nearly always) and,
 // when `total` is given, an atomic add the count of kept entries.
+// X0's row i of H into row ix of X (one wavefront; returns the kept count
+// before the cut at X.M, the same on every lane).  One pass in ascending
+// column order.  The diagonal H lacks, (emax - 0) inv, belongs between the
+// entries with j < i and those with j > i; at the first entry with j >= i it
+// is known whether H stores it (columns are sorted and unique), so the entries
+// with j > i are placed one further when it is inserted, and the diagonal
+// itself goes in at the end.
+template <typename T>
+__device__ __forceinline__ int x0_row(const EllView<double> &H, int i, const EllView<T> &X, int ix, double emax,
+                                      double inv, T tau)
+{
+  const int lane = lane_id();
+  const int n = uniform_i(H.nnz[i]);
+  const int32_t *ci = H.idx + (size_t)i * H.M;
+  const double *vi = H.val + (size_t)i * H.M;
+  const T xd = (T)((emax - 0.0) * inv);
+  int c = 0;       // kept entries of H so far
+  int c_lt = -1;   // kept entries with j < i (once known)
+  bool ins = false;
+  for (int q0 = 0; q0 < n; q0 += kWave) {
+    const int q = q0 + lane;
+    const bool in = q < n;
+    const int j = in ? ci[q] : INT_MAX;
+    const double h = in ? vi[q] : 0.0;
+    const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
+    const T xt = (T)x;
+    const bool keep = in && absv(xt) > tau;
+    const uint64_t m = __ballot(keep);
+    if (c_lt < 0) {
+      const uint64_t mge = __ballot(in && j >= i);
+      if (mge) {
+        const int f = __builtin_ctzll(mge);  // the first entry at or past the diagonal column
+        c_lt = c + __popcll(m & ((1ull << f) - 1ull));
+        ins = __ballot(in && j == i) == 0 && absv(xd) > tau;
+      }
+    }
+    const int pos = c + lanes_below(m) + (ins && j > i ? 1 : 0);
+    if (keep && pos < X.M) {
+      X.idx[(size_t)ix * X.M + pos] = j;
+      X.val[(size_t)ix * X.M + pos] = xt;
+    }
+    c += __popcll(m);
+  }
+  if (c_lt < 0) {  // every entry lies before the diagonal column
+    c_lt = c;
+    ins = absv(xd) > tau;
+  }
+  if (ins) {
+    if (lane == 0 && c_lt < X.M) {
+      X.idx[(size_t)ix * X.M + c_lt] = i;
+      X.val[(size_t)ix * X.M + c_lt] = xd;
+    }
+    ++c;
+  }
+  if (lane == 0) X.nnz[ix] = min(c, X.M);
+  return c;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T> X, const double *ee, double emax,
                                             double inv, T tau, int32_t *wmax, unsigned long long *total)
@@ -946,54 +1076,7 @@ __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T>
   int cmax = 0;
   unsigned long long csum = 0;
   for (int i = uniform_i(blockIdx.x * kWavesPerBlock + w); i < N; i += gridDim.x * kWavesPerBlock) {
-    const int n = uniform_i(H.nnz[i]);
-    const int32_t *ci = H.idx + (size_t)i * H.M;
-    const double *vi = H.val + (size_t)i * H.M;
-    // One pass in ascending column order.  The diagonal H lacks, (emax - 0)
-    // inv, belongs between the entries with j < i and those with j > i; at the
-    // first entry with j >= i it is known whether H stores it (columns are
-    // sorted and unique), so the entries with j > i are placed one further when
-    // it is inserted, and the diagonal itself goes in at the end.
-    const T xd = (T)((emax - 0.0) * inv);
-    int c = 0;       // kept entries of H so far
-    int c_lt = -1;   // kept entries with j < i (once known)
-    bool ins = false;
-    for (int q0 = 0; q0 < n; q0 += kWave) {
-      const int q = q0 + lane;
-      const bool in = q < n;
-      const int j = in ? ci[q] : INT_MAX;
-      const double h = in ? vi[q] : 0.0;
-      const double x = (j == i) ? (emax - h) * inv : (-h) * inv;
-      const T xt = (T)x;
-      const bool keep = in && absv(xt) > tau;
-      const uint64_t m = __ballot(keep);
-      if (c_lt < 0) {
-        const uint64_t mge = __ballot(in && j >= i);
-        if (mge) {
-          const int f = __builtin_ctzll(mge);  // the first entry at or past the diagonal column
-          c_lt = c + __popcll(m & ((1ull << f) - 1ull));
-          ins = __ballot(in && j == i) == 0 && absv(xd) > tau;
-        }
-      }
-      const int pos = c + lanes_below(m) + (ins && j > i ? 1 : 0);
-      if (keep && pos < X.M) {
-        X.idx[(size_t)i * X.M + pos] = j;
-        X.val[(size_t)i * X.M + pos] = xt;
-      }
-      c += __popcll(m);
-    }
-    if (c_lt < 0) {  // every entry lies before the diagonal column
-      c_lt = c;
-      ins = absv(xd) > tau;
-    }
-    if (ins) {
-      if (lane == 0 && c_lt < X.M) {
-        X.idx[(size_t)i * X.M + c_lt] = i;
-        X.val[(size_t)i * X.M + c_lt] = xd;
-      }
-      ++c;
-    }
-    if (lane == 0) X.nnz[i] = min(c, X.M);
+    const int c = x0_row<T>(H, i, X, i, emax, inv, tau);
     cmax = max(cmax, c);
     csum += (unsigned long long)c;
   }
@@ -1007,6 +1090,22 @@ __global__ __launch_bounds__(256) void k_x0(int N, EllView<double> H, EllView<T>
     if (m > __hip_atomic_load(wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(wmax, m);
     if (total) atomicAdd(total, ssum[0] + ssum[1] + ssum[2] + ssum[3]);
   }
+}
+
+// X0 of many matrices in one launch, one wavefront per packed row r: the
+// instance whose rows r0 .. r0 + N - 1 hold r (rows between instances and
+// instances of the other precision are left alone); rowc[r] = the kept count.
+template <typename T>
+__global__ __launch_bounds__(256) void k_x0_multi(const InitInst *in, const int32_t *rs, int n, int rows,
+                                                  EllView<T> X, int32_t *rowc)
+{
+  const int r = uniform_i(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+  if (r >= rows) return;
+  const int m = inst_of(rs, n, r);
+  const InitInst I = in[m];
+  if (r - I.r0 >= I.N || I.f32 != (sizeof(T) == 4 ? 1 : 0)) return;
+  const int c = x0_row<T>(I.H, r - I.r0, X, r, I.emax, I.inv, (T)I.tau);
+  if (lane_id() == 0) rowc[r] = c;
 }
 
 // Row copy between capacities and precisions (widening float -> double is exact).
@@ -1054,45 +1153,48 @@ __global__ __launch_bounds__(256) void k_validate(int N, EllView<T> A, int32_t *
 // are distinct entries below the diagonal (one per entry above it), so with a
 // zero balance they are all of them: H is bitwise symmetric iff the flag stays
 // clear and the balance is zero.  (Half the lookups of checking both sides.)
-__global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag,
-                                                         unsigned long long *balance)
+// row i of the check: this lane's entries of the row (lanes over its entries)
+__device__ __forceinline__ void check_row(const EllView<double> &H, int i, bool &bad, long long &bal)
+{
+  const int lane = lane_id();
+  const int n = H.nnz[i];
+  for (int s = lane; s < n; s += kWave) {
+    const int j = H.idx[(size_t)i * H.M + s];
+    if (j < i) --bal;
+    if (j <= i) continue;
+    ++bal;
+    const double v = H.val[(size_t)i * H.M + s];
+    const int32_t *cj = H.idx + (size_t)j * H.M;
+    // first the mirror slot, where (j, i) sits when rows i and j are bands of
+    // the same width (a slot below the capacity: in bounds whatever it holds)
+    const int pm = n - 1 - s;
+    const int nj = H.nnz[j];
+    if (pm < H.M && cj[pm] == i && pm < nj) {
+      bad = bad || __double_as_longlong(H.val[(size_t)j * H.M + pm]) != __double_as_longlong(v);
+      continue;
+    }
+    int lo = 0, hi = nj - 1;
+    bool found = false;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int c = cj[mid];
+      if (c == i) {
+        found = __double_as_longlong(H.val[(size_t)j * H.M + mid]) == __double_as_longlong(v);
+        break;
+      }
+      if (c < i) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    bad = bad || !found;
+  }
+}
+
+// the workgroup's results: flag |= 1 if any lane saw a missing or unequal
+// mirror, the balance gains the workgroup's sum (one atomic, when nonzero)
+__device__ __forceinline__ void check_out(bool bad, long long bal, int32_t *flag, unsigned long long *balance)
 {
   __shared__ long long sb[kWavesPerBlock];
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  bool bad = false;
-  long long bal = 0;  // this lane's entries above minus below the diagonal
-  for (int i = blockIdx.x * kWavesPerBlock + w; i < N; i += gridDim.x * kWavesPerBlock) {
-    const int n = H.nnz[i];
-    for (int s = lane; s < n; s += kWave) {
-      const int j = H.idx[(size_t)i * H.M + s];
-      if (j < i) --bal;
-      if (j <= i) continue;
-      ++bal;
-      const double v = H.val[(size_t)i * H.M + s];
-      const int32_t *cj = H.idx + (size_t)j * H.M;
-      // first the mirror slot, where (j, i) sits when rows i and j are bands of
-      // the same width (a slot below the capacity: in bounds whatever it holds)
-      const int pm = n - 1 - s;
-      const int nj = H.nnz[j];
-      if (pm < H.M && cj[pm] == i && pm < nj) {
-        bad = bad || __double_as_longlong(H.val[(size_t)j * H.M + pm]) != __double_as_longlong(v);
-        continue;
-      }
-      int lo = 0, hi = nj - 1;
-      bool found = false;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int c = cj[mid];
-        if (c == i) {
-          found = __double_as_longlong(H.val[(size_t)j * H.M + mid]) == __double_as_longlong(v);
-          break;
-        }
-        if (c < i) lo = mid + 1;
-        else hi = mid - 1;
-      }
-      bad = bad || !found;
-    }
-  }
   if (__ballot(bad) && lane == 0) atomicOr(flag, 1);
   for (int o = kWave / 2; o > 0; o >>= 1) bal += __shfl_xor(bal, o, kWave);
   if (lane == 0) sb[w] = bal;
@@ -1101,6 +1203,31 @@ __global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> 
     const long long t = (sb[0] + sb[1]) + (sb[2] + sb[3]);
     if (t != 0) atomicAdd(balance, (unsigned long long)t);  // (two's complement: a sum of signed counts)
   }
+}
+
+__global__ __launch_bounds__(256) void k_check_symmetric(int N, EllView<double> H, int32_t *flag,
+                                                         unsigned long long *balance)
+{
+  bool bad = false;
+  long long bal = 0;  // this lane's entries above minus below the diagonal
+  for (int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += gridDim.x * kWavesPerBlock)
+    check_row(H, i, bad, bal);
+  check_out(bad, bal, flag, balance);
+}
+
+// the check of many matrices in one launch: workgroup b of instance m takes
+// rows 4 (b - w0[m]) .. + 3, one per wavefront; instance m's flag word is
+// flag[4m], its balance the 64 bits at flag + 4m + 2
+__global__ __launch_bounds__(256) void k_check_symmetric_multi(const InitInst *in, const int32_t *ws, int n,
+                                                               int32_t *flag)
+{
+  const int m = inst_of(ws, n, blockIdx.x);
+  const InitInst I = in[m];
+  const int i = (blockIdx.x - I.w0) * kWavesPerBlock + (threadIdx.x >> 6);
+  bool bad = false;
+  long long bal = 0;
+  if (i < I.N) check_row(I.H, i, bad, bal);
+  check_out(bad, bal, flag + 4 * m, reinterpret_cast<unsigned long long *>(flag + 4 * m + 2));
 }
 
 // n words set to zero (a kernel rather than a memset node, so that a caller
@@ -1314,6 +1441,37 @@ hipError_t launch_check_symmetric(int N, EllView<double> H, int32_t *flag, unsig
   hipLaunchKernelGGL(k_check_symmetric, dim3(init_blocks(N)), dim3(256), 0, stream, N, H, flag, balance);
   return hipGetLastError();
 }
+
+hipError_t launch_gershgorin_multi(const InitInst *in, const int32_t *ws, int n, int nwork, double *plo,
+                                   double *phi, double *out, int32_t *flags, hipStream_t stream)
+{
+  if (n <= 0 || nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gersh_multi, dim3(nwork), dim3(kWave), 0, stream, in, ws, n, plo, phi, flags);
+  hipLaunchKernelGGL(k_gersh_final_multi, dim3(n), dim3(256), 0, stream, in, plo, phi, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_symmetric_multi(const InitInst *in, const int32_t *ws, int n, int nwork, int32_t *flag,
+                                        hipStream_t stream)
+{
+  if (n <= 0 || nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_symmetric_multi, dim3(nwork), dim3(256), 0, stream, in, ws, n, flag);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x0_multi(const InitInst *in, const int32_t *rs, int n, int rows, EllView<T> X, int32_t *rowc,
+                           hipStream_t stream)
+{
+  if (n <= 0 || rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_x0_multi<T>), dim3((rows + kWavesPerBlock - 1) / kWavesPerBlock), dim3(256), 0, stream, in,
+                     rs, n, rows, X, rowc);
+  return hipGetLastError();
+}
+template hipError_t launch_x0_multi<double>(const InitInst *, const int32_t *, int, int, EllView<double>, int32_t *,
+                                            hipStream_t);
+template hipError_t launch_x0_multi<float>(const InitInst *, const int32_t *, int, int, EllView<float>, int32_t *,
+                                           hipStream_t);
 
 hipError_t launch_zero_words(int n, int32_t *p, hipStream_t stream)
 {
