@@ -981,7 +981,7 @@ struct InitBlock {
   unsigned long long total;     // entries of X0 (the extent kernel's sums: then
   unsigned long long lensum;    //   the summed row interval lengths)
   int32_t maxlen;               // longest row interval of X0
-  int32_t xflags;               // bit 2: X0 stores an exact zero
+  int32_t xflags;               // bit 2: X0 stores an exact zero (never: it keeps |x| > tau >= 0)
 };
 
 // Per-iteration history, one block of arrays of max_iter entries each (device,
@@ -1223,11 +1223,11 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       HIP_TRY(W32.alloc(N, cap));
       HIP_TRY(launch_x0<float>(N, view<double>(H), W32.v(0), &ib->emin, (float)p->tau_fp32, &ib->wmax, nullptr,
                                st));
-      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, &ib->xflags, &ib->maxlen, &ib->total, st));
+      HIP_TRY(launch_ell_extent<float>(N, W32.v(0), nullptr, nullptr, &ib->maxlen, &ib->total, st));
     } else {
       HIP_TRY(W64.alloc(N, cap));
       HIP_TRY(launch_x0<double>(N, view<double>(H), W64.v(0), &ib->emin, p->tau, &ib->wmax, nullptr, st));
-      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, &ib->xflags, &ib->maxlen, &ib->total, st));
+      HIP_TRY(launch_ell_extent<double>(N, W64.v(0), nullptr, nullptr, &ib->maxlen, &ib->total, st));
     }
     HIP_TRY(hipMemcpyAsync(&hi, ib, sizeof(InitBlock), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -2005,13 +2005,12 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   }
   WorkSet<double> X64;
   WorkSet<float> X32;
-  DevMem xin, xrs, rowc, lens64, lens32, xflags;
+  DevMem xin, xrs, rowc, lens64, lens32;
   HIP_TRY(xin.alloc(sizeof(InitInst) * B.n));
   HIP_TRY(xrs.alloc(sizeof(int32_t) * B.n));
   HIP_TRY(rowc.alloc(sizeof(int32_t) * B.NT));
   HIP_TRY(lens64.alloc(sizeof(int32_t) * B.NT));
   if (B.any32) HIP_TRY(lens32.alloc(sizeof(int32_t) * B.NT));
-  HIP_TRY(xflags.alloc(sizeof(int32_t) * 2));
   HIP_TRY(hipMemcpyAsync(xin.p, xi.data(), sizeof(InitInst) * B.n, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(xrs.p, xr.data(), sizeof(int32_t) * B.n, hipMemcpyHostToDevice, st));
   HIP_TRY(rowc.zero(sizeof(int32_t) * B.NT));
@@ -2073,15 +2072,12 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
   }
   // ---- interval extents (one launch per precision over the packed rows);
   // instances the span form cannot hold run on their own ----
-  HIP_TRY(hipMemsetAsync(xflags.p, 0, sizeof(int32_t) * 2, st));
-  HIP_TRY(launch_ell_extent<double>(B.NT, X64.v(0), lens64.as<int32_t>(), xflags.as<int32_t>(), nullptr, nullptr, st));
-  if (B.any32)
-    HIP_TRY(launch_ell_extent<float>(B.NT, X32.v(0), lens32.as<int32_t>(), xflags.as<int32_t>() + 1, nullptr, nullptr,
-                                     st));
-  std::vector<int32_t> hl64(B.NT), hl32(B.any32 ? B.NT : 0), xf(2);
+  // (an X0 keeps |x| > tau >= 0: no exact zero, which the span form could not hold)
+  HIP_TRY(launch_ell_extent<double>(B.NT, X64.v(0), lens64.as<int32_t>(), nullptr, nullptr, nullptr, st));
+  if (B.any32) HIP_TRY(launch_ell_extent<float>(B.NT, X32.v(0), lens32.as<int32_t>(), nullptr, nullptr, nullptr, st));
+  std::vector<int32_t> hl64(B.NT), hl32(B.any32 ? B.NT : 0);
   HIP_TRY(hipMemcpyAsync(hl64.data(), lens64.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
   if (B.any32) HIP_TRY(hipMemcpyAsync(hl32.data(), lens32.p, sizeof(int32_t) * B.NT, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(xf.data(), xflags.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   int32_t sw = 64;
   for (int m = 0; m < B.n; ++m) {
@@ -2089,10 +2085,7 @@ extern "C" int sp2_solve_batched(int32_t n, const ellpack_t *const *H, ellpack_t
     if (I.solo) continue;
     const std::vector<int32_t> &hl = I.mixed ? hl32 : hl64;
     for (int i = 0; i < I.N; ++i) I.maxlen = std::max(I.maxlen, hl[I.r0 + i]);
-    // (an exact zero in any X0 of a precision sends all its instances to run
-    // on their own: with tau >= 0 an X0 keeps none)
-    I.zeros = (xf[I.mixed ? 1 : 0] & 4) != 0;
-    if (I.zeros || I.maxlen > kMaxCap) {
+    if (I.maxlen > kMaxCap) {
       I.solo = true;
       continue;
     }

@@ -502,7 +502,8 @@ __global__ __launch_bounds__(256) void k_x2_band_batch(int ngroups, SpanRot3<T> 
 // ---- conversions between ELLPACK and span form -----------------------------------------
 
 // Interval length of every row of an ELLPACK matrix, and a flag if any stored
-// value is exactly zero (the span form cannot represent it).
+// value is exactly zero (the span form cannot represent it; with flags null
+// the values are not read).
 template <typename T>
 __global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t *len, int32_t *flags,
                                                     int32_t *maxlen, unsigned long long *sums)
@@ -515,9 +516,11 @@ __global__ __launch_bounds__(256) void k_ell_extent(int N, EllView<T> A, int32_t
     n = A.nnz[i];
     if (n > 0) l = A.idx[(size_t)i * A.M + n - 1] - A.idx[(size_t)i * A.M] + 1;
     if (len) len[i] = l;
-    bool zero = false;
-    for (int q = 0; q < n; ++q) zero |= A.val[(size_t)i * A.M + q] == T(0);
-    if (zero) atomicOr(flags, 4);
+    if (flags) {  // (null: the caller knows the matrix stores no zero)
+      bool zero = false;
+      for (int q = 0; q < n; ++q) zero |= A.val[(size_t)i * A.M + q] == T(0);
+      if (zero) atomicOr(flags, 4);
+    }
   }
   if (!maxlen) return;  // the same for the whole launch
   unsigned long long sn = (unsigned long long)n, sl = (unsigned long long)l;
@@ -556,23 +559,17 @@ __global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanVi
   const T *vi = A.val + (size_t)i * A.M;
   const int b = n > 0 ? ci[0] & ~(align - 1) : 0;
   const int l = n > 0 ? ((ci[n - 1] | (align - 1)) + 1) - b : 0;
-  // each lane fills its positions by a binary search in the sorted row
-  for (int p = lane; p < l; p += kWave) {
-    const int j = b + p;
-    int lo = 0, hi = n - 1;
-    T v = T(0);
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int c = ci[mid];
-      if (c == j) {
-        v = vi[mid];
-        break;
-      }
-      if (c < j) lo = mid + 1;
-      else hi = mid - 1;
-    }
-    S.val[(size_t)i * S.SW + p] = v;
+  // each lane writes its stored entries and the zeros up to the next one
+  // (columns are sorted and unique); lane 0 also the zeros before the first
+  T *row = S.val + (size_t)i * S.SW;
+  for (int q = lane; q < n; q += kWave) {
+    const int c = ci[q] - b;
+    row[c] = vi[q];
+    const int next = q + 1 < n ? ci[q + 1] - b : l;
+    for (int p = c + 1; p < next; ++p) row[p] = T(0);
   }
+  if (lane == 0)
+    for (int p = 0; p < (n > 0 ? ci[0] - b : 0); ++p) row[p] = T(0);
   if (lane == 0) {
     S.base[i] = b;
     S.len[i] = l;
