@@ -577,8 +577,9 @@ __global__ __launch_bounds__(256) void k_ell_to_span(int N, EllView<T> A, SpanVi
 }
 
 // span form -> ELLPACK (nonzero positions, ascending), one wave per row, the
-// waves striding over the rows; the widest row goes to *wmax with one atomic
-// per workgroup.
+// waves striding over the rows; up to four 64-position chunks of a row are
+// loaded before they are compacted.  The widest row goes to *wmax with one
+// atomic per workgroup, skipped when the stored maximum is already as wide.
 template <typename TS, typename TD>
 __global__ __launch_bounds__(256) void k_span_to_ell(int N, SpanView<TS> S, EllView<TD> A, int32_t *wmax)
 {
@@ -590,19 +591,28 @@ __global__ __launch_bounds__(256) void k_span_to_ell(int N, SpanView<TS> S, EllV
   for (int i = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); i < N; i += gridDim.x * kWavesPerBlock) {
     const int b = S.base[i], l = S.len[i];
     int c = 0;
-    for (int p0 = 0; p0 < l; p0 += kWave) {
-      const int p = p0 + lane;
-      const TS v = p < l ? S.val[(size_t)i * S.SW + p] : TS(0);
-      const bool keep = v != TS(0);
-      const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int pos = c + lanes_below(m);
-        if (pos < A.M) {
-          A.idx[(size_t)i * A.M + pos] = b + p;
-          A.val[(size_t)i * A.M + pos] = (TD)v;
-        }
+    for (int p1 = 0; p1 < l; p1 += 4 * kWave) {
+      TS v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = p1 + u * kWave + lane;
+        v[u] = p < l ? S.val[(size_t)i * S.SW + p] : TS(0);
       }
-      c += __popcll(m);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p0 = p1 + u * kWave;
+        if (p0 >= l) break;  // (the same for the whole wave)
+        const bool keep = v[u] != TS(0);
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+          const int pos = c + lanes_below(m);
+          if (pos < A.M) {
+            A.idx[(size_t)i * A.M + pos] = b + p0 + lane;
+            A.val[(size_t)i * A.M + pos] = (TD)v[u];
+          }
+        }
+        c += __popcll(m);
+      }
     }
     if (lane == 0) A.nnz[i] = min(c, A.M);
     cmax = max(cmax, c);
@@ -610,7 +620,8 @@ __global__ __launch_bounds__(256) void k_span_to_ell(int N, SpanView<TS> S, EllV
   if (wmax) {
     if (lane == 0) atomicMax(&bmax, cmax);
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(wmax, bmax);
+    if (threadIdx.x == 0 && bmax > __hip_atomic_load(wmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(wmax, bmax);
   }
 }
 
