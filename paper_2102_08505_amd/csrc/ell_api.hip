@@ -1360,7 +1360,25 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
       fresh = false;
     }
     const int iter_before = hs.iter;
-    if ((rc = enqueue(1 - cur.k, nxt))) return rc;
+    // Near the end -- in the FP64 phase, the last norm squared, squared once
+    // per product (SP2 converges about quadratically), falls below the target
+    // within the batch waited for -- nothing is queued behind that batch: its
+    // launches would only return at once after the stop.  (A wrong guess costs
+    // the host's reading of the state between two batches; the results are the
+    // same either way.)
+    bool ahead = true;
+    if (!hs.phase32 && hs.iter > 0 && hs.eta2 > 0.0) {
+      double e = hs.eta2;
+      for (int j = 0; j < poll && ahead; ++j) {
+        e = e * e;
+        ahead = !(e < cfg.target2);
+      }
+    }
+    if (ahead) {
+      if ((rc = enqueue(1 - cur.k, nxt))) return rc;
+    } else {
+      nxt.m0 = nxt.m1 = S.marks.size();  // (nothing queued)
+    }
     HIP_TRY(hipEventSynchronize(S.polled[cur.k]));
     hs = slot[cur.k];
     if (S.profile) {
@@ -1371,10 +1389,11 @@ extern "C" int sp2_solve(const ellpack_t *H, ellpack_t *D, const sp2_params_t *p
         if ((int)(q - cur.m0) >= worked) S.marks[q].first = nullptr;
     }
     if (!hs.stop) {
-      cur = nxt;
+      if (ahead) cur = nxt;
+      else fresh = true;  // the guess was early: queue the next batch now
       continue;
     }
-    // the batch queued behind it saw the stop flag: let it drain
+    // the batch queued behind it (if any) saw the stop flag: let it drain
     HIP_TRY(hipStreamSynchronize(st));
     for (size_t q = nxt.m0; q < nxt.m1; ++q) S.marks[q].first = nullptr;
     fresh = true;
