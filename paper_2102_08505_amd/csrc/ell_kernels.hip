@@ -875,7 +875,25 @@ __device__ __forceinline__ void gersh_group(int N, const EllView<double> &H, int
     }
     __syncthreads();
     const int cnt = min(kGershCols, n - q0);  // <= 0 past the row's end and for lanes >= rows
-    for (int c = 0; c < cnt; ++c) {
+    // eight staged entries read before they are added in order, so that the
+    // LDS latency is paid once per eight
+    int c = 0;
+    for (; c + 8 <= cnt; c += 8) {
+      double hv[8];
+      int jv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        hv[u] = sv[lane * kGershStride + c + u];
+        jv[u] = sj[lane * kGershStride + c + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        bad = bad || !isfinite(hv[u]);
+        if (jv[u] == i) hii = hv[u];
+        else r = r + fabs(hv[u]);
+      }
+    }
+    for (; c < cnt; ++c) {
       const double h = sv[lane * kGershStride + c];
       bad = bad || !isfinite(h);
       if (sj[lane * kGershStride + c] == i) hii = h;
