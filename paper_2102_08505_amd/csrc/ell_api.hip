@@ -1632,7 +1632,6 @@ struct BatchInst {
   bool mixed = false;
   double emin = 0, emax = 0;
   int32_t maxlen = 0;
-  bool zeros = false;
   unsigned long long nnz0 = 0;
   int status = ST_RUNNING;   // set when the instance leaves the batch before the loop
   bool solo = false;         // finished by sp2_solve on its own (the batch cannot hold it)
